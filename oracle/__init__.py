@@ -1,0 +1,149 @@
+"""FP64 CPU oracle for organized-point-cloud meshing and smoothing.
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow reference that the
+GPU library is checked against.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import it; the GPU library never does, and the
+two share no code.
+
+Every function promotes its float32 input to float64 and calls the C routines
+in ``pl_oracle.c`` (each cites the passage of the paper it follows).  Array
+layouts match the GPU library: points ``[M, N, 3]``; per-triangle arrays in GID
+order ``[M-1, N-1, 2, 3]`` with GID = 2 (u (N-1) + v) + k (Sec. 4.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+__all__ = ["build", "mesh", "halfedges", "laplacian", "tri_normals",
+           "bilateral", "gather", "pipeline"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+            "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        i32, i64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        vp = ctypes.c_void_p
+        lib.oracle_mesh_triangles.argtypes = [vp, i32, i32, vp, vp]
+        lib.oracle_mesh_triangles.restype = i64
+        lib.oracle_mesh_halfedges.argtypes = [vp, i32, i32, i64, vp]
+        lib.oracle_mesh_halfedges.restype = None
+        lib.oracle_laplacian.argtypes = [vp, vp, i32, i32, i32, dbl, i32, i32]
+        lib.oracle_laplacian.restype = None
+        lib.oracle_tri_normals.argtypes = [vp, i32, i32, vp, vp, i32]
+        lib.oracle_tri_normals.restype = None
+        lib.oracle_bilateral.argtypes = [vp, vp, i32, i32, i32, dbl, dbl, i32, vp, i32]
+        lib.oracle_bilateral.restype = None
+        lib.oracle_gather.argtypes = [vp, vp, i32, i32, vp]
+        lib.oracle_gather.restype = None
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def mesh(pts):
+    """Alg. 1: returns (tri_map int32 [2(M-1)(N-1)], triangles int32 [n, 3])."""
+    p = _f64(pts)
+    M, N = p.shape[:2]
+    Q2 = 2 * (M - 1) * (N - 1)
+    tri_map = np.empty(Q2, dtype=np.int32)
+    tris = np.empty((max(Q2, 1), 3), dtype=np.int32)
+    n = _load().oracle_mesh_triangles(_ptr(p), M, N, _ptr(tri_map), _ptr(tris))
+    return tri_map, tris[:n].copy()
+
+
+def halfedges(tri_map, M: int, N: int, n_tri: int):
+    """Alg. 2: twin half-edge array int32 [3 n_tri], -1 = border."""
+    tm = np.ascontiguousarray(tri_map, dtype=np.int32)
+    he = np.empty(max(3 * n_tri, 1), dtype=np.int32)
+    _load().oracle_mesh_halfedges(_ptr(tm), M, N, n_tri, _ptr(he))
+    return he[:3 * n_tri].copy()
+
+
+def laplacian(pts, kernel: int, lam: float, iterations: int, threads: int = 1):
+    """Eqs. (1)-(2), Sec. 5.1: smoothed points float64 [M, N, 3]."""
+    p = _f64(pts)
+    M, N = p.shape[:2]
+    out = np.empty_like(p)
+    _load().oracle_laplacian(_ptr(p), _ptr(out), M, N, kernel, lam, iterations, threads)
+    return out
+
+
+def tri_normals(pts, threads: int = 1):
+    """Sec. 5.2: (normals, centroids), each float64 [M-1, N-1, 2, 3]."""
+    p = _f64(pts)
+    M, N = p.shape[:2]
+    n = np.empty((M - 1, N - 1, 2, 3), dtype=np.float64)
+    c = np.empty_like(n)
+    _load().oracle_tri_normals(_ptr(p), M, N, _ptr(n), _ptr(c), threads)
+    return n, c
+
+
+def bilateral(normals, centroids, kernel: int, sigma_length: float,
+              sigma_angle: float, iterations: int, threads: int = 1):
+    """Eqs. (3)-(6), Sec. 5.2: filtered normals float64 [M-1, N-1, 2, 3]."""
+    n = _f64(normals)
+    c = _f64(centroids)
+    Mq, Nq = n.shape[:2]
+    out = np.empty_like(n)
+    _load().oracle_bilateral(_ptr(n), _ptr(c), Mq + 1, Nq + 1, kernel,
+                             sigma_length, sigma_angle, iterations, _ptr(out), threads)
+    return out
+
+
+def gather(normals, tri_map, n_tri: int):
+    """Sec. 5.2: normals of the final mesh T, float64 [n_tri, 3]."""
+    n = _f64(normals)
+    Mq, Nq = n.shape[:2]
+    tm = np.ascontiguousarray(tri_map, dtype=np.int32)
+    out = np.full((max(n_tri, 1), 3), np.nan, dtype=np.float64)
+    _load().oracle_gather(_ptr(n), _ptr(tm), Mq + 1, Nq + 1, _ptr(out))
+    return out[:n_tri].copy()
+
+
+def pipeline(pts, kernel_lap: int, lam: float, iters_lap: int, kernel_bil: int,
+             sigma_length: float, sigma_angle: float, iters_bil: int,
+             threads: int = 1) -> dict:
+    """The whole path on one frame, in the paper's order: mesh (Alg. 1-2),
+    Laplacian, centroids and normals, bilateral, gather to T."""
+    M, N = pts.shape[:2]
+    tri_map, tris = mesh(pts)
+    he = halfedges(tri_map, M, N, len(tris))
+    smooth = laplacian(pts, kernel_lap, lam, iters_lap, threads)
+    normals, centroids = tri_normals(smooth, threads)
+    filtered = bilateral(normals, centroids, kernel_bil, sigma_length,
+                         sigma_angle, iters_bil, threads)
+    normals_T = gather(filtered, tri_map, len(tris))
+    return dict(tri_map=tri_map, triangles=tris, halfedges=he, points=smooth,
+                normals=normals, centroids=centroids, filtered=filtered,
+                normals_T=normals_T)

@@ -1,0 +1,390 @@
+/*
+ * FP64 CPU oracle for organized-point-cloud meshing and smoothing
+ * (Polylidar3D, Castagno & Atkins, arXiv 2007.12065).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU path is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header or
+ * constant with the HIP library, and the HIP library never calls it.
+ *
+ * Every floating-point step runs in double precision on double inputs (the
+ * caller promotes the float32 frame).  Loops follow the paper's definitions
+ * directly; the only parallelism is an OpenMP loop over independent outputs,
+ * so results do not depend on the thread count.
+ *
+ * Readings of points the paper leaves open are marked "Reading:" below.
+ *
+ * Grid conventions (Sec. 3, Sec. 4.2): points p[u][v], u = row in [0, M),
+ * v = column in [0, N), flat index i = u*N + v, 3 doubles per point.  Quad
+ * (u, v) with u < M-1, v < N-1 holds the corners
+ *     p1 = (u, v), p2 = (u, v+1), p3 = (u+1, v+1), p4 = (u+1, v)
+ * Reading: the paper leaves GetPointIndices undefined; this is the labelling
+ * under which the twin links of Alg. 2 (Right/Top/Left/Bottom) are true
+ * twins and the triangles wind counter-clockwise as displayed, with the cut
+ * along p1-p3.  The first triangle (k = 0) is (p3, p2, p1), the second
+ * (k = 1) is (p1, p4, p3), and the global id of t_{u,v,k} is
+ * GID = 2 (u (N-1) + v) + k.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_EXPORT __attribute__((visibility("default")))
+
+static int point_valid(const double *p)
+{
+    /* A point is valid iff none of its coordinates is NaN (Sec. 4.2). */
+    return !(isnan(p[0]) || isnan(p[1]) || isnan(p[2]));
+}
+
+static void quad_corners(int u, int v, int N, int64_t c[5])
+{
+    /* c[1..4] = flat indices of p1..p4 of quad (u, v); c[0] unused. */
+    c[0] = -1;
+    c[1] = (int64_t)u * N + v;
+    c[2] = (int64_t)u * N + v + 1;
+    c[3] = (int64_t)(u + 1) * N + v + 1;
+    c[4] = (int64_t)(u + 1) * N + v;
+}
+
+/* Vertex indices of t_{u,v,k} in Alg. 1's order. */
+static void tri_vertices(int u, int v, int k, int N, int64_t out[3])
+{
+    int64_t c[5];
+    quad_corners(u, v, N, c);
+    if (k == 0) { out[0] = c[3]; out[1] = c[2]; out[2] = c[1]; }
+    else        { out[0] = c[1]; out[1] = c[4]; out[2] = c[3]; }
+}
+
+/*
+ * Alg. 1 (Extract Triangles from OPC), Sec. 4.2.
+ * pts:       [M*N*3] doubles.
+ * tri_map:   [2(M-1)(N-1)] out; rank of each GID in T, or -1.
+ * triangles: [3 * 2(M-1)(N-1)] out; T in append order, 3 point indices each.
+ * Returns |T|.
+ */
+OR_EXPORT int64_t oracle_mesh_triangles(const double *pts, int M, int N,
+                                        int32_t *tri_map, int32_t *triangles)
+{
+    const int Mq = M - 1, Nq = N - 1;
+    int64_t n_tri = 0;
+    for (int64_t g = 0; g < 2LL * Mq * Nq; ++g) tri_map[g] = -1;
+    for (int u = 0; u < Mq; ++u) {
+        for (int v = 0; v < Nq; ++v) {
+            int64_t c[5];
+            quad_corners(u, v, N, c);
+            const int64_t first = 2LL * ((int64_t)u * Nq + v);
+            const int64_t second = first + 1;
+            const int ok1 = point_valid(pts + 3 * c[1]);
+            const int ok2 = point_valid(pts + 3 * c[2]);
+            const int ok3 = point_valid(pts + 3 * c[3]);
+            const int ok4 = point_valid(pts + 3 * c[4]);
+            if (ok1 && ok2 && ok3) {              /* first triangle {p3,p2,p1} */
+                triangles[3 * n_tri + 0] = (int32_t)c[3];
+                triangles[3 * n_tri + 1] = (int32_t)c[2];
+                triangles[3 * n_tri + 2] = (int32_t)c[1];
+                tri_map[first] = (int32_t)n_tri;
+                ++n_tri;
+            }
+            if (ok1 && ok3 && ok4) {              /* second triangle {p1,p4,p3} */
+                triangles[3 * n_tri + 0] = (int32_t)c[1];
+                triangles[3 * n_tri + 1] = (int32_t)c[4];
+                triangles[3 * n_tri + 2] = (int32_t)c[3];
+                tri_map[second] = (int32_t)n_tri;
+                ++n_tri;
+            }
+        }
+    }
+    return n_tri;
+}
+
+/* GID of t_{u,v,k}, or -1 when (u, v) lies outside the quad grid.
+ * Reading: the paper's GetNeighborsGID is undefined and says nothing about
+ * the grid border; a neighbour off the grid is treated as absent. */
+static int64_t gid_or_none(int u, int v, int k, int Mq, int Nq)
+{
+    if (u < 0 || u >= Mq || v < 0 || v >= Nq) return -1;
+    return 2LL * ((int64_t)u * Nq + v) + k;
+}
+
+static int32_t map_at(const int32_t *tri_map, int64_t gid)
+{
+    return gid < 0 ? -1 : tri_map[gid];
+}
+
+/*
+ * Alg. 2 (Extract Half-Edges from OPC), Sec. 4.2.
+ * Half-edge j of triangle t has id 3t + j and runs from vertex j to vertex
+ * (j+1) mod 3 (Sec. 4.2: the first triangle's half-edges are p3->p2, p2->p1,
+ * p1->p3).  The neighbours of quad (u, v) are
+ *   Right  = second triangle of (u, v+1)   (twin of the first's edge 0)
+ *   Top    = second triangle of (u-1, v)   (twin of the first's edge 1)
+ *   Left   = first triangle of (u, v-1)    (twin of the second's edge 0)
+ *   Bottom = first triangle of (u+1, v)    (twin of the second's edge 1)
+ * and the two triangles of a quad share their edge 2 across the cut.
+ * he: [3 n_tri] out, -1 where no twin exists (Sec. 3).
+ */
+OR_EXPORT void oracle_mesh_halfedges(const int32_t *tri_map, int M, int N,
+                                     int64_t n_tri, int32_t *he)
+{
+    const int Mq = M - 1, Nq = N - 1;
+    for (int64_t h = 0; h < 3 * n_tri; ++h) he[h] = -1;
+    for (int u = 0; u < Mq; ++u) {
+        for (int v = 0; v < Nq; ++v) {
+            const int32_t first = map_at(tri_map, gid_or_none(u, v, 0, Mq, Nq));
+            const int32_t second = map_at(tri_map, gid_or_none(u, v, 1, Mq, Nq));
+            const int64_t top_gid = gid_or_none(u - 1, v, 1, Mq, Nq);
+            const int64_t right_gid = gid_or_none(u, v + 1, 1, Mq, Nq);
+            const int64_t bottom_gid = gid_or_none(u + 1, v, 0, Mq, Nq);
+            const int64_t left_gid = gid_or_none(u, v - 1, 0, Mq, Nq);
+            if (first != -1) {
+                const int32_t top = map_at(tri_map, top_gid);
+                const int32_t right = map_at(tri_map, right_gid);
+                if (right != -1) he[3LL * first] = 3 * right;
+                if (top != -1) he[3LL * first + 1] = 3 * top + 1;
+                if (second != -1) he[3LL * first + 2] = 3 * second + 2;
+            }
+            if (second != -1) {
+                const int32_t bottom = map_at(tri_map, bottom_gid);
+                const int32_t left = map_at(tri_map, left_gid);
+                if (left != -1) he[3LL * second] = 3 * left;
+                if (bottom != -1) he[3LL * second + 1] = 3 * bottom + 1;
+                if (first != -1) he[3LL * second + 2] = 3 * first + 2;
+            }
+        }
+    }
+}
+
+/*
+ * Laplacian filter on the organized cloud: Eqs. (1)-(2) of Sec. 2.3 applied
+ * with the image-space neighbourhood of Sec. 5.1.
+ *
+ * Reading of Eq. (1): the printed "v_i . (lambda/W) sum w_j (v_i - v_j)" has
+ * a vector product that cannot be meant; the update used is
+ *     v_o = v_i - (lambda / W) sum_j w_j (v_i - v_j),   w_j = 1/||v_i - v_j||,
+ * i.e. v_i moves a fraction lambda toward the inverse-distance-weighted mean
+ * of its neighbours (lambda in [0, 1] adjusts smoothing).
+ * Neighbours of pixel (u, v): every (u+du, v+dv) with |du|, |dv| <= K/2,
+ * (du, dv) != (0, 0), that is valid.  Readings: a NaN neighbour is skipped; a
+ * neighbour at distance 0 is skipped (its weight would be infinite); a pixel
+ * with no usable neighbour keeps its value; an invalid pixel is copied.
+ * Pixels within K/2 of the image border are not filtered (Sec. 5.1).
+ * Iterations are Jacobi: each one reads only the previous iteration's values.
+ * in/out: [M*N*3]; they may not alias.
+ */
+OR_EXPORT void oracle_laplacian(const double *in, double *out, int M, int N,
+                                int K, double lambda, int iterations,
+                                int nthreads)
+{
+    const int64_t P = (int64_t)M * N;
+    const int r = K / 2;
+    double *prev = (double *)malloc(sizeof(double) * 3 * P);
+    memcpy(prev, in, sizeof(double) * 3 * P);
+    memcpy(out, in, sizeof(double) * 3 * P);
+    for (int it = 0; it < iterations; ++it) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int u = 0; u < M; ++u) {
+            for (int v = 0; v < N; ++v) {
+                const double *vi = prev + 3 * ((int64_t)u * N + v);
+                double *vo = out + 3 * ((int64_t)u * N + v);
+                vo[0] = vi[0]; vo[1] = vi[1]; vo[2] = vi[2];
+                if (!point_valid(vi)) continue;
+                if (u < r || u >= M - r || v < r || v >= N - r) continue;
+                double W = 0.0, S[3] = {0.0, 0.0, 0.0};
+                for (int du = -r; du <= r; ++du) {
+                    for (int dv = -r; dv <= r; ++dv) {
+                        if (du == 0 && dv == 0) continue;
+                        const double *vj = prev + 3 * ((int64_t)(u + du) * N + (v + dv));
+                        if (!point_valid(vj)) continue;
+                        const double dx = vi[0] - vj[0];
+                        const double dy = vi[1] - vj[1];
+                        const double dz = vi[2] - vj[2];
+                        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                        if (!(d > 0.0)) continue;
+                        const double w = 1.0 / d;
+                        W += w;
+                        S[0] += w * dx; S[1] += w * dy; S[2] += w * dz;
+                    }
+                }
+                if (W > 0.0) {
+                    vo[0] = vi[0] - lambda / W * S[0];
+                    vo[1] = vi[1] - lambda / W * S[1];
+                    vo[2] = vi[2] - lambda / W * S[2];
+                }
+            }
+        }
+        memcpy(prev, out, sizeof(double) * 3 * P);
+    }
+    free(prev);
+}
+
+/*
+ * Triangle centroids and normals over the implicit full mesh T_FC (Sec. 5.2),
+ * laid out in GID order: normals/centroids [2(M-1)(N-1)][3].
+ * For t_{u,v,k} with vertices (a, b, c) in Alg. 1's order:
+ *     centroid = (a + b + c) / 3,   normal = (b - a) x (c - a) / ||.||
+ * Any NaN vertex makes both NaN (Sec. 5.2).  Reading: the paper prints no
+ * normal formula; this orientation agrees with the counter-clockwise winding
+ * of Sec. 4.2 and points toward a camera looking down +z.  A degenerate
+ * triangle (zero cross product) gets a NaN normal.
+ */
+OR_EXPORT void oracle_tri_normals(const double *pts, int M, int N,
+                                  double *normals, double *centroids,
+                                  int nthreads)
+{
+    const int Mq = M - 1, Nq = N - 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int u = 0; u < Mq; ++u) {
+        for (int v = 0; v < Nq; ++v) {
+            for (int k = 0; k < 2; ++k) {
+                const int64_t g = 2LL * ((int64_t)u * Nq + v) + k;
+                int64_t idx[3];
+                tri_vertices(u, v, k, N, idx);
+                const double *a = pts + 3 * idx[0];
+                const double *b = pts + 3 * idx[1];
+                const double *c = pts + 3 * idx[2];
+                double *n = normals + 3 * g;
+                double *ce = centroids + 3 * g;
+                if (!point_valid(a) || !point_valid(b) || !point_valid(c)) {
+                    n[0] = n[1] = n[2] = NAN;
+                    ce[0] = ce[1] = ce[2] = NAN;
+                    continue;
+                }
+                for (int d = 0; d < 3; ++d) ce[d] = (a[d] + b[d] + c[d]) / 3.0;
+                const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+                const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+                const double x[3] = {e1[1] * e2[2] - e1[2] * e2[1],
+                                     e1[2] * e2[0] - e1[0] * e2[2],
+                                     e1[0] * e2[1] - e1[1] * e2[0]};
+                const double len = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                if (!(len > 0.0)) {
+                    n[0] = n[1] = n[2] = NAN;
+                    continue;
+                }
+                n[0] = x[0] / len; n[1] = x[1] / len; n[2] = x[2] / len;
+            }
+        }
+    }
+}
+
+static int vec_ok(const double *p)
+{
+    return !(isnan(p[0]) || isnan(p[1]) || isnan(p[2]));
+}
+
+/*
+ * Bilateral normal filter on the organized mesh: Eqs. (3)-(6) of Sec. 2.3 on
+ * the neighbourhood of Sec. 5.2.
+ *
+ * Neighbour set (Reading): the quad is the unit of work and the K x K window
+ * is over quads.  The neighbours of t_{u,v,k} are both triangles of each of
+ * the K*K - 1 other quads (u+du, v+dv), |du|, |dv| <= K/2, (du, dv) != 0, that
+ * lie on the grid and have neither a NaN centroid nor a NaN normal.  At
+ * K = 3 that is at most 16 neighbours, the count the paper gives.  The
+ * triangle itself and its partner in the same quad are not neighbours.
+ *
+ * Weights (Eqs. 4-5): w_j = exp(-||c_i - c_j||^2 / (2 sl^2))
+ *                         * exp(-||n_i - n_j||^2 / (2 sa^2)).
+ * Reading of Eq. (6): the weighted mean is renormalised to unit length, so
+ * the constant K cancels and any common positive factor of the weights does
+ * too.  The sum is therefore formed with every exponent shifted by the
+ * smallest one in the neighbourhood, which is the same value in exact
+ * arithmetic and keeps the largest term at exp(0) = 1 instead of letting all
+ * terms underflow.  A triangle with no neighbour, or whose weighted sum is
+ * the zero vector, keeps its normal.  A triangle whose own normal or
+ * centroid has a NaN is copied unchanged.  Centroids never change (vertices
+ * are not updated, Sec. 5.2); iterations are Jacobi on the normals.
+ *
+ * normals_in/normals_out/centroids: [2(M-1)(N-1)][3] in GID order.
+ */
+OR_EXPORT void oracle_bilateral(const double *normals_in, const double *centroids,
+                                int M, int N, int K, double sigma_length,
+                                double sigma_angle, int iterations,
+                                double *normals_out, int nthreads)
+{
+    const int Mq = M - 1, Nq = N - 1;
+    const int64_t T = 2LL * Mq * Nq;
+    const int r = K / 2;
+    const int max_nb = 2 * (K * K - 1);
+    double *prev = (double *)malloc(sizeof(double) * 3 * T);
+    memcpy(prev, normals_in, sizeof(double) * 3 * T);
+    memcpy(normals_out, normals_in, sizeof(double) * 3 * T);
+    const double cl = 1.0 / (2.0 * sigma_length * sigma_length);
+    const double ca = 1.0 / (2.0 * sigma_angle * sigma_angle);
+    for (int it = 0; it < iterations; ++it) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int u = 0; u < Mq; ++u) {
+            double *e = (double *)malloc(sizeof(double) * max_nb);
+            int64_t *nb = (int64_t *)malloc(sizeof(int64_t) * max_nb);
+            for (int v = 0; v < Nq; ++v) {
+                for (int k = 0; k < 2; ++k) {
+                    const int64_t i = 2LL * ((int64_t)u * Nq + v) + k;
+                    const double *ni = prev + 3 * i;
+                    const double *ci = centroids + 3 * i;
+                    double *no = normals_out + 3 * i;
+                    no[0] = ni[0]; no[1] = ni[1]; no[2] = ni[2];
+                    if (!vec_ok(ni) || !vec_ok(ci)) continue;
+                    int cnt = 0;
+                    for (int du = -r; du <= r; ++du) {
+                        for (int dv = -r; dv <= r; ++dv) {
+                            if (du == 0 && dv == 0) continue;
+                            const int uu = u + du, vv = v + dv;
+                            if (uu < 0 || uu >= Mq || vv < 0 || vv >= Nq) continue;
+                            for (int kk = 0; kk < 2; ++kk) {
+                                const int64_t j = 2LL * ((int64_t)uu * Nq + vv) + kk;
+                                const double *nj = prev + 3 * j;
+                                const double *cj = centroids + 3 * j;
+                                if (!vec_ok(nj) || !vec_ok(cj)) continue;
+                                double dc2 = 0.0, dn2 = 0.0;
+                                for (int d = 0; d < 3; ++d) {
+                                    const double a = ci[d] - cj[d];
+                                    const double b = ni[d] - nj[d];
+                                    dc2 += a * a;
+                                    dn2 += b * b;
+                                }
+                                e[cnt] = dc2 * cl + dn2 * ca;
+                                nb[cnt] = j;
+                                ++cnt;
+                            }
+                        }
+                    }
+                    if (cnt == 0) continue;
+                    double emin = e[0];
+                    for (int q = 1; q < cnt; ++q) if (e[q] < emin) emin = e[q];
+                    double s[3] = {0.0, 0.0, 0.0};
+                    for (int q = 0; q < cnt; ++q) {
+                        const double w = exp(-(e[q] - emin));
+                        const double *nj = prev + 3 * nb[q];
+                        s[0] += w * nj[0]; s[1] += w * nj[1]; s[2] += w * nj[2];
+                    }
+                    const double len = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+                    if (!(len > 0.0)) continue;
+                    no[0] = s[0] / len; no[1] = s[1] / len; no[2] = s[2] / len;
+                }
+            }
+            free(e);
+            free(nb);
+        }
+        memcpy(prev, normals_out, sizeof(double) * 3 * T);
+    }
+    free(prev);
+}
+
+/*
+ * Smoothed normals of the final mesh T (Sec. 5.2): the filter runs on T_FC
+ * and T_map picks out the triangles that exist.  normals_T[T_map[g]] =
+ * normals[g] for every g with T_map[g] != -1.
+ */
+OR_EXPORT void oracle_gather(const double *normals, const int32_t *tri_map,
+                             int M, int N, double *normals_T)
+{
+    const int64_t T = 2LL * (M - 1) * (N - 1);
+    for (int64_t g = 0; g < T; ++g) {
+        const int32_t t = tri_map[g];
+        if (t < 0) continue;
+        normals_T[3LL * t + 0] = normals[3 * g + 0];
+        normals_T[3LL * t + 1] = normals[3 * g + 1];
+        normals_T[3LL * t + 2] = normals[3 * g + 2];
+    }
+}
