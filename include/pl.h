@@ -1,0 +1,180 @@
+/*
+ * pl.h -- C ABI of the MI355X (gfx950) organized-point-cloud meshing and
+ * smoothing library (libpl.so).
+ *
+ * The operations are those of Polylidar3D (Castagno & Atkins, arXiv
+ * 2007.12065): implicit right-cut meshing of an organized point cloud
+ * (Sec. 4.2, Alg. 1 and Alg. 2), the Laplacian vertex filter (Sec. 2.3
+ * Eqs. 1-2, applied as in Sec. 5.1), triangle centroids and normals, and the
+ * bilateral triangle-normal filter (Sec. 2.3 Eqs. 3-6, applied as in
+ * Sec. 5.2) with the gather of filtered normals onto the final mesh.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Every array argument is a DEVICE pointer allocated and owned by
+ *           the caller; the library never keeps a pointer after a call
+ *           returns and allocates no device memory.  Temporary storage is a
+ *           caller-provided workspace whose size the matching *_workspace()
+ *           function returns (0 means none is needed; ws may then be NULL).
+ * Streams.  Every call only enqueues kernels on `stream` (NULL = the null
+ *           stream) and returns without synchronising; results are ready when
+ *           the stream reaches that point.  Scalars produced on the device
+ *           (the triangle count) are written to device memory.
+ * Points.   float32, row-major [M][N][3] (x, y, z), flat index i = u*N + v
+ *           for row u and column v.  A point is invalid iff any coordinate is
+ *           NaN (Sec. 4.2); infinities are outside the contract.
+ * Triangles of the implicit full mesh T_FC (Sec. 4.2).  Quad (u, v),
+ *           0 <= u < M-1, 0 <= v < N-1, has corners p1 = (u, v),
+ *           p2 = (u, v+1), p3 = (u+1, v+1), p4 = (u+1, v).  Its first
+ *           triangle (k = 0) is (p3, p2, p1), its second (k = 1) is
+ *           (p1, p4, p3); GID = 2 (u (N-1) + v) + k.  Per-triangle arrays
+ *           ("T_FC layout") are [M-1][N-1][2][3] in GID order.
+ * Alignment. Every array pointer and the workspace must be 16-byte aligned
+ *           (device allocations are); PL_ERR_ARG otherwise.
+ * Errors.   Arguments are checked before anything is launched; on error
+ *           nothing is enqueued and pl_last_error() describes the problem.
+ *           PL_ERR_HIP means a launch failed after earlier launches of the
+ *           same call may already have been enqueued.
+ * Threads.  All entry points are re-entrant.  The error message is
+ *           thread-local.
+ */
+#ifndef PL_H
+#define PL_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PL_OK = 0,
+    PL_ERR_ARG = -1,       /* NULL required pointer, lambda outside [0, 1],
+                              sigma <= 0 or not finite, iterations < 0,
+                              cap < 0, unknown dtype                        */
+    PL_ERR_SHAPE = -2,     /* M < 2 or N < 2, or 6 (M-1)(N-1) >= 2^31       */
+    PL_ERR_KERNEL = -3,    /* kernel size even, < 3 or > 9                  */
+    PL_ERR_ALIAS = -4,     /* an output overlaps an input (Jacobi semantics) */
+    PL_ERR_WORKSPACE = -5, /* ws NULL or ws_bytes below the required size   */
+    PL_ERR_HIP = -6        /* a HIP launch failed                           */
+} pl_status;
+
+/* Storage type of triangle normals.  Arithmetic is float32 either way. */
+typedef enum { PL_F32 = 0, PL_F16 = 1 } pl_dtype;
+
+/* Version of this ABI (major * 100 + minor). */
+int32_t pl_version(void);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *pl_last_error(void);
+
+/*
+ * Mesh extraction, Sec. 4.2: Alg. 1 (Extract Triangles from OPC) and Alg. 2
+ * (Extract Half-Edges from OPC).
+ *
+ * pts        [M][N][3] float32 points, NaN = invalid.
+ * tri_valid  optional (may be NULL): uint8 [2(M-1)(N-1)] in GID order,
+ *            1 iff all three vertices of that T_FC triangle are valid.
+ * tri_map    int32 [2(M-1)(N-1)]: T_map of Alg. 1, the index of each GID in
+ *            T, or -1 if that triangle is not in T.
+ * triangles  int32 [cap][3]: T, the valid triangles in increasing GID order,
+ *            each as three flat point indices in the order above.
+ * halfedges  optional (may be NULL): int32 [3 cap]: HE of Alg. 2; entry
+ *            3t + j is the twin of half-edge j of triangle t (j runs from
+ *            vertex j to vertex (j+1) mod 3), or -1 on a border.
+ * cap        capacity of triangles/halfedges in triangles; 2(M-1)(N-1)
+ *            always suffices.  Only triangles with index < cap are written;
+ *            *n_tri still receives the full count, so *n_tri > cap reports
+ *            truncation (twin indices may then refer to triangles >= cap).
+ * n_tri      int32 device scalar: |T|.
+ * Workspace: pl_mesh_opc_workspace(M, N) bytes.
+ * Outputs are bit-exact and deterministic (an ordered compaction, no
+ * atomics).
+ */
+size_t pl_mesh_opc_workspace(int32_t M, int32_t N);
+pl_status pl_mesh_opc(const float *pts, int32_t M, int32_t N,
+                      uint8_t *tri_valid, int32_t *tri_map, int32_t *triangles,
+                      int32_t *halfedges, int32_t cap, int32_t *n_tri,
+                      void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Laplacian vertex filter, Sec. 2.3 Eqs. (1)-(2) on the image-space
+ * neighbourhood of Sec. 5.1, `iterations` Jacobi sweeps:
+ *     v_o = v_i + lambda * sum_j w_j (v_j - v_i) / sum_j w_j,
+ *     w_j = 1 / ||v_j - v_i||,
+ * over the valid pixels j != i of the kernel x kernel window around i.
+ * Neighbours at distance 0 are skipped; a pixel with no usable neighbour
+ * keeps its value.  Invalid pixels and pixels within kernel/2 of the image
+ * border are copied unchanged (bitwise).
+ *
+ * pts_in/pts_out  [M][N][3] float32; must not overlap.
+ * kernel          odd window size, 3..9.
+ * lambda          in [0, 1].
+ * iterations      >= 0; 0 copies pts_in to pts_out.
+ * Workspace: pl_laplacian_workspace(M, N, iterations) bytes.
+ */
+size_t pl_laplacian_workspace(int32_t M, int32_t N, int32_t iterations);
+
+/* Sweeps the library fuses into one kernel launch for this window size
+ * (ceil(iterations / this) launches per pl_laplacian call); 0 if the kernel
+ * size is invalid.  Informational: results do not depend on it. */
+int32_t pl_laplacian_fused_sweeps(int32_t kernel);
+
+pl_status pl_laplacian(const float *pts_in, float *pts_out, int32_t M, int32_t N,
+                       int32_t kernel, float lambda, int32_t iterations,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Triangle centroids and normals over T_FC, Sec. 5.2.  For each triangle
+ * with vertices (a, b, c) in the order above:
+ *     centroid = (a + b + c) / 3,   normal = (b - a) x (c - a) / ||.||.
+ * Both are NaN if any vertex is invalid; the normal is NaN if the cross
+ * product is zero.
+ *
+ * pts        [M][N][3] float32.
+ * normals    T_FC layout, float32 [..][3] (ndt = PL_F32) or float16 [..][3]
+ *            (ndt = PL_F16, rounded to nearest from the float32 result).
+ * centroids  T_FC layout float32 [..][3].
+ */
+pl_status pl_tri_normals(const float *pts, int32_t M, int32_t N,
+                         void *normals, pl_dtype ndt, float *centroids,
+                         hipStream_t stream);
+
+/*
+ * Bilateral normal filter, Sec. 2.3 Eqs. (3)-(6) on the organized mesh of
+ * Sec. 5.2, `iterations` Jacobi sweeps over the normals (centroids fixed):
+ *     n_o = normalize( sum_j exp(-||c_i - c_j||^2 / (2 sigma_length^2)
+ *                               -||n_i - n_j||^2 / (2 sigma_angle^2)) n_j ).
+ * Neighbours of t_{u,v,k}: both triangles of every other quad (u+du, v+dv),
+ * |du|, |dv| <= kernel/2, (du, dv) != (0, 0), on the grid, whose normal and
+ * centroid are free of NaN (16 at kernel 3).  The result is renormalised to
+ * unit length (the constant of Eq. 6 cancels); a triangle without
+ * neighbours, or whose weighted sum vanishes, keeps its normal; a triangle
+ * whose own normal or centroid holds a NaN is copied unchanged.
+ *
+ * normals_in   T_FC layout, storage type ndt.
+ * centroids    T_FC layout float32.
+ * normals_out  T_FC layout, storage type ndt; must not overlap the inputs.
+ * tri_map      optional (NULL = no gather): T_map from pl_mesh_opc.
+ * normals_T    required iff tri_map is given: [2(M-1)(N-1)][3] of type ndt;
+ *              row T_map[g] receives the filtered normal of GID g for every
+ *              g with T_map[g] >= 0 (Sec. 5.2); rows >= |T| are untouched.
+ * kernel       odd window size in quads, 3..9.
+ * sigma_length, sigma_angle  finite and > 0.
+ * iterations   >= 0; 0 copies normals_in to normals_out (and gathers).
+ * Workspace: pl_bilateral_workspace(M, N, ndt, iterations) bytes.
+ */
+size_t pl_bilateral_workspace(int32_t M, int32_t N, pl_dtype ndt, int32_t iterations);
+pl_status pl_bilateral(const void *normals_in, const float *centroids, pl_dtype ndt,
+                       int32_t M, int32_t N, int32_t kernel,
+                       float sigma_length, float sigma_angle, int32_t iterations,
+                       void *normals_out, const int32_t *tri_map, void *normals_T,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PL_H */

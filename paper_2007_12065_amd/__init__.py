@@ -1,0 +1,270 @@
+"""Python binding of libpl.so, the gfx950 HIP library for organized-point-cloud
+meshing and smoothing (Polylidar3D, arXiv 2007.12065, Sec. 4.2 and Sec. 5).
+
+The functions carry the C ABI's names (include/pl.h) and only marshal
+arguments: they check tensor placement, allocate outputs and workspaces with
+PyTorch on the tensors' device, and pass raw device pointers and the current
+HIP stream.  Every step runs in the library's kernels; there is no CPU path.
+Importing this module fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpl.so")
+
+PL_F32, PL_F16 = 0, 1
+_STATUS = {0: "PL_OK", -1: "PL_ERR_ARG", -2: "PL_ERR_SHAPE", -3: "PL_ERR_KERNEL",
+           -4: "PL_ERR_ALIAS", -5: "PL_ERR_WORKSPACE", -6: "PL_ERR_HIP"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: the HIP library must be built first "
+        "(python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i32, _f32, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
+_lib.pl_version.restype = _i32
+_lib.pl_last_error.restype = ctypes.c_char_p
+_lib.pl_mesh_opc_workspace.argtypes = [_i32, _i32]
+_lib.pl_mesh_opc_workspace.restype = _sz
+_lib.pl_mesh_opc.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.pl_mesh_opc.restype = _i32
+_lib.pl_laplacian_workspace.argtypes = [_i32, _i32, _i32]
+_lib.pl_laplacian_workspace.restype = _sz
+_lib.pl_laplacian_fused_sweeps.argtypes = [_i32]
+_lib.pl_laplacian_fused_sweeps.restype = _i32
+_lib.pl_laplacian.argtypes = [_vp, _vp, _i32, _i32, _i32, _f32, _i32, _vp, _sz, _vp]
+_lib.pl_laplacian.restype = _i32
+_lib.pl_tri_normals.argtypes = [_vp, _i32, _i32, _vp, _i32, _vp, _vp]
+_lib.pl_tri_normals.restype = _i32
+_lib.pl_bilateral_workspace.argtypes = [_i32, _i32, _i32, _i32]
+_lib.pl_bilateral_workspace.restype = _sz
+_lib.pl_bilateral.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _f32, _f32, _i32,
+                              _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.pl_bilateral.restype = _i32
+
+EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc",
+           "pl_laplacian_workspace", "pl_laplacian_fused_sweeps", "pl_laplacian", "pl_tri_normals",
+           "pl_bilateral_workspace", "pl_bilateral"]
+
+
+class PLError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.pl_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise PLError(status, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_tensor(t: torch.Tensor, dtype, name: str) -> None:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ws(nbytes: int, device) -> torch.Tensor | None:
+    return torch.empty(nbytes, dtype=torch.uint8, device=device) if nbytes else None
+
+
+def _ndt(dtype) -> int:
+    if dtype in (torch.float32, "f32", PL_F32):
+        return PL_F32
+    if dtype in (torch.float16, "f16", PL_F16):
+        return PL_F16
+    raise ValueError(f"normal storage must be float32 or float16, got {dtype}")
+
+
+def _tdtype(ndt: int):
+    return torch.float32 if ndt == PL_F32 else torch.float16
+
+
+def pl_version() -> int:
+    return int(_lib.pl_version())
+
+
+def lap_fused_sweeps(kernel: int) -> int:
+    """Laplacian sweeps fused per kernel launch for this window size."""
+    return int(_lib.pl_laplacian_fused_sweeps(kernel))
+
+
+def pl_mesh_opc(pts: torch.Tensor, *, tri_valid: bool = True, halfedges: bool = True,
+                cap: int | None = None) -> dict:
+    """Alg. 1 and Alg. 2 on a [M, N, 3] float32 device tensor.  Returns a dict
+    of device tensors: tri_valid (uint8 [2Q] or None), tri_map (int32 [2Q]),
+    triangles (int32 [cap, 3]), halfedges (int32 [3 cap] or None) and n_tri
+    (int32 [1]); only the first n_tri rows of triangles/halfedges are set."""
+    _dev_tensor(pts, torch.float32, "pts")
+    if pts.dim() != 3 or pts.shape[2] != 3:
+        raise ValueError("pts must be [M, N, 3]")
+    M, N = int(pts.shape[0]), int(pts.shape[1])
+    dev = pts.device
+    T = 2 * max(M - 1, 0) * max(N - 1, 0)
+    cap = T if cap is None else int(cap)
+    out = dict(
+        tri_valid=torch.empty(T, dtype=torch.uint8, device=dev) if tri_valid else None,
+        tri_map=torch.empty(T, dtype=torch.int32, device=dev),
+        triangles=torch.empty((max(cap, 1), 3), dtype=torch.int32, device=dev),
+        halfedges=torch.empty(3 * max(cap, 1), dtype=torch.int32, device=dev) if halfedges else None,
+        n_tri=torch.empty(1, dtype=torch.int32, device=dev),
+    )
+    ws_n = _lib.pl_mesh_opc_workspace(M, N)
+    ws = _ws(ws_n, dev)
+    _check(_lib.pl_mesh_opc(_ptr(pts), M, N, _ptr(out["tri_valid"]), _ptr(out["tri_map"]),
+                            _ptr(out["triangles"]), _ptr(out["halfedges"]), cap,
+                            _ptr(out["n_tri"]), _ptr(ws), ws_n, _stream(dev)), "pl_mesh_opc")
+    return out
+
+
+def pl_laplacian(pts: torch.Tensor, kernel: int, lam: float, iterations: int,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Eqs. (1)-(2), Sec. 5.1: `iterations` Jacobi sweeps; returns [M, N, 3]."""
+    _dev_tensor(pts, torch.float32, "pts")
+    M, N = int(pts.shape[0]), int(pts.shape[1])
+    out = torch.empty_like(pts) if out is None else out
+    _dev_tensor(out, torch.float32, "out")
+    ws_n = _lib.pl_laplacian_workspace(M, N, iterations)
+    ws = _ws(ws_n, pts.device)
+    _check(_lib.pl_laplacian(_ptr(pts), _ptr(out), M, N, kernel, lam, iterations,
+                             _ptr(ws), ws_n, _stream(pts.device)), "pl_laplacian")
+    return out
+
+
+def pl_tri_normals(pts: torch.Tensor, dtype=torch.float32):
+    """Sec. 5.2: (normals, centroids) in T_FC layout [M-1, N-1, 2, 3]; normals
+    stored as `dtype` (float32 or float16), centroids float32."""
+    _dev_tensor(pts, torch.float32, "pts")
+    M, N = int(pts.shape[0]), int(pts.shape[1])
+    ndt = _ndt(dtype)
+    shape = (max(M - 1, 1), max(N - 1, 1), 2, 3)
+    normals = torch.empty(shape, dtype=_tdtype(ndt), device=pts.device)
+    centroids = torch.empty(shape, dtype=torch.float32, device=pts.device)
+    _check(_lib.pl_tri_normals(_ptr(pts), M, N, _ptr(normals), ndt, _ptr(centroids),
+                               _stream(pts.device)), "pl_tri_normals")
+    return normals, centroids
+
+
+def pl_bilateral(normals: torch.Tensor, centroids: torch.Tensor, kernel: int,
+                 sigma_length: float, sigma_angle: float, iterations: int,
+                 tri_map: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                 normals_T: torch.Tensor | None = None):
+    """Eqs. (3)-(6), Sec. 5.2.  Returns (filtered normals in T_FC layout,
+    normals gathered onto T [2Q, 3] or None); the storage type follows
+    `normals` (float32 or float16)."""
+    ndt = _ndt(normals.dtype)
+    _dev_tensor(normals, _tdtype(ndt), "normals")
+    _dev_tensor(centroids, torch.float32, "centroids")
+    if normals.dim() != 4 or tuple(normals.shape[2:]) != (2, 3):
+        raise ValueError("normals must be [M-1, N-1, 2, 3]")
+    M, N = int(normals.shape[0]) + 1, int(normals.shape[1]) + 1
+    dev = normals.device
+    out = torch.empty_like(normals) if out is None else out
+    if tri_map is not None:
+        _dev_tensor(tri_map, torch.int32, "tri_map")
+        if normals_T is None:
+            normals_T = torch.empty((2 * (M - 1) * (N - 1), 3), dtype=normals.dtype, device=dev)
+    ws_n = _lib.pl_bilateral_workspace(M, N, ndt, iterations)
+    ws = _ws(ws_n, dev)
+    _check(_lib.pl_bilateral(_ptr(normals), _ptr(centroids), ndt, M, N, kernel,
+                             sigma_length, sigma_angle, iterations, _ptr(out), _ptr(tri_map),
+                             _ptr(normals_T) if tri_map is not None else None,
+                             _ptr(ws), ws_n, _stream(dev)), "pl_bilateral")
+    return out, (normals_T if tri_map is not None else None)
+
+
+def smooth_frame(pts: torch.Tensor, kernel_lap: int, lam: float, iters_lap: int,
+                 kernel_bil: int, sigma_length: float, sigma_angle: float, iters_bil: int,
+                 normal_dtype=torch.float32) -> dict:
+    """The whole path on one frame in the paper's order: mesh (Alg. 1-2),
+    Laplacian, centroids and normals, bilateral, gather onto T.  All outputs
+    stay on the device; nothing synchronises."""
+    mesh = pl_mesh_opc(pts)
+    smooth = pl_laplacian(pts, kernel_lap, lam, iters_lap)
+    normals, centroids = pl_tri_normals(smooth, normal_dtype)
+    filtered, normals_T = pl_bilateral(normals, centroids, kernel_bil, sigma_length,
+                                       sigma_angle, iters_bil, tri_map=mesh["tri_map"])
+    return dict(mesh, points=smooth, normals=normals, centroids=centroids,
+                filtered=filtered, normals_T=normals_T)
+
+
+class FramePlan:
+    """Device buffers for one frame shape, allocated once, and the four ABI
+    calls of the whole path on them.  run() only enqueues work on the current
+    stream (mesh, Laplacian, normals, bilateral with the gather onto T) and
+    allocates nothing."""
+
+    def __init__(self, M: int, N: int, kernel_lap: int, lam: float, iters_lap: int,
+                 kernel_bil: int, sigma_length: float, sigma_angle: float, iters_bil: int,
+                 normal_dtype=torch.float32, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.M, self.N, self.device = M, N, dev
+        self.kernel_lap, self.lam, self.iters_lap = kernel_lap, lam, iters_lap
+        self.kernel_bil, self.sigma_length, self.sigma_angle = kernel_bil, sigma_length, sigma_angle
+        self.iters_bil = iters_bil
+        self.ndt = _ndt(normal_dtype)
+        T = 2 * (M - 1) * (N - 1)
+        nd = _tdtype(self.ndt)
+        e = lambda shape, dt: torch.empty(shape, dtype=dt, device=dev)
+        self.points = e((M, N, 3), torch.float32)
+        self.tri_valid = e(T, torch.uint8)
+        self.tri_map = e(T, torch.int32)
+        self.triangles = e((T, 3), torch.int32)
+        self.halfedges = e(3 * T, torch.int32)
+        self.n_tri = e(1, torch.int32)
+        self.normals = e((M - 1, N - 1, 2, 3), nd)
+        self.centroids = e((M - 1, N - 1, 2, 3), torch.float32)
+        self.filtered = e((M - 1, N - 1, 2, 3), nd)
+        self.normals_T = e((T, 3), nd)
+        self._ws_mesh_n = _lib.pl_mesh_opc_workspace(M, N)
+        self._ws_lap_n = _lib.pl_laplacian_workspace(M, N, iters_lap)
+        self._ws_bil_n = _lib.pl_bilateral_workspace(M, N, self.ndt, iters_bil)
+        self.ws_mesh = _ws(self._ws_mesh_n, dev)
+        self.ws_lap = _ws(self._ws_lap_n, dev)
+        self.ws_bil = _ws(self._ws_bil_n, dev)
+        self.T = T
+
+    def run_mesh(self, pts, s):
+        _check(_lib.pl_mesh_opc(_ptr(pts), self.M, self.N, _ptr(self.tri_valid), _ptr(self.tri_map),
+                                _ptr(self.triangles), _ptr(self.halfedges), self.T, _ptr(self.n_tri),
+                                _ptr(self.ws_mesh), self._ws_mesh_n, s), "pl_mesh_opc")
+
+    def run_laplacian(self, pts, s):
+        _check(_lib.pl_laplacian(_ptr(pts), _ptr(self.points), self.M, self.N, self.kernel_lap,
+                                 self.lam, self.iters_lap, _ptr(self.ws_lap), self._ws_lap_n, s),
+               "pl_laplacian")
+
+    def run_normals(self, s):
+        _check(_lib.pl_tri_normals(_ptr(self.points), self.M, self.N, _ptr(self.normals), self.ndt,
+                                   _ptr(self.centroids), s), "pl_tri_normals")
+
+    def run_bilateral(self, s):
+        _check(_lib.pl_bilateral(_ptr(self.normals), _ptr(self.centroids), self.ndt, self.M, self.N,
+                                 self.kernel_bil, self.sigma_length, self.sigma_angle, self.iters_bil,
+                                 _ptr(self.filtered), _ptr(self.tri_map), _ptr(self.normals_T),
+                                 _ptr(self.ws_bil), self._ws_bil_n, s), "pl_bilateral")
+
+    def run(self, pts: torch.Tensor) -> None:
+        s = _stream(self.device)
+        self.run_mesh(pts, s)
+        self.run_laplacian(pts, s)
+        self.run_normals(s)
+        self.run_bilateral(s)

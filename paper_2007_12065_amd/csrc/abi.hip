@@ -1,0 +1,260 @@
+// extern "C" entry points of libpl.so: argument validation, then dispatch to
+// the kernel launchers.  Nothing is enqueued when validation fails.
+#include "common.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+namespace pl {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+pl_status hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return PL_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return PL_ERR_HIP;
+}
+
+namespace {
+
+struct Range {
+    const void *p;
+    size_t bytes;
+};
+
+bool overlap(Range a, Range b) {
+    if (!a.p || !b.p || !a.bytes || !b.bytes) return false;
+    const uintptr_t a0 = (uintptr_t)a.p, b0 = (uintptr_t)b.p;
+    return a0 < b0 + b.bytes && b0 < a0 + a.bytes;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+pl_status check_shape(int32_t M, int32_t N) {
+    if (M < 2 || N < 2) {
+        set_error("shape %d x %d: need M >= 2 and N >= 2", M, N);
+        return PL_ERR_SHAPE;
+    }
+    if (6.0 * (double)(M - 1) * (double)(N - 1) >= 2147483648.0) {
+        set_error("shape %d x %d: 6 (M-1)(N-1) must stay below 2^31", M, N);
+        return PL_ERR_SHAPE;
+    }
+    return PL_OK;
+}
+
+pl_status check_kernel(int32_t k) {
+    if (k < 3 || k > 9 || (k % 2) == 0) {
+        set_error("kernel size %d: must be odd and in [3, 9]", k);
+        return PL_ERR_KERNEL;
+    }
+    return PL_OK;
+}
+
+pl_status check_ptrs(std::initializer_list<std::pair<const void *, const char *>> ps) {
+    for (auto &p : ps) {
+        if (!p.first) {
+            set_error("%s is NULL", p.second);
+            return PL_ERR_ARG;
+        }
+        if (!aligned16(p.first)) {
+            set_error("%s is not 16-byte aligned", p.second);
+            return PL_ERR_ARG;
+        }
+    }
+    return PL_OK;
+}
+
+pl_status check_ws(const void *ws, size_t have, size_t need) {
+    if (need == 0) return PL_OK;
+    if (!ws || have < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? have : (size_t)0);
+        return PL_ERR_WORKSPACE;
+    }
+    if (!aligned16(ws)) {
+        set_error("workspace is not 16-byte aligned");
+        return PL_ERR_ARG;
+    }
+    return PL_OK;
+}
+
+}  // namespace
+}  // namespace pl
+
+using namespace pl;
+
+#define PL_TRY(x)                          \
+    do {                                   \
+        if (pl_status _s = (x)) return _s; \
+    } while (0)
+
+extern "C" {
+
+__attribute__((visibility("default"))) int32_t pl_version(void) { return 100; }
+
+__attribute__((visibility("default"))) const char *pl_last_error(void) { return g_err; }
+
+__attribute__((visibility("default"))) size_t pl_mesh_opc_workspace(int32_t M, int32_t N) {
+    if (M < 2 || N < 2) return 0;
+    return mesh_workspace(M, N);
+}
+
+__attribute__((visibility("default"))) pl_status pl_mesh_opc(
+    const float *pts, int32_t M, int32_t N, uint8_t *tri_valid, int32_t *tri_map,
+    int32_t *triangles, int32_t *halfedges, int32_t cap, int32_t *n_tri, void *ws,
+    size_t ws_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    PL_TRY(check_shape(M, N));
+    if (cap < 0) {
+        set_error("cap %d < 0", cap);
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ptrs({{pts, "pts"}, {tri_map, "tri_map"}, {n_tri, "n_tri"}}));
+    if (cap > 0) PL_TRY(check_ptrs({{triangles, "triangles"}}));
+    if (halfedges && cap > 0) PL_TRY(check_ptrs({{halfedges, "halfedges"}}));
+    if (tri_valid) PL_TRY(check_ptrs({{tri_valid, "tri_valid"}}));
+    PL_TRY(check_ws(ws, ws_bytes, mesh_workspace(M, N)));
+    const size_t T = 2 * (size_t)(M - 1) * (N - 1);
+    const Range in{pts, sizeof(float) * 3 * (size_t)M * N};
+    const Range outs[] = {{tri_valid, tri_valid ? T : 0},
+                          {tri_map, 4 * T},
+                          {triangles, 12 * (size_t)cap},
+                          {halfedges, halfedges ? 12 * (size_t)cap : 0},
+                          {n_tri, 4},
+                          {ws, mesh_workspace(M, N)}};
+    for (size_t i = 0; i < sizeof(outs) / sizeof(outs[0]); ++i) {
+        if (overlap(in, outs[i])) {
+            set_error("output %zu overlaps pts", i);
+            return PL_ERR_ALIAS;
+        }
+        for (size_t j = i + 1; j < sizeof(outs) / sizeof(outs[0]); ++j)
+            if (overlap(outs[i], outs[j])) {
+                set_error("outputs %zu and %zu overlap", i, j);
+                return PL_ERR_ALIAS;
+            }
+    }
+    return launch_mesh(pts, M, N, tri_valid, tri_map, triangles, cap > 0 ? halfedges : nullptr,
+                       cap, n_tri, ws, stream);
+}
+
+__attribute__((visibility("default"))) size_t pl_laplacian_workspace(int32_t M, int32_t N,
+                                                                     int32_t iterations) {
+    if (M < 2 || N < 2 || iterations < 0) return 0;
+    return laplacian_workspace(M, N, iterations);
+}
+
+__attribute__((visibility("default"))) int32_t pl_laplacian_fused_sweeps(int32_t kernel) {
+    if (kernel < 3 || kernel > 9 || (kernel % 2) == 0) return 0;
+    return laplacian_fused_sweeps(kernel);
+}
+
+__attribute__((visibility("default"))) pl_status pl_laplacian(
+    const float *pts_in, float *pts_out, int32_t M, int32_t N, int32_t kernel, float lambda,
+    int32_t iterations, void *ws, size_t ws_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    PL_TRY(check_shape(M, N));
+    PL_TRY(check_kernel(kernel));
+    if (!(lambda >= 0.f && lambda <= 1.f)) {
+        set_error("lambda %g outside [0, 1]", (double)lambda);
+        return PL_ERR_ARG;
+    }
+    if (iterations < 0) {
+        set_error("iterations %d < 0", iterations);
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ptrs({{pts_in, "pts_in"}, {pts_out, "pts_out"}}));
+    const size_t need = laplacian_workspace(M, N, iterations);
+    PL_TRY(check_ws(ws, ws_bytes, need));
+    const size_t bytes = sizeof(float) * 3 * (size_t)M * N;
+    if (overlap({pts_in, bytes}, {pts_out, bytes}) || overlap({pts_in, bytes}, {ws, need}) ||
+        overlap({pts_out, bytes}, {ws, need})) {
+        set_error("pts_in, pts_out and the workspace must not overlap");
+        return PL_ERR_ALIAS;
+    }
+    return launch_laplacian(pts_in, pts_out, M, N, kernel, lambda, iterations, ws, stream);
+}
+
+__attribute__((visibility("default"))) pl_status pl_tri_normals(const float *pts, int32_t M,
+                                                                int32_t N, void *normals,
+                                                                pl_dtype ndt, float *centroids,
+                                                                hipStream_t stream) {
+    g_err[0] = 0;
+    PL_TRY(check_shape(M, N));
+    if (ndt != PL_F32 && ndt != PL_F16) {
+        set_error("unknown normal dtype %d", (int)ndt);
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ptrs({{pts, "pts"}, {normals, "normals"}, {centroids, "centroids"}}));
+    const size_t T = 2 * (size_t)(M - 1) * (N - 1);
+    const Range in{pts, sizeof(float) * 3 * (size_t)M * N};
+    const Range nr{normals, T * 3 * (ndt == PL_F32 ? 4 : 2)};
+    const Range cr{centroids, T * 12};
+    if (overlap(in, nr) || overlap(in, cr) || overlap(nr, cr)) {
+        set_error("pts, normals and centroids must not overlap");
+        return PL_ERR_ALIAS;
+    }
+    return launch_tri_normals(pts, M, N, normals, ndt, centroids, stream);
+}
+
+__attribute__((visibility("default"))) size_t pl_bilateral_workspace(int32_t M, int32_t N,
+                                                                     pl_dtype ndt,
+                                                                     int32_t iterations) {
+    if (M < 2 || N < 2 || iterations < 0 || (ndt != PL_F32 && ndt != PL_F16)) return 0;
+    return bilateral_workspace(M, N, ndt, iterations);
+}
+
+__attribute__((visibility("default"))) pl_status pl_bilateral(
+    const void *normals_in, const float *centroids, pl_dtype ndt, int32_t M, int32_t N,
+    int32_t kernel, float sigma_length, float sigma_angle, int32_t iterations,
+    void *normals_out, const int32_t *tri_map, void *normals_T, void *ws, size_t ws_bytes,
+    hipStream_t stream) {
+    g_err[0] = 0;
+    PL_TRY(check_shape(M, N));
+    PL_TRY(check_kernel(kernel));
+    if (ndt != PL_F32 && ndt != PL_F16) {
+        set_error("unknown normal dtype %d", (int)ndt);
+        return PL_ERR_ARG;
+    }
+    if (!(sigma_length > 0.f) || !isfinite(sigma_length) || !(sigma_angle > 0.f) ||
+        !isfinite(sigma_angle)) {
+        set_error("sigmas must be finite and > 0 (got %g, %g)", (double)sigma_length,
+                  (double)sigma_angle);
+        return PL_ERR_ARG;
+    }
+    if (iterations < 0) {
+        set_error("iterations %d < 0", iterations);
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ptrs({{normals_in, "normals_in"}, {centroids, "centroids"},
+                       {normals_out, "normals_out"}}));
+    if (tri_map) PL_TRY(check_ptrs({{tri_map, "tri_map"}, {normals_T, "normals_T"}}));
+    const size_t need = bilateral_workspace(M, N, ndt, iterations);
+    PL_TRY(check_ws(ws, ws_bytes, need));
+    const size_t T = 2 * (size_t)(M - 1) * (N - 1);
+    const size_t nb = T * 3 * (ndt == PL_F32 ? 4 : 2);
+    const Range ins[] = {{normals_in, nb}, {centroids, T * 12}, {tri_map, tri_map ? T * 4 : 0}};
+    const Range outs[] = {{normals_out, nb}, {normals_T, tri_map ? nb : 0}, {ws, need}};
+    for (const Range &o : outs) {
+        for (const Range &i : ins)
+            if (overlap(i, o)) {
+                set_error("an output of pl_bilateral overlaps an input");
+                return PL_ERR_ALIAS;
+            }
+    }
+    if (overlap(outs[0], outs[1]) || overlap(outs[0], outs[2]) || overlap(outs[1], outs[2])) {
+        set_error("normals_out, normals_T and the workspace must not overlap");
+        return PL_ERR_ALIAS;
+    }
+    return launch_bilateral(normals_in, centroids, ndt, M, N, kernel, sigma_length,
+                            sigma_angle, iterations, normals_out, tri_map, normals_T, ws,
+                            stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal helpers shared by the gfx950 kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/pl.h"
+
+namespace pl {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kNumXcd = 8;       // MI355X: 8 accelerator complex dies, 32 CUs each
+
+// NaN test on the bit pattern: exponent all ones, mantissa non-zero.  Immune
+// to any fast-math or finite-math compiler flag.
+__device__ __forceinline__ bool is_nan_bits(float x) {
+    return (__float_as_uint(x) & 0x7fffffffu) > 0x7f800000u;
+}
+
+__device__ __forceinline__ float qnan() { return __uint_as_float(0x7fc00000u); }
+
+// Workgroups are dispatched round-robin over the XCDs (workgroup b runs on
+// XCD b mod 8), and each XCD has its own L2.  Remap the dispatch index so
+// each XCD receives a contiguous range of tiles: neighbouring tiles, which
+// share halo data, then hit the same L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int xcd = b % kNumXcd;
+    const int idx = b / kNumXcd;
+    const int q = n / kNumXcd;
+    const int rem = n % kNumXcd;
+    const int start = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+    return start + idx;
+}
+
+// Inclusive prefix sum across one 64-wide wavefront.
+__device__ __forceinline__ int wave_inclusive_scan(int x) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+// Half storage helpers (normals in PL_F16 mode).
+__device__ __forceinline__ float ld_f(const float *p) { return *p; }
+__device__ __forceinline__ float ld_f(const __half *p) { return __half2float(*p); }
+__device__ __forceinline__ void st_f(float *p, float v) { *p = v; }
+__device__ __forceinline__ void st_f(__half *p, float v) { *p = __float2half_rn(v); }
+
+// ---- host side -----------------------------------------------------------
+
+void set_error(const char *fmt, ...);
+pl_status hip_check(hipError_t e, const char *what);
+
+// Launchers implemented next to their kernels.  Arguments are validated by
+// the ABI layer before these run.
+pl_status launch_mesh(const float *pts, int M, int N, uint8_t *tri_valid,
+                      int32_t *tri_map, int32_t *triangles, int32_t *halfedges,
+                      int32_t cap, int32_t *n_tri, void *ws, hipStream_t s);
+size_t mesh_workspace(int M, int N);
+
+pl_status launch_laplacian(const float *in, float *out, int M, int N, int kernel,
+                           float lambda, int iterations, void *ws, hipStream_t s);
+size_t laplacian_workspace(int M, int N, int iterations);
+int laplacian_fused_sweeps(int kernel);
+
+pl_status launch_tri_normals(const float *pts, int M, int N, void *normals,
+                             pl_dtype ndt, float *centroids, hipStream_t s);
+
+pl_status launch_bilateral(const void *nin, const float *cen, pl_dtype ndt, int M,
+                           int N, int kernel, float sigma_length, float sigma_angle,
+                           int iterations, void *nout, const int32_t *tri_map,
+                           void *normals_T, void *ws, hipStream_t s);
+size_t bilateral_workspace(int M, int N, pl_dtype ndt, int iterations);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace pl

@@ -1,0 +1,99 @@
+"""The C ABI without a GPU: the library loads, exports every entry point its
+header declares, and rejects bad arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pl.h")
+
+
+@pytest.fixture(scope="module")
+def pl():
+    import paper_2007_12065_amd as pl
+    return pl
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pl_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(pl):
+    names = header_functions()
+    assert "pl_mesh_opc" in names and "pl_bilateral" in names
+    lib = ctypes.CDLL(pl.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(pl.EXPORTS)
+
+
+def test_version(pl):
+    assert pl.pl_version() == 100
+
+
+def test_workspace_sizes(pl):
+    lib = pl._lib
+    M, N = 480, 640
+    assert lib.pl_mesh_opc_workspace(M, N) >= (M - 1) * (N - 1) + 4 * (2 * M - 1)
+    assert lib.pl_laplacian_workspace(M, N, 1) == 0
+    assert lib.pl_laplacian_workspace(M, N, 4) == 12 * M * N
+    assert lib.pl_bilateral_workspace(M, N, 0, 1) == 0
+    assert lib.pl_bilateral_workspace(M, N, 0, 2) == 2 * (M - 1) * (N - 1) * 12
+    assert lib.pl_bilateral_workspace(M, N, 1, 2) == 2 * (M - 1) * (N - 1) * 6
+    assert lib.pl_mesh_opc_workspace(1, 5) == 0
+
+
+A, B, C = 0x100000, 0x200000, 0x300000     # fake aligned addresses, never dereferenced
+
+
+def err(pl):
+    return pl._lib.pl_last_error().decode()
+
+
+def test_laplacian_argument_errors(pl):
+    lib = pl._lib
+    assert lib.pl_laplacian(A, B, 1, 5, 3, 1.0, 1, None, 0, None) == -2
+    assert lib.pl_laplacian(A, B, 10, 10, 4, 1.0, 1, None, 0, None) == -3
+    assert lib.pl_laplacian(A, B, 10, 10, 11, 1.0, 1, None, 0, None) == -3
+    assert lib.pl_laplacian(A, B, 10, 10, 3, 1.5, 1, None, 0, None) == -1
+    assert lib.pl_laplacian(A, B, 10, 10, 3, float("nan"), 1, None, 0, None) == -1
+    assert lib.pl_laplacian(A, B, 10, 10, 3, 1.0, -1, None, 0, None) == -1
+    assert lib.pl_laplacian(None, B, 10, 10, 3, 1.0, 1, None, 0, None) == -1
+    assert "pts_in" in err(pl)
+    assert lib.pl_laplacian(A + 4, B, 10, 10, 3, 1.0, 1, None, 0, None) == -1
+    assert "aligned" in err(pl)
+    assert lib.pl_laplacian(A, A + 16, 10, 10, 3, 1.0, 1, None, 0, None) == -4
+    assert lib.pl_laplacian(A, B, 10, 10, 3, 1.0, 3, None, 0, None) == -5
+    assert lib.pl_laplacian(A, B, 10, 10, 3, 1.0, 3, C, 100, None) == -5
+
+
+def test_mesh_argument_errors(pl):
+    lib = pl._lib
+    ws = lib.pl_mesh_opc_workspace(10, 10)
+    assert lib.pl_mesh_opc(A, 10, 1, None, B, C, None, 10, C + 4096, C + 8192, ws, None) == -2
+    assert lib.pl_mesh_opc(A, 40000, 40000, None, B, C, None, 10, C + 4096, C + 8192, ws, None) == -2
+    assert lib.pl_mesh_opc(A, 10, 10, None, B, C, None, -1, C + 4096, C + 8192, ws, None) == -1
+    assert lib.pl_mesh_opc(A, 10, 10, None, None, C, None, 10, C + 4096, C + 8192, ws, None) == -1
+    assert lib.pl_mesh_opc(A, 10, 10, None, B, C, None, 10, C + 4096, None, 0, None) == -5
+    # tri_map overlapping the points
+    assert lib.pl_mesh_opc(A, 10, 10, None, A + 256, C, None, 10, C + 4096, C + 8192, ws, None) == -4
+
+
+def test_normals_and_bilateral_argument_errors(pl):
+    lib = pl._lib
+    assert lib.pl_tri_normals(A, 10, 10, B, 7, C, None) == -1
+    assert lib.pl_tri_normals(A, 10, 10, A, 0, C, None) == -4
+    def bil(nin=A, cen=B, ndt=0, M=10, N=10, K=3, sl=0.1, sa=0.1, it=1, nout=C,
+            tm=None, nT=None, ws=None, wsb=0):
+        return lib.pl_bilateral(nin, cen, ndt, M, N, K, sl, sa, it, nout, tm, nT, ws, wsb, None)
+    assert bil(K=2) == -3
+    assert bil(sl=0.0) == -1
+    assert bil(sa=float("inf")) == -1
+    assert bil(ndt=3) == -1
+    assert bil(tm=C + 65536) == -1            # gather without a destination
+    assert bil(nout=A) == -4
+    assert bil(it=2) == -5
