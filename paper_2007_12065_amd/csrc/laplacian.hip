@@ -21,8 +21,17 @@ namespace pl {
 
 namespace {
 
-constexpr int TH = 16;
-constexpr int TW = 64;
+#ifndef PL_LAP_TH
+#define PL_LAP_TH 16
+#endif
+#ifndef PL_LAP_TW
+#define PL_LAP_TW 64
+#endif
+#ifndef PL_LAP_FUSE
+#define PL_LAP_FUSE 4          // sweeps fused per launch for the 3x3 window
+#endif
+constexpr int TH = PL_LAP_TH;
+constexpr int TW = PL_LAP_TW;
 constexpr int kBlock = 256;
 
 struct LapGeom {
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_f32(const float *__restrict__ a
 
 // Sweeps fused per launch: more sweeps cut HBM traffic but grow the halo
 // (LDS and redundant edge work).
-int max_fused(int R) { return R == 1 ? 4 : (R == 2 ? 2 : 1); }
+int max_fused(int R) { return R == 1 ? PL_LAP_FUSE : (R == 2 ? (PL_LAP_FUSE + 1) / 2 : 1); }
 
 template <int R>
 pl_status run(const float *in, float *out, int M, int N, float lam, int iterations,

@@ -1,15 +1,17 @@
 // Organized-point-cloud mesh extraction (Sec. 4.2, Alg. 1 and Alg. 2) as an
 // ordered compaction over quad rows.
 //
-//   k_mesh_count : one workgroup per quad row.  Tests the four corners of
-//                  each quad for NaN, stores a 2-bit code per quad (bit 0:
-//                  first triangle valid, bit 1: second) and the row's count.
-//   k_mesh_scan  : one workgroup; exclusive scan of the row counts -> the
-//                  index in T of each row's first triangle, and |T|.
-//   k_mesh_emit  : one workgroup per quad row.  Re-scans the codes of rows
-//                  u-1, u, u+1 (bytes, L2-resident) so every triangle knows
-//                  its own index and its four cross-quad neighbours' indices,
-//                  then writes T_map, T and HE in one pass.
+//   k_mesh_count : one workgroup per quad row.  Tests the points of rows u
+//                  and u+1 for NaN (all loads of a 1024-column chunk in
+//                  flight at once, validity staged in LDS), stores a 2-bit
+//                  code per quad (bit 0: first triangle valid, bit 1:
+//                  second) and the row's triangle count.
+//   k_mesh_emit  : one workgroup per quad row.  Sums the counts of the rows
+//                  above it (a few hundred to a few thousand integers, L2
+//                  hits) to place its rows in T, re-scans the codes of rows
+//                  u-1, u, u+1 (bytes) so every triangle knows its own index
+//                  and its four cross-quad neighbours' indices, then writes
+//                  T_map, T and HE in one pass; the last row writes |T|.
 //
 // Triangle indices come from prefix sums in GID order, so T is in exactly
 // the append order of Alg. 1 and every output is bit-exact and
@@ -27,29 +29,57 @@ __device__ __forceinline__ bool point_valid(const float *p) {
     return !(is_nan_bits(p[0]) || is_nan_bits(p[1]) || is_nan_bits(p[2]));
 }
 
+constexpr int kChunk = 4 * kBlock;     // columns per pass of k_mesh_count
+
 __global__ __launch_bounds__(kBlock) void k_mesh_count(
     const float *__restrict__ pts, int N, uint8_t *__restrict__ codes,
     uint8_t *__restrict__ tri_valid, int *__restrict__ row_count) {
+    __shared__ uint8_t ok[2][kChunk + 1];
     __shared__ int red[kWaves];
     const int u = blockIdx.x;
     const int Nq = N - 1;
     const float *r0 = pts + (size_t)u * N * 3;
     const float *r1 = r0 + (size_t)N * 3;
     int cnt = 0;
-    for (int v = threadIdx.x; v < Nq; v += kBlock) {
-        const bool p1 = point_valid(r0 + 3 * v);
-        const bool p2 = point_valid(r0 + 3 * (v + 1));
-        const bool p3 = point_valid(r1 + 3 * (v + 1));
-        const bool p4 = point_valid(r1 + 3 * v);
-        const int f = p1 & p2 & p3;          // first triangle (p3, p2, p1)
-        const int s = p1 & p3 & p4;          // second triangle (p1, p4, p3)
-        const size_t q = (size_t)u * Nq + v;
-        codes[q] = (uint8_t)(f | (s << 1));
-        if (tri_valid) {
-            tri_valid[2 * q] = (uint8_t)f;
-            tri_valid[2 * q + 1] = (uint8_t)s;
+    for (int v0 = 0; v0 < Nq; v0 += kChunk) {
+        // validity of points v0 .. v0 + kChunk of both rows, all loads issued
+        // before any is used
+        float x[2][5], y[2][5], z[2][5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int v = v0 + threadIdx.x + j * kBlock;
+            const bool in = (j < 4 || threadIdx.x == 0) && v < N && v <= v0 + kChunk;
+            x[0][j] = in ? r0[3 * v] : 0.f; y[0][j] = in ? r0[3 * v + 1] : 0.f; z[0][j] = in ? r0[3 * v + 2] : 0.f;
+            x[1][j] = in ? r1[3 * v] : 0.f; y[1][j] = in ? r1[3 * v + 1] : 0.f; z[1][j] = in ? r1[3 * v + 2] : 0.f;
         }
-        cnt += f + s;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int l = threadIdx.x + j * kBlock;
+            if (j < 4 || threadIdx.x == 0) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+                    ok[r][l] = !(is_nan_bits(x[r][j]) || is_nan_bits(y[r][j]) || is_nan_bits(z[r][j]));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int l = threadIdx.x + j * kBlock;
+            const int v = v0 + l;
+            if (v < Nq) {
+                const int p1 = ok[0][l], p2 = ok[0][l + 1], p3 = ok[1][l + 1], p4 = ok[1][l];
+                const int f = p1 & p2 & p3;          // first triangle (p3, p2, p1)
+                const int s = p1 & p3 & p4;          // second triangle (p1, p4, p3)
+                const size_t q = (size_t)u * Nq + v;
+                codes[q] = (uint8_t)(f | (s << 1));
+                if (tri_valid) {
+                    tri_valid[2 * q] = (uint8_t)f;
+                    tri_valid[2 * q + 1] = (uint8_t)s;
+                }
+                cnt += f + s;
+            }
+        }
+        __syncthreads();
     }
     cnt = wave_sum(cnt);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = cnt;
@@ -59,41 +89,6 @@ __global__ __launch_bounds__(kBlock) void k_mesh_count(
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) t += red[w];
         row_count[u] = t;
-    }
-}
-
-constexpr int kScanBlock = 1024;
-
-__global__ __launch_bounds__(kScanBlock) void k_mesh_scan(
-    const int *__restrict__ row_count, int Mq, int *__restrict__ row_off,
-    int32_t *__restrict__ n_tri) {
-    __shared__ int wsum[kScanBlock / kWave];
-    __shared__ int carry_s;
-    if (threadIdx.x == 0) carry_s = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    for (int base = 0; base < Mq; base += kScanBlock) {
-        const int i = base + threadIdx.x;
-        const int x = i < Mq ? row_count[i] : 0;
-        const int incl = wave_inclusive_scan(x);
-        if (lane == kWave - 1) wsum[wid] = incl;
-        __syncthreads();
-        if (wid == 0) {
-            const int w = lane < kScanBlock / kWave ? wsum[lane] : 0;
-            const int wi = wave_inclusive_scan(w);
-            if (lane < kScanBlock / kWave) wsum[lane] = wi - w;   // exclusive
-        }
-        __syncthreads();
-        const int carry = carry_s;
-        if (i < Mq) row_off[i] = carry + wsum[wid] + incl - x;
-        __syncthreads();
-        if (threadIdx.x == kScanBlock - 1) carry_s = carry + wsum[wid] + incl;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        row_off[Mq] = carry_s;
-        *n_tri = carry_s;
     }
 }
 
@@ -122,17 +117,28 @@ __device__ __forceinline__ int block_exclusive_scan(int x, int *total) {
 __device__ __forceinline__ int popc2(int c) { return (c & 1) + ((c >> 1) & 1); }
 
 __global__ __launch_bounds__(kBlock) void k_mesh_emit(
-    const uint8_t *__restrict__ codes, const int *__restrict__ row_off, int Mq, int N,
+    const uint8_t *__restrict__ codes, const int *__restrict__ row_count, int Mq, int N,
     int32_t *__restrict__ tri_map, int32_t *__restrict__ tris,
-    int32_t *__restrict__ he, int cap) {
+    int32_t *__restrict__ he, int cap, int32_t *__restrict__ n_tri) {
+    __shared__ int red[kWaves];
     const int u = blockIdx.x;
     const int Nq = N - 1;
     const uint8_t *cr0 = codes + (size_t)u * Nq;
     const uint8_t *crm = u > 0 ? cr0 - Nq : cr0;        // row u-1
     const uint8_t *crp = u + 1 < Mq ? cr0 + Nq : cr0;   // row u+1
-    const int base0 = row_off[u];
-    const int basem = u > 0 ? row_off[u - 1] : 0;
-    const int basep = u + 1 < Mq ? row_off[u + 1] : 0;
+    // index in T of the first triangle of rows u-1, u, u+1
+    int above = 0;
+    for (int r = threadIdx.x; r < u - 1; r += kBlock) above += row_count[r];
+    above = wave_sum(above);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = above;
+    __syncthreads();
+    int basem = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) basem += red[w];
+    const int cm_row = u > 0 ? row_count[u - 1] : 0;
+    const int base0 = basem + cm_row;
+    const int basep = base0 + row_count[u];
+    if (u == Mq - 1 && threadIdx.x == 0) *n_tri = basep;
     int carry0 = 0, carrym = 0, carryp = 0;
     for (int v0 = 0; v0 < Nq; v0 += kBlock) {
         const int v = v0 + threadIdx.x;
@@ -188,7 +194,6 @@ __global__ __launch_bounds__(kBlock) void k_mesh_emit(
 struct MeshWs {
     uint8_t *codes;
     int *row_count;
-    int *row_off;
 };
 
 MeshWs carve(void *ws, int M, int N) {
@@ -196,10 +201,7 @@ MeshWs carve(void *ws, int M, int N) {
     uint8_t *b = static_cast<uint8_t *>(ws);
     MeshWs w;
     w.codes = b;
-    size_t off = align_up(Q, 256);
-    w.row_count = reinterpret_cast<int *>(b + off);
-    off += align_up(sizeof(int) * (M - 1), 256);
-    w.row_off = reinterpret_cast<int *>(b + off);
+    w.row_count = reinterpret_cast<int *>(b + align_up(Q, 256));
     return w;
 }
 
@@ -207,8 +209,7 @@ MeshWs carve(void *ws, int M, int N) {
 
 size_t mesh_workspace(int M, int N) {
     const size_t Q = (size_t)(M - 1) * (N - 1);
-    return align_up(Q, 256) + align_up(sizeof(int) * (M - 1), 256) +
-           align_up(sizeof(int) * M, 256);
+    return align_up(Q, 256) + align_up(sizeof(int) * (M - 1), 256);
 }
 
 pl_status launch_mesh(const float *pts, int M, int N, uint8_t *tri_valid,
@@ -218,10 +219,8 @@ pl_status launch_mesh(const float *pts, int M, int N, uint8_t *tri_valid,
     MeshWs w = carve(ws, M, N);
     k_mesh_count<<<Mq, kBlock, 0, s>>>(pts, N, w.codes, tri_valid, w.row_count);
     if (pl_status st = hip_check(hipGetLastError(), "k_mesh_count")) return st;
-    k_mesh_scan<<<1, kScanBlock, 0, s>>>(w.row_count, Mq, w.row_off, n_tri);
-    if (pl_status st = hip_check(hipGetLastError(), "k_mesh_scan")) return st;
-    k_mesh_emit<<<Mq, kBlock, 0, s>>>(w.codes, w.row_off, Mq, N, tri_map, triangles,
-                                      halfedges, cap);
+    k_mesh_emit<<<Mq, kBlock, 0, s>>>(w.codes, w.row_count, Mq, N, tri_map, triangles,
+                                      halfedges, cap, n_tri);
     return hip_check(hipGetLastError(), "k_mesh_emit");
 }
 

@@ -38,7 +38,7 @@ def test_version(pl):
 def test_workspace_sizes(pl):
     lib = pl._lib
     M, N = 480, 640
-    assert lib.pl_mesh_opc_workspace(M, N) >= (M - 1) * (N - 1) + 4 * (2 * M - 1)
+    assert lib.pl_mesh_opc_workspace(M, N) >= (M - 1) * (N - 1) + 4 * (M - 1)
     assert lib.pl_laplacian_workspace(M, N, 1) == 0
     assert lib.pl_laplacian_workspace(M, N, 4) == 12 * M * N
     assert lib.pl_bilateral_workspace(M, N, 0, 1) == 0

@@ -358,8 +358,13 @@ def test_deterministic(pl):
                         k.sigma_length, k.sigma_angle, k.iters_bil)
     b = pl.smooth_frame(x, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
                         k.sigma_length, k.sigma_angle, k.iters_bil)
+    n = int(host(a["n_tri"])[0])
+    valid_rows = {"triangles": n, "halfedges": 3 * n, "normals_T": n}
     for key in ("tri_map", "triangles", "halfedges", "points", "filtered", "normals_T"):
-        assert np.array_equal(host(a[key]).view(np.uint8), host(b[key]).view(np.uint8)), key
+        x, y = host(a[key]), host(b[key])
+        if key in valid_rows:          # rows past |T| are never written
+            x, y = x[:valid_rows[key]], y[:valid_rows[key]]
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), key
 
 
 def test_errors_on_device(pl):
