@@ -173,6 +173,86 @@ pl_status pl_bilateral(const void *normals_in, const float *centroids, pl_dtype 
                        void *normals_out, const int32_t *tri_map, void *normals_T,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Tile shapes and sweep fusion ("tuning").  Every stage runs its kernel
+ * over tiles of tile_rows x tile_cols (points for the Laplacian, quads for
+ * the bilateral) and fuses up to `fuse` sweeps per launch.  float32 results
+ * do not depend on these values (the arithmetic of every output is the same
+ * whatever the tiling), and float16 results do not depend on `fuse`.  The
+ * table is process-wide; pl_tune_set is meant for a tuner run before work
+ * is enqueued (it does not affect launches already enqueued).
+ * kernel      odd window size, 3..9.
+ * tile_rows * tile_cols <= 16384; the LDS the shape needs must fit 160 KB.
+ * Returns PL_ERR_KERNEL / PL_ERR_ARG for an invalid request.
+ */
+typedef enum { PL_STAGE_LAPLACIAN = 0, PL_STAGE_BILATERAL = 1 } pl_stage;
+pl_status pl_tune_get(pl_stage stage, int32_t kernel, int32_t *tile_rows, int32_t *tile_cols,
+                      int32_t *fuse);
+pl_status pl_tune_set(pl_stage stage, int32_t kernel, int32_t tile_rows, int32_t tile_cols,
+                      int32_t fuse);
+
+/*
+ * Batched path: a set of frames of any sizes and filter settings through the
+ * whole pipeline (mesh, Laplacian, normals, bilateral, gather) with one
+ * persistent launch per stage over a tile work-queue.  Each frame's outputs
+ * are exactly those of the single-frame calls with the same parameters:
+ *   pl_mesh_opc(pts, M, N, tri_valid, tri_map, triangles, halfedges,
+ *               cap = 2(M-1)(N-1), n_tri)
+ *   pl_laplacian(pts -> pts_out, kernel_lap, lambda, iters_lap)
+ *   pl_tri_normals(pts_out -> normals before filtering, centroids)
+ *   pl_bilateral(-> normals, kernel_bil, sigma_length, sigma_angle,
+ *                iters_bil, tri_map -> normals_T)
+ * All pointers are device pointers owned by the caller, 16-byte aligned,
+ * with the sizes of the single-frame calls (triangles [2(M-1)(N-1)][3],
+ * halfedges [6(M-1)(N-1)], normals / normals_T in the batch's dtype);
+ * tri_valid and halfedges may be NULL.  No output may overlap any input or
+ * any other output of the batch.
+ *
+ * pl_batch_workspace  bytes of workspace the batch needs (0 if the frame
+ *                     list is invalid); depends on the tuning table.
+ * pl_batch_create     validates the frames, builds the plan in `ws` (which
+ *                     must stay allocated and untouched until
+ *                     pl_batch_destroy) and uploads its tables; synchronises
+ *                     `stream` once.  The frames' buffers are bound to the
+ *                     plan: later runs read and write the same addresses.
+ * pl_batch_run        enqueues one pass of the whole pipeline on `stream`;
+ *                     device-only work, no allocation, no synchronisation,
+ *                     legal under stream capture.
+ * pl_batch_capture    records pl_batch_run into a HIP graph owned by the
+ *                     plan (replacing any previous one); pl_batch_replay
+ *                     launches that graph on `stream`.
+ * pl_batch_destroy    releases the host-side plan (and its graph).
+ * Runs of one plan must not overlap in time (they share the queue counters
+ * and scratch in `ws`).
+ */
+typedef struct {
+    const float *pts;          /* [M][N][3] input points                     */
+    int32_t M, N;
+    int32_t kernel_lap, iters_lap;
+    float lambda;
+    int32_t kernel_bil, iters_bil;
+    float sigma_length, sigma_angle;
+    float *pts_out;            /* [M][N][3] smoothed points                  */
+    void *normals;             /* T_FC layout, filtered normals              */
+    float *centroids;          /* T_FC layout                                */
+    uint8_t *tri_valid;        /* optional [2(M-1)(N-1)]                     */
+    int32_t *tri_map;          /* [2(M-1)(N-1)]                              */
+    int32_t *triangles;        /* [2(M-1)(N-1)][3]                           */
+    int32_t *halfedges;        /* optional [6(M-1)(N-1)]                     */
+    int32_t *n_tri;            /* device scalar                              */
+    void *normals_T;           /* [2(M-1)(N-1)][3]                           */
+} pl_frame;
+
+typedef struct pl_batch_s *pl_batch;
+
+size_t pl_batch_workspace(const pl_frame *frames, int32_t n, pl_dtype ndt);
+pl_status pl_batch_create(const pl_frame *frames, int32_t n, pl_dtype ndt, void *ws,
+                          size_t ws_bytes, hipStream_t stream, pl_batch *out);
+pl_status pl_batch_run(pl_batch batch, hipStream_t stream);
+pl_status pl_batch_capture(pl_batch batch, hipStream_t stream);
+pl_status pl_batch_replay(pl_batch batch, hipStream_t stream);
+void pl_batch_destroy(pl_batch batch);
+
 #ifdef __cplusplus
 }
 #endif

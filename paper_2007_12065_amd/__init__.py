@@ -48,9 +48,42 @@ _lib.pl_bilateral.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _f32, _f32, _i32
                               _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.pl_bilateral.restype = _i32
 
+class PLFrame(ctypes.Structure):
+    """Mirror of the C struct pl_frame (include/pl.h)."""
+    _fields_ = [("pts", _vp), ("M", _i32), ("N", _i32), ("kernel_lap", _i32),
+                ("iters_lap", _i32), ("lambda_", _f32), ("kernel_bil", _i32),
+                ("iters_bil", _i32), ("sigma_length", _f32), ("sigma_angle", _f32),
+                ("pts_out", _vp), ("normals", _vp), ("centroids", _vp), ("tri_valid", _vp),
+                ("tri_map", _vp), ("triangles", _vp), ("halfedges", _vp), ("n_tri", _vp),
+                ("normals_T", _vp)]
+
+
+_lib.pl_tune_get.argtypes = [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                             ctypes.POINTER(_i32)]
+_lib.pl_tune_get.restype = _i32
+_lib.pl_tune_set.argtypes = [_i32, _i32, _i32, _i32, _i32]
+_lib.pl_tune_set.restype = _i32
+_lib.pl_batch_workspace.argtypes = [ctypes.POINTER(PLFrame), _i32, _i32]
+_lib.pl_batch_workspace.restype = _sz
+_lib.pl_batch_create.argtypes = [ctypes.POINTER(PLFrame), _i32, _i32, _vp, _sz, _vp,
+                                 ctypes.POINTER(_vp)]
+_lib.pl_batch_create.restype = _i32
+_lib.pl_batch_run.argtypes = [_vp, _vp]
+_lib.pl_batch_run.restype = _i32
+_lib.pl_batch_capture.argtypes = [_vp, _vp]
+_lib.pl_batch_capture.restype = _i32
+_lib.pl_batch_replay.argtypes = [_vp, _vp]
+_lib.pl_batch_replay.restype = _i32
+_lib.pl_batch_destroy.argtypes = [_vp]
+_lib.pl_batch_destroy.restype = None
+
+PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL = 0, 1
+
 EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc",
            "pl_laplacian_workspace", "pl_laplacian_fused_sweeps", "pl_laplacian", "pl_tri_normals",
-           "pl_bilateral_workspace", "pl_bilateral"]
+           "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
+           "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
+           "pl_batch_replay", "pl_batch_destroy"]
 
 
 class PLError(RuntimeError):
@@ -268,3 +301,102 @@ class FramePlan:
         self.run_laplacian(pts, s)
         self.run_normals(s)
         self.run_bilateral(s)
+
+
+def pl_tune_get(stage: int, kernel: int) -> tuple[int, int, int]:
+    """(tile_rows, tile_cols, fuse) used for a stage and window size."""
+    r, c, f = _i32(), _i32(), _i32()
+    _check(_lib.pl_tune_get(stage, kernel, ctypes.byref(r), ctypes.byref(c), ctypes.byref(f)),
+           "pl_tune_get")
+    return r.value, c.value, f.value
+
+
+def pl_tune_set(stage: int, kernel: int, tile_rows: int, tile_cols: int, fuse: int) -> None:
+    _check(_lib.pl_tune_set(stage, kernel, tile_rows, tile_cols, fuse), "pl_tune_set")
+
+
+class Batch:
+    """A batch of frames through the whole path with one persistent launch
+    per stage (pl_batch_* in include/pl.h).
+
+    `frames` is a list of dicts with keys pts ([M, N, 3] float32 device
+    tensor), kernel_lap, lam, iters_lap, kernel_bil, sigma_length,
+    sigma_angle, iters_bil.  Outputs are allocated here, once, and stay bound
+    to the plan: outputs[i] holds points, normals (filtered, T_FC layout),
+    centroids, tri_valid, tri_map, triangles, halfedges, n_tri, normals_T."""
+
+    def __init__(self, frames: list, normal_dtype=torch.float32, halfedges: bool = True,
+                 tri_valid: bool = True):
+        if not frames:
+            raise ValueError("a batch needs at least one frame")
+        self.ndt = _ndt(normal_dtype)
+        nd = _tdtype(self.ndt)
+        self.device = frames[0]["pts"].device
+        self.inputs, self.outputs = [], []
+        arr = (PLFrame * len(frames))()
+        for i, f in enumerate(frames):
+            pts = f["pts"]
+            _dev_tensor(pts, torch.float32, f"frames[{i}].pts")
+            M, N = int(pts.shape[0]), int(pts.shape[1])
+            T = 2 * max(M - 1, 1) * max(N - 1, 1)
+            e = lambda shape, dt: torch.empty(shape, dtype=dt, device=self.device)
+            o = dict(points=e((M, N, 3), torch.float32),
+                     normals=e((M - 1, N - 1, 2, 3), nd),
+                     centroids=e((M - 1, N - 1, 2, 3), torch.float32),
+                     tri_valid=e(T, torch.uint8) if tri_valid else None,
+                     tri_map=e(T, torch.int32), triangles=e((T, 3), torch.int32),
+                     halfedges=e(3 * T, torch.int32) if halfedges else None,
+                     n_tri=e(1, torch.int32), normals_T=e((T, 3), nd))
+            self.inputs.append(pts)
+            self.outputs.append(o)
+            a = arr[i]
+            a.pts = pts.data_ptr()
+            a.M, a.N = M, N
+            a.kernel_lap, a.iters_lap, a.lambda_ = f["kernel_lap"], f["iters_lap"], f["lam"]
+            a.kernel_bil, a.iters_bil = f["kernel_bil"], f["iters_bil"]
+            a.sigma_length, a.sigma_angle = f["sigma_length"], f["sigma_angle"]
+            for key, field in (("points", "pts_out"), ("normals", "normals"),
+                               ("centroids", "centroids"), ("tri_valid", "tri_valid"),
+                               ("tri_map", "tri_map"), ("triangles", "triangles"),
+                               ("halfedges", "halfedges"), ("n_tri", "n_tri"),
+                               ("normals_T", "normals_T")):
+                setattr(a, field, o[key].data_ptr() if o[key] is not None else None)
+        self._frames = arr
+        n = len(frames)
+        ws_n = _lib.pl_batch_workspace(arr, n, self.ndt)
+        if ws_n == 0:
+            raise PLError(-1, "pl_batch_workspace")
+        self.ws = torch.empty(ws_n, dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_lib.pl_batch_create(arr, n, self.ndt, _ptr(self.ws), ws_n, _stream(self.device),
+                                    ctypes.byref(h)), "pl_batch_create")
+        self._h = h
+        self.n = n
+        self.triangles_total = sum(2 * (int(x.shape[0]) - 1) * (int(x.shape[1]) - 1)
+                                   for x in self.inputs)
+
+    def run(self) -> None:
+        _check(_lib.pl_batch_run(self._h, _stream(self.device)), "pl_batch_run")
+
+    def capture(self) -> None:
+        """Record run() into a HIP graph owned by the plan.  Capture happens
+        on a private stream (the legacy default stream cannot be captured);
+        nothing executes while recording."""
+        self._cap_stream = torch.cuda.Stream(self.device)
+        h = ctypes.c_void_p(self._cap_stream.cuda_stream)
+        _check(_lib.pl_batch_capture(self._h, h), "pl_batch_capture")
+
+    def replay(self) -> None:
+        """Launch the captured graph on the current stream."""
+        _check(_lib.pl_batch_replay(self._h, _stream(self.device)), "pl_batch_replay")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.pl_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,6 +1,10 @@
 // extern "C" entry points of libpl.so: argument validation, then dispatch to
 // the kernel launchers.  Nothing is enqueued when validation fails.
 #include "common.h"
+#include "tuning.h"
+
+#include <algorithm>
+#include <vector>
 
 #include <math.h>
 #include <stdarg.h>
@@ -255,6 +259,201 @@ __attribute__((visibility("default"))) pl_status pl_bilateral(
     return launch_bilateral(normals_in, centroids, ndt, M, N, kernel, sigma_length,
                             sigma_angle, iterations, normals_out, tri_map, normals_T, ws,
                             stream);
+}
+
+__attribute__((visibility("default"))) pl_status pl_tune_get(pl_stage stage, int32_t kernel,
+                                                             int32_t *tile_rows,
+                                                             int32_t *tile_cols, int32_t *fuse) {
+    g_err[0] = 0;
+    PL_TRY(check_kernel(kernel));
+    if (stage != PL_STAGE_LAPLACIAN && stage != PL_STAGE_BILATERAL) {
+        set_error("unknown stage %d", (int)stage);
+        return PL_ERR_ARG;
+    }
+    const TileCfg c = tile_cfg(stage == PL_STAGE_LAPLACIAN ? kStageLaplacian : kStageBilateral,
+                               kernel / 2);
+    if (tile_rows) *tile_rows = c.th;
+    if (tile_cols) *tile_cols = c.tw;
+    if (fuse) *fuse = c.fuse;
+    return PL_OK;
+}
+
+__attribute__((visibility("default"))) pl_status pl_tune_set(pl_stage stage, int32_t kernel,
+                                                             int32_t tile_rows,
+                                                             int32_t tile_cols, int32_t fuse) {
+    g_err[0] = 0;
+    PL_TRY(check_kernel(kernel));
+    if (stage != PL_STAGE_LAPLACIAN && stage != PL_STAGE_BILATERAL) {
+        set_error("unknown stage %d", (int)stage);
+        return PL_ERR_ARG;
+    }
+    if (!set_tile_cfg(stage == PL_STAGE_LAPLACIAN ? kStageLaplacian : kStageBilateral,
+                      kernel / 2, TileCfg{tile_rows, tile_cols, fuse})) {
+        set_error("tile %d x %d with %d fused sweeps is outside the kernels' limits", tile_rows,
+                  tile_cols, fuse);
+        return PL_ERR_ARG;
+    }
+    return PL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Span {
+    uintptr_t a, b;     // [a, b)
+    int frame;
+    bool output;
+};
+
+// Full validation of a batch's frame list.
+pl_status check_batch(const pl_frame *frames, int32_t n, pl_dtype ndt) {
+    if (!frames || n < 1) {
+        set_error("a batch needs at least one frame");
+        return PL_ERR_ARG;
+    }
+    if (ndt != PL_F32 && ndt != PL_F16) {
+        set_error("unknown normal dtype %d", (int)ndt);
+        return PL_ERR_ARG;
+    }
+    std::vector<Span> spans;
+    const size_t nb = ndt == PL_F32 ? 4 : 2;
+    for (int i = 0; i < n; ++i) {
+        const pl_frame &f = frames[i];
+        if (pl_status st = check_shape(f.M, f.N)) {
+            set_error("frame %d: %s", i, pl_last_error());
+            return st;
+        }
+        if (check_kernel(f.kernel_lap) || check_kernel(f.kernel_bil)) {
+            set_error("frame %d: kernel sizes %d / %d must be odd and in [3, 9]", i, f.kernel_lap,
+                      f.kernel_bil);
+            return PL_ERR_KERNEL;
+        }
+        if (!(f.lambda >= 0.f && f.lambda <= 1.f) || f.iters_lap < 0 || f.iters_bil < 0 ||
+            !(f.sigma_length > 0.f) || !isfinite(f.sigma_length) || !(f.sigma_angle > 0.f) ||
+            !isfinite(f.sigma_angle)) {
+            set_error("frame %d: lambda, sigmas or sweep counts out of range", i);
+            return PL_ERR_ARG;
+        }
+        const std::pair<const void *, const char *> req[] = {
+            {f.pts, "pts"}, {f.pts_out, "pts_out"}, {f.normals, "normals"},
+            {f.centroids, "centroids"}, {f.tri_map, "tri_map"}, {f.triangles, "triangles"},
+            {f.n_tri, "n_tri"}, {f.normals_T, "normals_T"}};
+        for (auto &r : req) {
+            if (!r.first || !aligned16(r.first)) {
+                set_error("frame %d: %s is NULL or not 16-byte aligned", i, r.second);
+                return PL_ERR_ARG;
+            }
+        }
+        if ((f.tri_valid && !aligned16(f.tri_valid)) || (f.halfedges && !aligned16(f.halfedges))) {
+            set_error("frame %d: tri_valid / halfedges not 16-byte aligned", i);
+            return PL_ERR_ARG;
+        }
+        const size_t P = (size_t)f.M * f.N, T = 2 * (size_t)(f.M - 1) * (f.N - 1);
+        auto add = [&](const void *p, size_t bytes, bool out) {
+            if (p && bytes) spans.push_back(Span{(uintptr_t)p, (uintptr_t)p + bytes, i, out});
+        };
+        add(f.pts, 12 * P, false);
+        add(f.pts_out, 12 * P, true);
+        add(f.normals, 3 * T * nb, true);
+        add(f.centroids, 12 * T, true);
+        add(f.tri_valid, T, true);
+        add(f.tri_map, 4 * T, true);
+        add(f.triangles, 12 * T, true);
+        add(f.halfedges, 12 * T, true);
+        add(f.n_tri, 4, true);
+        add(f.normals_T, 3 * T * nb, true);
+    }
+    std::sort(spans.begin(), spans.end(), [](const Span &x, const Span &y) { return x.a < y.a; });
+    uintptr_t reach = 0;
+    int holder = -1;
+    bool holder_out = false;
+    for (const Span &sp : spans) {
+        // an overlap is allowed only between two inputs (frames may share pts)
+        if (holder >= 0 && sp.a < reach && (sp.output || holder_out)) {
+            set_error("buffers of frames %d and %d overlap (an output must not overlap anything)",
+                      holder, sp.frame);
+            return PL_ERR_ALIAS;
+        }
+        if (sp.b > reach) {
+            reach = sp.b;
+            holder = sp.frame;
+            holder_out = sp.output;
+        } else if (sp.output) {
+            holder_out = true;
+        }
+    }
+    return PL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) size_t pl_batch_workspace(const pl_frame *frames,
+                                                                 int32_t n, pl_dtype ndt) {
+    if (check_batch(frames, n, ndt)) return 0;
+    return batch_workspace(frames, n, ndt);
+}
+
+__attribute__((visibility("default"))) pl_status pl_batch_create(const pl_frame *frames,
+                                                                 int32_t n, pl_dtype ndt,
+                                                                 void *ws, size_t ws_bytes,
+                                                                 hipStream_t stream,
+                                                                 pl_batch *out) {
+    g_err[0] = 0;
+    if (!out) {
+        set_error("out is NULL");
+        return PL_ERR_ARG;
+    }
+    *out = nullptr;
+    PL_TRY(check_batch(frames, n, ndt));
+    const size_t need = batch_workspace(frames, n, ndt);
+    PL_TRY(check_ws(ws, ws_bytes, need));
+    const uintptr_t w0 = (uintptr_t)ws, w1 = w0 + need;
+    for (int i = 0; i < n; ++i) {
+        const pl_frame &f = frames[i];
+        const size_t P = (size_t)f.M * f.N;
+        const uintptr_t a = (uintptr_t)f.pts;
+        if (a < w1 && w0 < a + 12 * P) {
+            set_error("frame %d: pts overlaps the workspace", i);
+            return PL_ERR_ALIAS;
+        }
+    }
+    return batch_create(frames, n, ndt, ws, stream, out);
+}
+
+__attribute__((visibility("default"))) pl_status pl_batch_run(pl_batch batch, hipStream_t stream) {
+    g_err[0] = 0;
+    if (!batch) {
+        set_error("batch is NULL");
+        return PL_ERR_ARG;
+    }
+    return batch_run(batch, stream);
+}
+
+__attribute__((visibility("default"))) pl_status pl_batch_capture(pl_batch batch,
+                                                                  hipStream_t stream) {
+    g_err[0] = 0;
+    if (!batch) {
+        set_error("batch is NULL");
+        return PL_ERR_ARG;
+    }
+    return batch_capture(batch, stream);
+}
+
+__attribute__((visibility("default"))) pl_status pl_batch_replay(pl_batch batch,
+                                                                 hipStream_t stream) {
+    g_err[0] = 0;
+    if (!batch) {
+        set_error("batch is NULL");
+        return PL_ERR_ARG;
+    }
+    return batch_replay(batch, stream);
+}
+
+__attribute__((visibility("default"))) void pl_batch_destroy(pl_batch batch) {
+    batch_destroy(batch);
 }
 
 }  // extern "C"

@@ -1,0 +1,582 @@
+// Per-tile device bodies shared by the single-frame kernels and the batched
+// persistent kernels, so that a frame gets bit-for-bit the same result
+// whichever way it is launched.  Tile shapes and the number of fused sweeps
+// are runtime values (LDS is dynamic), which lets the tuner pick them.
+#pragma once
+
+#include "common.h"
+
+#include <float.h>
+
+namespace pl {
+
+constexpr int kTileBlock = 256;        // threads per workgroup for every tile body
+
+// ---------------------------------------------------------------------------
+// Mesh (Sec. 4.2, Alg. 1 and Alg. 2), one quad row per call.
+// ---------------------------------------------------------------------------
+
+constexpr int kMeshChunk = 4 * kTileBlock;    // columns staged per pass
+
+// Validity codes of quad row u (bit 0: first triangle, bit 1: second) and the
+// row's triangle count.  All point loads of a 1024-column chunk are issued
+// before any is used; point validity is staged in LDS.
+__device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, int N, int u,
+                                               uint8_t *__restrict__ codes,
+                                               uint8_t *__restrict__ tri_valid,
+                                               int *__restrict__ row_count) {
+    __shared__ uint8_t ok[2][kMeshChunk + 1];
+    __shared__ int red[kTileBlock / kWave];
+    const int Nq = N - 1;
+    const float *r0 = pts + (size_t)u * N * 3;
+    const float *r1 = r0 + (size_t)N * 3;
+    int cnt = 0;
+    for (int v0 = 0; v0 < Nq; v0 += kMeshChunk) {
+        float x[2][5], y[2][5], z[2][5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int v = v0 + threadIdx.x + j * kTileBlock;
+            const bool in = (j < 4 || threadIdx.x == 0) && v < N && v <= v0 + kMeshChunk;
+            x[0][j] = in ? r0[3 * v] : 0.f; y[0][j] = in ? r0[3 * v + 1] : 0.f; z[0][j] = in ? r0[3 * v + 2] : 0.f;
+            x[1][j] = in ? r1[3 * v] : 0.f; y[1][j] = in ? r1[3 * v + 1] : 0.f; z[1][j] = in ? r1[3 * v + 2] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int l = threadIdx.x + j * kTileBlock;
+            if (j < 4 || threadIdx.x == 0) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+                    ok[r][l] = !(is_nan_bits(x[r][j]) || is_nan_bits(y[r][j]) || is_nan_bits(z[r][j]));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int l = threadIdx.x + j * kTileBlock;
+            const int v = v0 + l;
+            if (v < Nq) {
+                const int p1 = ok[0][l], p2 = ok[0][l + 1], p3 = ok[1][l + 1], p4 = ok[1][l];
+                const int f = p1 & p2 & p3;          // first triangle (p3, p2, p1)
+                const int s = p1 & p3 & p4;          // second triangle (p1, p4, p3)
+                const size_t q = (size_t)u * Nq + v;
+                codes[q] = (uint8_t)(f | (s << 1));
+                if (tri_valid) {
+                    tri_valid[2 * q] = (uint8_t)f;
+                    tri_valid[2 * q + 1] = (uint8_t)s;
+                }
+                cnt += f + s;
+            }
+        }
+        __syncthreads();
+    }
+    cnt = wave_sum(cnt);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+#pragma unroll
+        for (int w = 0; w < kTileBlock / kWave; ++w) t += red[w];
+        row_count[u] = t;
+    }
+    __syncthreads();                 // LDS is reused by the next call in a persistent loop
+}
+
+// Block-wide exclusive scan of a packed triple of 10-bit counters (a chunk of
+// kTileBlock quads holds at most 512 triangles per row).
+__device__ __forceinline__ int mesh_block_scan(int x, int *total) {
+    __shared__ int wsum[kTileBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int incl = wave_inclusive_scan(x);
+    __syncthreads();
+    if (lane == kWave - 1) wsum[wid] = incl;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kTileBlock / kWave; ++w) {
+        const int t = wsum[w];
+        before += w < wid ? t : 0;
+        all += t;
+    }
+    *total = all;
+    return before + incl - x;
+}
+
+__device__ __forceinline__ int popc2(int c) { return (c & 1) + ((c >> 1) & 1); }
+
+// T_map, T and HE of quad row u.  The row's place in T is the sum of the
+// counts of the rows above it; the codes of rows u-1 and u+1 give the
+// indices of the Top and Bottom twins.  The last row writes |T|.
+__device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
+                                              const int *__restrict__ row_count, int Mq, int N,
+                                              int u, int32_t *__restrict__ tri_map,
+                                              int32_t *__restrict__ tris,
+                                              int32_t *__restrict__ he, int cap,
+                                              int32_t *__restrict__ n_tri) {
+    __shared__ int red[kTileBlock / kWave];
+    const int Nq = N - 1;
+    const uint8_t *cr0 = codes + (size_t)u * Nq;
+    const uint8_t *crm = u > 0 ? cr0 - Nq : cr0;        // row u-1
+    const uint8_t *crp = u + 1 < Mq ? cr0 + Nq : cr0;   // row u+1
+    int above = 0;
+    for (int r = threadIdx.x; r < u - 1; r += kTileBlock) above += row_count[r];
+    above = wave_sum(above);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = above;
+    __syncthreads();
+    int basem = 0;
+#pragma unroll
+    for (int w = 0; w < kTileBlock / kWave; ++w) basem += red[w];
+    const int base0 = basem + (u > 0 ? row_count[u - 1] : 0);
+    const int basep = base0 + row_count[u];
+    if (u == Mq - 1 && threadIdx.x == 0) *n_tri = basep;
+    int carry0 = 0, carrym = 0, carryp = 0;
+    for (int v0 = 0; v0 < Nq; v0 += kTileBlock) {
+        const int v = v0 + threadIdx.x;
+        const bool in = v < Nq;
+        const int c0 = in ? cr0[v] : 0;
+        const int cm = (in && u > 0) ? crm[v] : 0;
+        const int cp = (in && u + 1 < Mq) ? crp[v] : 0;
+        const int n0 = popc2(c0);
+        int total;
+        const int ex = mesh_block_scan(n0 | (popc2(cm) << 10) | (popc2(cp) << 20), &total);
+        const int p0 = ex & 1023, pm = (ex >> 10) & 1023, pp = (ex >> 20) & 1023;
+        if (in) {
+            const int f = c0 & 1, s = (c0 >> 1) & 1;
+            const int rank0 = base0 + carry0 + p0;       // index of (u,v,0) if valid
+            const int rF = f ? rank0 : -1;
+            const int rS = s ? rank0 + f : -1;
+            const size_t q = (size_t)u * Nq + v;
+            *reinterpret_cast<int2 *>(tri_map + 2 * q) = make_int2(rF, rS);
+            const int i1 = u * N + v, i2 = i1 + 1, i3 = i1 + N + 1, i4 = i1 + N;
+            if (f && rF < cap) {
+                tris[3 * rF + 0] = i3; tris[3 * rF + 1] = i2; tris[3 * rF + 2] = i1;
+            }
+            if (s && rS < cap) {
+                tris[3 * rS + 0] = i1; tris[3 * rS + 1] = i4; tris[3 * rS + 2] = i3;
+            }
+            if (he) {
+                // Right = (u, v+1, 1), Top = (u-1, v, 1), Left = (u, v-1, 0),
+                // Bottom = (u+1, v, 0); indices from the prefix sums.
+                const int cr = v + 1 < Nq ? cr0[v + 1] : 0;
+                const int cl = v > 0 ? cr0[v - 1] : 0;
+                const int right = (cr & 2) ? rank0 + n0 + (cr & 1) : -1;
+                const int left = (cl & 1) ? rank0 - popc2(cl) : -1;
+                const int top = (cm & 2) ? basem + carrym + pm + (cm & 1) : -1;
+                const int bottom = (cp & 1) ? basep + carryp + pp : -1;
+                if (f && rF < cap) {
+                    he[3 * rF + 0] = right >= 0 ? 3 * right : -1;
+                    he[3 * rF + 1] = top >= 0 ? 3 * top + 1 : -1;
+                    he[3 * rF + 2] = s ? 3 * rS + 2 : -1;
+                }
+                if (s && rS < cap) {
+                    he[3 * rS + 0] = left >= 0 ? 3 * left : -1;
+                    he[3 * rS + 1] = bottom >= 0 ? 3 * bottom + 1 : -1;
+                    he[3 * rS + 2] = f ? 3 * rF + 2 : -1;
+                }
+            }
+        }
+        carry0 += total & 1023;
+        carrym += (total >> 10) & 1023;
+        carryp += (total >> 20) & 1023;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Laplacian (Sec. 2.3 Eqs. 1-2 on the image neighbourhood of Sec. 5.1):
+// F Jacobi sweeps of one TH x TW tile, temporally blocked in LDS.
+//
+// The tile plus a halo of R*F pixels is staged as float4 (x, y, z, pad);
+// sweep f updates the region that is still exact after f steps (shrinking by
+// R per side) between two LDS buffers, and the centre is written back.
+// Invalid pixels (any NaN coordinate) and pixels outside the image are staged
+// as (0, 0, 0, +inf): the pad makes the squared distance +inf, whose
+// reciprocal square root is exactly 0, so they drop out of both sums without
+// a branch.  Invalid pixels and the border band are never updated; invalid
+// pixels are written back from the input bits.  F = 0 copies the tile.
+// LDS: 2 * (TH + 2RF) * (TW + 2RF) float4.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ constexpr size_t lap_lds_bytes(int R, int F, int TH, int TW) {
+    return 2 * sizeof(float4) * (size_t)(TH + 2 * R * F) * (size_t)(TW + 2 * R * F);
+}
+
+template <int R>
+__device__ __forceinline__ void lap_tile(const float *__restrict__ src, float *__restrict__ dst,
+                                         int M, int N, float lam, int F, int TH, int TW,
+                                         int ty0, int tx0, float4 *lds) {
+    const int halo = R * F;
+    const int H = TH + 2 * halo, W = TW + 2 * halo;
+    float4 *A = lds;
+    float4 *B = lds + H * W;
+    const int oy = ty0 - halo, ox = tx0 - halo;
+    const float inf = __builtin_inff();
+
+    for (int idx = threadIdx.x; idx < H * W; idx += kTileBlock) {
+        const int ly = idx / W, lx = idx - ly * W;
+        const int gy = oy + ly, gx = ox + lx;
+        float4 p = make_float4(0.f, 0.f, 0.f, inf);
+        if (gy >= 0 && gy < M && gx >= 0 && gx < N) {
+            const float *q = src + 3 * ((size_t)gy * N + gx);
+            const float x = q[0], y = q[1], z = q[2];
+            if (!(is_nan_bits(x) || is_nan_bits(y) || is_nan_bits(z))) p = make_float4(x, y, z, 0.f);
+        }
+        A[idx] = p;
+    }
+    __syncthreads();
+
+    for (int f = 1; f <= F; ++f) {
+        const int lo = R * f;
+        const int Hf = H - 2 * lo, Wf = W - 2 * lo;
+        for (int idx = threadIdx.x; idx < Hf * Wf; idx += kTileBlock) {
+            const int ry = idx / Wf;
+            const int ly = lo + ry, lx = lo + (idx - ry * Wf);
+            const int gy = oy + ly, gx = ox + lx;
+            const float4 c = A[ly * W + lx];
+            float4 o = c;
+            const bool active = c.w == 0.f && gy >= R && gy < M - R && gx >= R && gx < N - R;
+            if (active) {
+                float ws = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+                // 3x3: fully unrolled; larger windows: one row of the window
+                // per iteration, so only that row's neighbours are live
+#pragma unroll(R == 1 ? 3 : 1)
+                for (int dy = -R; dy <= R; ++dy) {
+#pragma unroll
+                    for (int dx = -R; dx <= R; ++dx) {
+                        if (dy == 0 && dx == 0) continue;
+                        const float4 p = A[(ly + dy) * W + lx + dx];
+                        const float ex = p.x - c.x, ey = p.y - c.y, ez = p.z - c.z;
+                        const float d2 = fmaf(ex, ex, fmaf(ey, ey, fmaf(ez, ez, p.w)));
+                        float w = __builtin_amdgcn_rsqf(d2);     // 1/||v_j - v_i||
+                        w = d2 > 0.f ? w : 0.f;                   // coincident: skipped
+                        ws += w;
+                        sx = fmaf(w, ex, sx);
+                        sy = fmaf(w, ey, sy);
+                        sz = fmaf(w, ez, sz);
+                    }
+                }
+                if (ws > 0.f) {
+                    const float k = lam / ws;
+                    o.x = fmaf(k, sx, c.x);
+                    o.y = fmaf(k, sy, c.y);
+                    o.z = fmaf(k, sz, c.z);
+                }
+            }
+            B[ly * W + lx] = o;
+        }
+        __syncthreads();
+        float4 *t = A; A = B; B = t;
+    }
+
+    for (int idx = threadIdx.x; idx < TH * TW; idx += kTileBlock) {
+        const int ry = idx / TW, rx = idx - ry * TW;
+        const int gy = ty0 + ry, gx = tx0 + rx;
+        if (gy >= M || gx >= N) continue;
+        const size_t off = 3 * ((size_t)gy * N + gx);
+        const float4 c = A[(ry + halo) * W + rx + halo];
+        if (c.w == 0.f) {
+            dst[off] = c.x; dst[off + 1] = c.y; dst[off + 2] = c.z;
+        } else {
+            dst[off] = src[off]; dst[off + 1] = src[off + 1]; dst[off + 2] = src[off + 2];
+        }
+    }
+    __syncthreads();                 // LDS is reused by the next tile
+}
+
+// ---------------------------------------------------------------------------
+// Triangle centroids and normals (Sec. 5.2) of one quad.
+// ---------------------------------------------------------------------------
+
+struct V3 {
+    float x, y, z;
+};
+
+__device__ __forceinline__ V3 ld3(const float *p) { return V3{p[0], p[1], p[2]}; }
+__device__ __forceinline__ bool ok3(const V3 &a) {
+    return !(is_nan_bits(a.x) || is_nan_bits(a.y) || is_nan_bits(a.z));
+}
+
+// centroid (a + b + c) / 3 and unit normal of (b - a) x (c - a); NaN normal
+// when the cross product vanishes.
+__device__ __forceinline__ void tri_geom(const V3 &a, const V3 &b, const V3 &c, V3 &cen, V3 &nrm) {
+    const float third = 1.0f / 3.0f;
+    cen.x = (a.x + b.x + c.x) * third;
+    cen.y = (a.y + b.y + c.y) * third;
+    cen.z = (a.z + b.z + c.z) * third;
+    const float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
+    const float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
+    const float nx = e1y * e2z - e1z * e2y;
+    const float ny = e1z * e2x - e1x * e2z;
+    const float nz = e1x * e2y - e1y * e2x;
+    const float l2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+    if (l2 > 0.f) {
+        const float k = __builtin_amdgcn_rsqf(l2);
+        nrm = V3{nx * k, ny * k, nz * k};
+    } else {
+        nrm = V3{qnan(), qnan(), qnan()};
+    }
+}
+
+template <typename NT>
+__device__ __forceinline__ void normals_quad(const float *__restrict__ pts, int N, int Nq, size_t q,
+                                             NT *__restrict__ normals,
+                                             float *__restrict__ centroids) {
+    const int u = (int)(q / Nq), v = (int)(q - (size_t)u * Nq);
+    const float *r0 = pts + 3 * ((size_t)u * N + v);
+    const float *r1 = r0 + 3 * (size_t)N;
+    const V3 p1 = ld3(r0), p2 = ld3(r0 + 3), p3 = ld3(r1 + 3), p4 = ld3(r1);
+    const bool v1 = ok3(p1), v2 = ok3(p2), v3 = ok3(p3), v4 = ok3(p4);
+    const V3 nan3{qnan(), qnan(), qnan()};
+    V3 c0 = nan3, n0 = nan3, c1 = nan3, n1 = nan3;
+    if (v1 & v2 & v3) tri_geom(p3, p2, p1, c0, n0);     // first triangle
+    if (v1 & v3 & v4) tri_geom(p1, p4, p3, c1, n1);     // second triangle
+    float *co = centroids + 6 * q;
+    co[0] = c0.x; co[1] = c0.y; co[2] = c0.z;
+    co[3] = c1.x; co[4] = c1.y; co[5] = c1.z;
+    NT *no = normals + 6 * q;
+    st_f(no + 0, n0.x); st_f(no + 1, n0.y); st_f(no + 2, n0.z);
+    st_f(no + 3, n1.x); st_f(no + 4, n1.y); st_f(no + 5, n1.z);
+}
+
+// ---------------------------------------------------------------------------
+// Bilateral normal filter (Sec. 2.3 Eqs. 3-6; neighbourhood of Sec. 5.2):
+// F Jacobi sweeps of one TQH x TQW tile of quads, temporally blocked in LDS.
+//
+// A thread owns a quad and filters both of its triangles, which share every
+// neighbour load (the paper's unit of work).  With log2(e) folded into
+//     ka = log2(e) / (2 sigma_l^2),  kb = log2(e) / (2 sigma_a^2),
+// a neighbour's weight is w = 2^-e, e = ka ||c_i - c_j||^2 + kb ||n_i - n_j||^2.
+// Both squared distances come from component differences (exact for nearby
+// float32 values) before scaling; expanding them or pre-scaling the
+// centroids saves instructions but costs ~1e-5 relative weight accuracy.
+//
+// Eq. 6 renormalises, so a common factor of the weights cancels.  Since
+// e >= 0 no weight exceeds 1; if the whole neighbourhood is so far away that
+// the total weight drops below 2^-60, that triangle is recomputed with every
+// exponent shifted by the smallest one (the same value in exact arithmetic),
+// which keeps the largest term at 1.  Only the lanes that need it take it.
+//
+// Off-grid quads and triangles with a NaN normal or centroid are staged with
+// an infinite centroid and a zero normal: infinite exponent, weight exactly 0,
+// contribution 0.  A triangle that is itself missing is copied through (its
+// input bits).  Float16-stored normals produced by an intermediate sweep are
+// re-rounded to float16, as if stored between launches, so results do not
+// depend on F.  F = 0 copies the tile (and gathers).
+// LDS: 3 * 2 * (TQH + 2RF) * (TQW + 2RF) float4 (centroids, two normal
+// buffers); with F <= 1 the second normal buffer is not used.
+// ---------------------------------------------------------------------------
+
+constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
+
+__host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW) {
+    return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F);
+}
+
+template <typename NT> __device__ __forceinline__ float round_storage(float x);
+template <> __device__ __forceinline__ float round_storage<float>(float x) { return x; }
+template <> __device__ __forceinline__ float round_storage<__half>(float x) {
+    return __half2float(__float2half_rn(x));
+}
+
+struct BilOwn {
+    float cx, cy, cz;
+    float nx, ny, nz;
+    float ka, kb;
+};
+
+__device__ __forceinline__ float bil_pair_e(const BilOwn &o, const float4 c, const float4 n) {
+    const float ax = o.nx - n.x, ay = o.ny - n.y, az = o.nz - n.z;
+    const float dn2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
+    const float dx = o.cx - c.x, dy = o.cy - c.y, dz = o.cz - c.z;
+    const float dc2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    return fmaf(dc2, o.ka, dn2 * o.kb);
+}
+
+struct BilAcc {
+    float x, y, z, w;
+};
+
+__device__ __forceinline__ void bil_accumulate(BilAcc &s, const BilOwn &o, const float4 c,
+                                               const float4 n) {
+    const float w = __builtin_amdgcn_exp2f(-bil_pair_e(o, c, n));
+    s.w += w;
+    s.x = fmaf(w, n.x, s.x);
+    s.y = fmaf(w, n.y, s.y);
+    s.z = fmaf(w, n.z, s.z);
+}
+
+template <int R>
+__device__ __forceinline__ BilAcc bil_shifted_sum(const BilOwn o, const float4 *sc,
+                                                  const float4 *sn, int a0, int pitch,
+                                                  int plane) {
+    const float inf = __builtin_inff();
+    float m = inf;
+#pragma unroll 1
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll 1
+        for (int dx = -R; dx <= R; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            for (int kk = 0; kk < 2; ++kk) {
+                const int b = a0 + dy * pitch + dx + kk * plane;
+                m = fminf(m, bil_pair_e(o, sc[b], sn[b]));
+            }
+        }
+    BilAcc s{0.f, 0.f, 0.f, 0.f};
+    if (!(m < inf)) return s;               // no usable neighbour
+#pragma unroll 1
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll 1
+        for (int dx = -R; dx <= R; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            for (int kk = 0; kk < 2; ++kk) {
+                const int b = a0 + dy * pitch + dx + kk * plane;
+                const float4 n = sn[b];
+                const float w = __builtin_amdgcn_exp2f(m - bil_pair_e(o, sc[b], n));
+                s.w += w;
+                s.x = fmaf(w, n.x, s.x);
+                s.y = fmaf(w, n.y, s.y);
+                s.z = fmaf(w, n.z, s.z);
+            }
+        }
+    return s;
+}
+
+template <typename NT>
+__device__ __forceinline__ float4 bil_finish(BilAcc s, float4 cur) {
+    const float l2 = fmaf(s.x, s.x, fmaf(s.y, s.y, s.z * s.z));
+    if (!(s.w > 0.f) || !(l2 > 0.f)) return cur;
+    const float k = __builtin_amdgcn_rsqf(l2);
+    return make_float4(round_storage<NT>(s.x * k), round_storage<NT>(s.y * k),
+                       round_storage<NT>(s.z * k), cur.w);
+}
+
+// Filter both triangles of the quad at LDS index a; usable flags live in the
+// centroids' fourth lane.
+template <int R, typename NT>
+__device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *sn, int a,
+                                                int pitch, int plane, float ka, float kb,
+                                                float4 &r0, float4 &r1) {
+    const float4 c0 = sc[a], c1 = sc[plane + a];
+    const float4 n0 = sn[a], n1 = sn[plane + a];
+    const BilOwn o0{c0.x, c0.y, c0.z, n0.x, n0.y, n0.z, ka, kb};
+    const BilOwn o1{c1.x, c1.y, c1.z, n1.x, n1.y, n1.z, ka, kb};
+    BilAcc s0{0.f, 0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f, 0.f};
+    // one window row per iteration keeps only that row's neighbours live
+#pragma unroll 1
+    for (int dy = -R; dy <= R; ++dy) {
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            if (dy == 0 && dx == 0) continue;     // the own quad is not a neighbour
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int b = a + dy * pitch + dx + kk * plane;
+                const float4 c = sc[b], n = sn[b];
+                bil_accumulate(s0, o0, c, n);
+                bil_accumulate(s1, o1, c, n);
+            }
+        }
+    }
+    const bool ok0 = c0.w != 0.f, ok1 = c1.w != 0.f;
+    if (ok0 && !(s0.w >= kBilUnderflow)) s0 = bil_shifted_sum<R>(o0, sc, sn, a, pitch, plane);
+    if (ok1 && !(s1.w >= kBilUnderflow)) s1 = bil_shifted_sum<R>(o1, sc, sn, a, pitch, plane);
+    r0 = ok0 ? bil_finish<NT>(s0, n0) : n0;
+    r1 = ok1 ? bil_finish<NT>(s1, n1) : n1;
+}
+
+template <int R, typename NT>
+__device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float *__restrict__ cen,
+                                         NT *__restrict__ nout, int Mq, int Nq, float ka, float kb,
+                                         int F, int TQH, int TQW, int qy0, int qx0,
+                                         const int32_t *__restrict__ tri_map, NT *__restrict__ nT,
+                                         float4 *lds) {
+    const int halo = R * F;
+    const int H = TQH + 2 * halo, W = TQW + 2 * halo, S = H * W;
+    float4 *s_c = lds;                  // [2][S] centroids, w = 1 if usable
+    float4 *s_n = lds + 2 * S;          // [2][S] normals
+    float4 *s_m = lds + 4 * S;          // [2][S] second normal buffer (F > 1)
+    const float inf = __builtin_inff();
+    const int oy = qy0 - halo, ox = qx0 - halo;
+
+    if (F > 0) {
+        for (int idx = threadIdx.x; idx < S; idx += kTileBlock) {
+            const int ly = idx / W, lx = idx - ly * W;
+            const int qy = oy + ly, qx = ox + lx;
+            float4 c0 = make_float4(inf, inf, inf, 0.f), c1 = c0;
+            float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
+            if (qy >= 0 && qy < Mq && qx >= 0 && qx < Nq) {
+                const size_t q = (size_t)qy * Nq + qx;
+                float n[6], c[6];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) { n[i] = ld_f(nin + 6 * q + i); c[i] = cen[6 * q + i]; }
+                bool ok0 = true, ok1 = true;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    ok0 = ok0 && !is_nan_bits(n[i]) && !is_nan_bits(c[i]);
+                    ok1 = ok1 && !is_nan_bits(n[3 + i]) && !is_nan_bits(c[3 + i]);
+                }
+                if (ok0) { c0 = make_float4(c[0], c[1], c[2], 1.f); n0 = make_float4(n[0], n[1], n[2], 0.f); }
+                if (ok1) { c1 = make_float4(c[3], c[4], c[5], 1.f); n1 = make_float4(n[3], n[4], n[5], 0.f); }
+            }
+            s_c[idx] = c0; s_c[S + idx] = c1;
+            s_n[idx] = n0; s_n[S + idx] = n1;
+        }
+        __syncthreads();
+    }
+
+    const float4 *cur = s_n;
+    float4 *nxt = s_m;
+    // intermediate sweeps: LDS to LDS over the shrinking exact region
+    for (int f = 1; f < F; ++f) {
+        const int lo = R * f;
+        const int Hf = H - 2 * lo, Wf = W - 2 * lo;
+        for (int idx = threadIdx.x; idx < Hf * Wf; idx += kTileBlock) {
+            const int ry = idx / Wf;
+            const int a = (lo + ry) * W + lo + (idx - ry * Wf);
+            float4 r0, r1;
+            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r0, r1);
+            nxt[a] = r0;
+            nxt[S + a] = r1;
+        }
+        __syncthreads();
+        float4 *t = const_cast<float4 *>(cur);
+        cur = nxt;
+        nxt = t;
+    }
+
+    // last sweep (or the copy when F = 0): the tile itself, to global memory
+    for (int idx = threadIdx.x; idx < TQH * TQW; idx += kTileBlock) {
+        const int ty = idx / TQW, tx = idx - ty * TQW;
+        const int qy = qy0 + ty, qx = qx0 + tx;
+        if (qy >= Mq || qx >= Nq) continue;
+        const size_t q = (size_t)qy * Nq + qx;
+        NT v[6];
+        if (F > 0) {
+            const int a = (ty + halo) * W + tx + halo;
+            float4 r[2];
+            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r[0], r[1]);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (s_c[k * S + a].w != 0.f) {
+                    st_f(&v[3 * k], r[k].x); st_f(&v[3 * k + 1], r[k].y); st_f(&v[3 * k + 2], r[k].z);
+                } else {                       // missing triangle: input bits unchanged
+                    v[3 * k] = nin[6 * q + 3 * k];
+                    v[3 * k + 1] = nin[6 * q + 3 * k + 1];
+                    v[3 * k + 2] = nin[6 * q + 3 * k + 2];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) v[i] = nin[6 * q + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) nout[6 * q + i] = v[i];
+        if (tri_map) {
+            const int t0 = tri_map[2 * q], t1 = tri_map[2 * q + 1];
+            if (t0 >= 0) { nT[3 * (size_t)t0] = v[0]; nT[3 * (size_t)t0 + 1] = v[1]; nT[3 * (size_t)t0 + 2] = v[2]; }
+            if (t1 >= 0) { nT[3 * (size_t)t1] = v[3]; nT[3 * (size_t)t1 + 1] = v[4]; nT[3 * (size_t)t1 + 2] = v[5]; }
+        }
+    }
+    __syncthreads();                 // LDS is reused by the next tile
+}
+
+}  // namespace pl

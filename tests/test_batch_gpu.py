@@ -1,0 +1,157 @@
+"""The batched path (one persistent launch per stage over mixed frames) gives
+every frame exactly its single-frame result, replays correctly from a HIP
+graph, and float32 outputs do not depend on tile shapes or sweep fusion."""
+import numpy as np
+import pytest
+
+from synth import KINDS, make_frame, random_grid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2007_12065_amd as pl
+    return pl
+
+
+def dev_t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def spec(pts, kl, lam, il, kb, sl, sa, ib):
+    return dict(pts=dev_t(pts), kernel_lap=kl, lam=lam, iters_lap=il, kernel_bil=kb,
+                sigma_length=sl, sigma_angle=sa, iters_bil=ib)
+
+
+def mixed_specs():
+    out = []
+    for kind, seed in [("rgbd_small", 1), ("rgbd", 2), ("lidar", 3), ("lidar128", 4), ("rgbd", 5)]:
+        k = KINDS[kind]
+        out.append(spec(make_frame(kind, seed), k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
+                        k.sigma_length, k.sigma_angle, k.iters_bil))
+    out.append(spec(random_grid(2, 2, 7), 3, 1.0, 2, 3, 0.1, 0.1, 2))
+    out.append(spec(random_grid(3, 300, 8, nan_frac=0.2), 7, 0.5, 3, 7, 0.05, 0.3, 1))
+    out.append(spec(random_grid(37, 150, 9, nan_frac=0.1), 9, 0.8, 5, 9, 0.2, 0.2, 3))
+    out.append(spec(random_grid(50, 70, 10, nan_frac=0.3), 5, 1.0, 0, 3, 0.1, 0.1, 0))
+    out.append(spec(random_grid(9, 600, 11, nan_frac=0.05), 3, 1.0, 9, 5, 0.1, 0.1, 4))
+    return out
+
+
+def single(pl, s, dtype):
+    """The four single-frame ABI calls with the same parameters."""
+    m = pl.pl_mesh_opc(s["pts"])
+    pts = pl.pl_laplacian(s["pts"], s["kernel_lap"], s["lam"], s["iters_lap"])
+    n, c = pl.pl_tri_normals(pts, dtype)
+    f, nT = pl.pl_bilateral(n, c, s["kernel_bil"], s["sigma_length"], s["sigma_angle"],
+                            s["iters_bil"], tri_map=m["tri_map"])
+    return dict(m, points=pts, normals=f, centroids=c, normals_T=nT)
+
+
+def assert_frame_equal(got, want, tag):
+    n = int(host(want["n_tri"])[0])
+    assert int(host(got["n_tri"])[0]) == n, tag
+    rows = {"triangles": n, "halfedges": 3 * n, "normals_T": n}
+    for key in ("tri_valid", "tri_map", "triangles", "halfedges", "points", "normals",
+                "centroids", "normals_T"):
+        a, b = host(got[key]), host(want[key])
+        if key in rows:
+            a, b = a[:rows[key]], b[:rows[key]]
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (tag, key)
+
+
+@pytest.mark.parametrize("dtype_name", ["float32", "float16"])
+def test_batch_equals_single_frames(pl, dtype_name):
+    import torch
+    dtype = getattr(torch, dtype_name)
+    specs = mixed_specs()
+    print("[case] batch of", len(specs), "frames,", dtype_name, flush=True)
+    b = pl.Batch(specs, dtype)
+    b.run()
+    torch.cuda.synchronize()
+    for i, s in enumerate(specs):
+        assert_frame_equal(b.outputs[i], single(pl, s, dtype), f"frame {i}")
+    b.close()
+
+
+def test_batch_graph_replay(pl):
+    import torch
+    specs = mixed_specs()[:6]
+    b = pl.Batch(specs, torch.float32)
+    b.run()
+    torch.cuda.synchronize()
+    want = [{k: (v.clone() if v is not None else None) for k, v in o.items()} for o in b.outputs]
+    b.capture()
+    other = dev_t(make_frame("rgbd", 77))
+    for rep in range(3):
+        print("[case] graph replay", rep, flush=True)
+        for o in b.outputs:                      # poison every output first
+            for v in o.values():
+                if v is not None:
+                    v.fill_(-7) if v.dtype != torch.uint8 else v.fill_(9)
+        pl.pl_laplacian(other, 3, 1.0, 2)        # unrelated eager work between replays
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        for i in range(len(specs)):
+            assert_frame_equal(b.outputs[i], want[i], f"replay {rep} frame {i}")
+    b.close()
+
+
+def test_batch_runs_repeatedly(pl):
+    import torch
+    specs = mixed_specs()[5:]
+    b = pl.Batch(specs, torch.float32)
+    b.run()
+    torch.cuda.synchronize()
+    first = [host(o["normals_T"]).copy() for o in b.outputs]
+    for _ in range(3):
+        b.run()
+    torch.cuda.synchronize()
+    for f, o in zip(first, b.outputs):
+        assert np.array_equal(f.view(np.uint8), host(o["normals_T"]).view(np.uint8))
+    b.close()
+
+
+def test_tiling_invariance(pl):
+    import torch
+    pts = dev_t(make_frame("lidar", 31))
+    ref_lap = host(pl.pl_laplacian(pts, 5, 1.0, 4)).copy()
+    n, c = pl.pl_tri_normals(dev_t(make_frame("rgbd", 32)))
+    ref_bil = host(pl.pl_bilateral(n, c, 3, 0.1, 0.1, 3)[0]).copy()
+    saved = [pl.pl_tune_get(0, 5), pl.pl_tune_get(1, 3)]
+    try:
+        for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 128, 4), (32, 8, 3)]:
+            print("[case] laplacian tile", th, tw, fu, flush=True)
+            pl.pl_tune_set(0, 5, th, tw, fu)
+            assert np.array_equal(host(pl.pl_laplacian(pts, 5, 1.0, 4)).view(np.uint8),
+                                  ref_lap.view(np.uint8))
+        for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 32, 3), (2, 128, 1)]:
+            print("[case] bilateral tile", th, tw, fu, flush=True)
+            pl.pl_tune_set(1, 3, th, tw, fu)
+            assert np.array_equal(host(pl.pl_bilateral(n, c, 3, 0.1, 0.1, 3)[0]).view(np.uint8),
+                                  ref_bil.view(np.uint8))
+    finally:
+        pl.pl_tune_set(0, 5, *saved[0])
+        pl.pl_tune_set(1, 3, *saved[1])
+
+
+def test_batch_overlap_rejected(pl):
+    import torch
+    s = mixed_specs()[5]
+    b = pl.Batch([s], torch.float32)
+    arr = (pl.PLFrame * 2)()
+    arr[0] = b._frames[0]
+    arr[1] = b._frames[0]                       # same outputs twice
+    assert pl._lib.pl_batch_workspace(arr, 2, 0) == 0
+    assert "overlap" in pl._lib.pl_last_error().decode()
+    b.close()
