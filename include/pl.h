@@ -215,12 +215,17 @@ pl_status pl_tune_set(pl_stage stage, int32_t kernel, int32_t tile_rows, int32_t
  *                     pl_batch_destroy) and uploads its tables; synchronises
  *                     `stream` once.  The frames' buffers are bound to the
  *                     plan: later runs read and write the same addresses.
- * pl_batch_run        enqueues one pass of the whole pipeline on `stream`;
- *                     device-only work, no allocation, no synchronisation,
- *                     legal under stream capture.
- * pl_batch_capture    records pl_batch_run into a HIP graph owned by the
- *                     plan (replacing any previous one); pl_batch_replay
- *                     launches that graph on `stream`.
+ * pl_batch_run        enqueues one pass of the whole pipeline on `stream`
+ *                     over the frames i with active[i] != 0, where `active`
+ *                     is a DEVICE array of n bytes read when the run
+ *                     executes (NULL = every frame).  Frames left out keep
+ *                     their previous outputs.  Device-only work: no
+ *                     allocation, no synchronisation, legal under capture.
+ * pl_batch_capture    records pl_batch_run(active) into a HIP graph owned by
+ *                     the plan (replacing any previous one); pl_batch_replay
+ *                     launches it on `stream`.  The graph reads the mask's
+ *                     contents at replay time, so one graph serves any subset
+ *                     of the plan's frames.
  * pl_batch_destroy    releases the host-side plan (and its graph).
  * Runs of one plan must not overlap in time (they share the queue counters
  * and scratch in `ws`).
@@ -248,8 +253,8 @@ typedef struct pl_batch_s *pl_batch;
 size_t pl_batch_workspace(const pl_frame *frames, int32_t n, pl_dtype ndt);
 pl_status pl_batch_create(const pl_frame *frames, int32_t n, pl_dtype ndt, void *ws,
                           size_t ws_bytes, hipStream_t stream, pl_batch *out);
-pl_status pl_batch_run(pl_batch batch, hipStream_t stream);
-pl_status pl_batch_capture(pl_batch batch, hipStream_t stream);
+pl_status pl_batch_run(pl_batch batch, const uint8_t *active, hipStream_t stream);
+pl_status pl_batch_capture(pl_batch batch, const uint8_t *active, hipStream_t stream);
 pl_status pl_batch_replay(pl_batch batch, hipStream_t stream);
 void pl_batch_destroy(pl_batch batch);
 

@@ -68,9 +68,9 @@ _lib.pl_batch_workspace.restype = _sz
 _lib.pl_batch_create.argtypes = [ctypes.POINTER(PLFrame), _i32, _i32, _vp, _sz, _vp,
                                  ctypes.POINTER(_vp)]
 _lib.pl_batch_create.restype = _i32
-_lib.pl_batch_run.argtypes = [_vp, _vp]
+_lib.pl_batch_run.argtypes = [_vp, _vp, _vp]
 _lib.pl_batch_run.restype = _i32
-_lib.pl_batch_capture.argtypes = [_vp, _vp]
+_lib.pl_batch_capture.argtypes = [_vp, _vp, _vp]
 _lib.pl_batch_capture.restype = _i32
 _lib.pl_batch_replay.argtypes = [_vp, _vp]
 _lib.pl_batch_replay.restype = _i32
@@ -375,16 +375,24 @@ class Batch:
         self.triangles_total = sum(2 * (int(x.shape[0]) - 1) * (int(x.shape[1]) - 1)
                                    for x in self.inputs)
 
-    def run(self) -> None:
-        _check(_lib.pl_batch_run(self._h, _stream(self.device)), "pl_batch_run")
+    def run(self, active: torch.Tensor | None = None) -> None:
+        """One pass over the frames with active[i] != 0 (uint8 device tensor
+        of length n; None = all frames)."""
+        if active is not None:
+            _dev_tensor(active, torch.uint8, "active")
+        _check(_lib.pl_batch_run(self._h, _ptr(active), _stream(self.device)), "pl_batch_run")
 
-    def capture(self) -> None:
-        """Record run() into a HIP graph owned by the plan.  Capture happens
-        on a private stream (the legacy default stream cannot be captured);
+    def capture(self, active: torch.Tensor | None = None) -> None:
+        """Record run(active) into a HIP graph owned by the plan; the graph
+        reads the mask's contents at each replay.  Capture happens on a
+        private stream (the legacy default stream cannot be captured);
         nothing executes while recording."""
+        if active is not None:
+            _dev_tensor(active, torch.uint8, "active")
+        self._cap_active = active
         self._cap_stream = torch.cuda.Stream(self.device)
         h = ctypes.c_void_p(self._cap_stream.cuda_stream)
-        _check(_lib.pl_batch_capture(self._h, h), "pl_batch_capture")
+        _check(_lib.pl_batch_capture(self._h, _ptr(active), h), "pl_batch_capture")
 
     def replay(self) -> None:
         """Launch the captured graph on the current stream."""

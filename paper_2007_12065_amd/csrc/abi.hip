@@ -423,23 +423,26 @@ __attribute__((visibility("default"))) pl_status pl_batch_create(const pl_frame 
     return batch_create(frames, n, ndt, ws, stream, out);
 }
 
-__attribute__((visibility("default"))) pl_status pl_batch_run(pl_batch batch, hipStream_t stream) {
+__attribute__((visibility("default"))) pl_status pl_batch_run(pl_batch batch,
+                                                              const uint8_t *active,
+                                                              hipStream_t stream) {
     g_err[0] = 0;
     if (!batch) {
         set_error("batch is NULL");
         return PL_ERR_ARG;
     }
-    return batch_run(batch, stream);
+    return batch_run(batch, active, stream);
 }
 
 __attribute__((visibility("default"))) pl_status pl_batch_capture(pl_batch batch,
+                                                                  const uint8_t *active,
                                                                   hipStream_t stream) {
     g_err[0] = 0;
     if (!batch) {
         set_error("batch is NULL");
         return PL_ERR_ARG;
     }
-    return batch_capture(batch, stream);
+    return batch_capture(batch, active, stream);
 }
 
 __attribute__((visibility("default"))) pl_status pl_batch_replay(pl_batch batch,

@@ -88,8 +88,8 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 size_t batch_workspace(const pl_frame *frames, int n, pl_dtype ndt);
 pl_status batch_create(const pl_frame *frames, int n, pl_dtype ndt, void *ws, hipStream_t s,
                        pl_batch_s **out);
-pl_status batch_run(const pl_batch_s *b, hipStream_t s);
-pl_status batch_capture(pl_batch_s *b, hipStream_t s);
+pl_status batch_run(const pl_batch_s *b, const uint8_t *active, hipStream_t s);
+pl_status batch_capture(pl_batch_s *b, const uint8_t *active, hipStream_t s);
 pl_status batch_replay(const pl_batch_s *b, hipStream_t s);
 void batch_destroy(pl_batch_s *b);
 

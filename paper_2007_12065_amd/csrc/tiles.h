@@ -239,7 +239,8 @@ __device__ __forceinline__ void lap_tile(const float *__restrict__ src, float *_
                 float ws = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
                 // 3x3: fully unrolled; larger windows: one row of the window
                 // per iteration, so only that row's neighbours are live
-#pragma unroll(R == 1 ? 3 : 1)
+                constexpr int kRowUnroll = R == 1 ? 3 : 1;
+#pragma unroll kRowUnroll
                 for (int dy = -R; dy <= R; ++dy) {
 #pragma unroll
                     for (int dx = -R; dx <= R; ++dx) {

@@ -107,6 +107,37 @@ def test_batch_graph_replay(pl):
     b.close()
 
 
+def test_batch_active_subset(pl):
+    # frames left out of a run keep their previous outputs; the others are
+    # recomputed exactly
+    import torch
+    specs = mixed_specs()
+    b = pl.Batch(specs, torch.float32)
+    b.run()
+    torch.cuda.synchronize()
+    want = [{k: (v.clone() if v is not None else None) for k, v in o.items()} for o in b.outputs]
+    mask = torch.tensor([i % 2 for i in range(len(specs))], dtype=torch.uint8, device="cuda:0")
+    for o in b.outputs:
+        o["normals_T"].fill_(-3)
+        o["points"].fill_(-3)
+    b.run(mask)
+    torch.cuda.synchronize()
+    for i, o in enumerate(b.outputs):
+        if i % 2:
+            assert_frame_equal(o, want[i], f"active frame {i}")
+        else:
+            assert bool((o["normals_T"] == -3).all()) and bool((o["points"] == -3).all())
+    # a graph captured with the mask follows the mask's contents at replay
+    b.capture(mask)
+    mask.fill_(1)
+    torch.cuda.synchronize()
+    b.replay()
+    torch.cuda.synchronize()
+    for i, o in enumerate(b.outputs):
+        assert_frame_equal(o, want[i], f"replayed frame {i}")
+    b.close()
+
+
 def test_batch_runs_repeatedly(pl):
     import torch
     specs = mixed_specs()[5:]
