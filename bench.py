@@ -38,6 +38,10 @@ def parse():
                     help="bound on the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also measure the 64-frame mixed batch (0 = skip)")
+    ap.add_argument("--serving-seconds", type=float, default=6.0,
+                    help="measured seconds of the Poisson serving run after 1 s warm-up (0 = skip)")
     return ap.parse_args()
 
 
@@ -93,6 +97,100 @@ def cpu_baseline(frames_np, k, seconds):
                       f"{threads} OpenMP threads), {el:.1f} s"}
 
 
+def angle_stats(got, ref):
+    import numpy as np
+    g = np.asarray(got, dtype=np.float64).reshape(-1, 3)
+    r = np.asarray(ref, dtype=np.float64).reshape(-1, 3)
+    ok = ~np.isnan(r).any(-1)
+    a = np.arctan2(np.linalg.norm(np.cross(g[ok], r[ok]), axis=-1), np.sum(g[ok] * r[ok], axis=-1))
+    return {"p50": float(np.median(a)), "p99": float(np.percentile(a, 99)), "max": float(a.max())}
+
+
+def batched_bench(reps=20):
+    """The 64-frame mix (16x 120x160, 24x 480x640, 16x 64x1024, 8x 128x2048):
+    plain per-frame float32 path vs one batch plan (graph replay), float32
+    and float16 normals.  Angular error of a sample against the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    import paper_2007_12065_amd as pl
+    from synth import KINDS, batch_mix, make_frame
+    dev = torch.device("cuda:0")
+    host, specs = [], []
+    for kind, seed in batch_mix():
+        k = KINDS[kind]
+        f = make_frame(kind, seed)
+        host.append((f, k))
+        specs.append(dict(pts=torch.from_numpy(f).to(dev), kernel_lap=k.kernel_lap, lam=k.lam,
+                          iters_lap=k.iters_lap, kernel_bil=k.kernel_bil, sigma_length=k.sigma_length,
+                          sigma_angle=k.sigma_angle, iters_bil=k.iters_bil))
+    T = sum(2 * (f.shape[0] - 1) * (f.shape[1] - 1) for f, _ in host)
+    plans = [pl.FramePlan(f.shape[0], f.shape[1], k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
+                          k.sigma_length, k.sigma_angle, k.iters_bil, torch.float32, dev)
+             for f, k in host]
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize(dev)
+        return (time.perf_counter() - t0) / reps
+
+    def plain():
+        for p, sp in zip(plans, specs):
+            p.run(sp["pts"])
+    t_plain = timed(plain)
+    out = {"frames": len(specs), "triangles": T,
+           "plain_f32": {"ms": round(t_plain * 1e3, 3), "triangles_per_s": T / t_plain}}
+    sample = [0, 16, 40, 56]          # one frame of each kind for the error report
+    for name, dt in (("batched_f32", torch.float32), ("batched_f16", torch.float16)):
+        b = pl.Batch(specs, dt)
+        b.run()
+        b.capture()
+        t = timed(b.replay)
+        errs = []
+        import oracle
+        for i in sample:
+            f, k = host[i]
+            ref = oracle.pipeline(f, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil, k.sigma_length,
+                                  k.sigma_angle, k.iters_bil, threads=min(16, os.cpu_count() or 1))
+            n = int(b.outputs[i]["n_tri"].item())
+            errs.append(angle_stats(b.outputs[i]["normals_T"][:n].float().cpu().numpy(), ref["normals_T"]))
+        out[name] = {"ms": round(t * 1e3, 3), "triangles_per_s": T / t, "vs_plain_f32": t_plain / t,
+                     "angle_err_rad_vs_fp64": {kk: max(e[kk] for e in errs) if kk == "max" else
+                                               float(np.median([e[kk] for e in errs])) for kk in errs[0]}}
+        b.close()
+    return out
+
+
+def serving_bench(seconds):
+    """Poisson arrivals at 1500 frames/s, sizes 40% 480x640, 30% 64x1024,
+    20% 128x2048, 10% 120x160, 16 GB budget, float16 normals, graph replay;
+    the same stream through the plain per-frame float32 path."""
+    import torch
+
+    from paper_2007_12065_amd.serve import FrameClass, PlainServer, Server
+    from synth import KINDS, make_frame, poisson_arrivals
+    classes = {k: FrameClass(k, v.M, v.N, v.kernel_lap, v.lam, v.iters_lap, v.kernel_bil,
+                             v.sigma_length, v.sigma_angle, v.iters_bil)
+               for k, v in KINDS.items()}
+    pool_per_kind = 4
+    host = {k: [make_frame(k, 4000 + 100 * j + i) for i in range(pool_per_kind)]
+            for j, k in enumerate(classes)}
+    warm = 1.0
+    times, kinds = poisson_arrivals(1500.0, warm + seconds, seed=4000)
+    srv = Server(classes, host, 16 << 30, torch.float16)
+    srv.presize({"rgbd": 16, "lidar": 12, "lidar128": 8, "rgbd_small": 4})
+    batched = srv.serve(times, kinds, warmup_s=warm)
+    plain = PlainServer(classes, host).serve(times, kinds, warmup_s=warm)
+    return {"rate_hz": 1500.0, "measured_s": seconds, "continuous_batching_f16": batched,
+            "plain_f32": plain,
+            "throughput_ratio": batched.get("triangles_per_s", 0) / max(plain.get("triangles_per_s", 1), 1)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -120,6 +218,12 @@ def main():
              for _ in range(sets)]
     stream = torch.cuda.current_stream(dev)
     s = pl._stream(dev)
+    # tile shapes and sweep fusion for the window sizes in use (3x3 on the
+    # 480x640 frames, 5x5 on the LiDAR frames of the batched and served mixes)
+    from paper_2007_12065_amd import tune
+    lidar = torch.from_numpy(make_frame("lidar128", 7)).to(dev)
+    tuning = tune.autotune([(frames[0], k.kernel_lap, k.iters_lap, k.kernel_bil, k.iters_bil),
+                            (lidar, 5, 4, 5, 3)], cache_path=None, reps=20)
     print(f"[bench] {sets} frame sets ready; warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
 
@@ -183,11 +287,14 @@ def main():
                  "hbm_frac": round(byte_frac, 4), "traffic": None})
 
     if args.copy_probe:
-        # plain copy kernel of known size for counter calibration: 12 P bytes
-        # read and written (pl_laplacian with zero sweeps is a copy)
-        for p, x in zip(plans[:4], frames[:4]):
-            pl.pl_laplacian(x, k.kernel_lap, k.lam, 0, out=p.points)
+        # plain copy of known size for counter calibration: 256 MiB read and
+        # 256 MiB written by one device-to-device copy kernel, larger than L2
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b_ = torch.empty_like(a)
         torch.cuda.synchronize(dev)
+        b_.copy_(a)
+        torch.cuda.synchronize(dev)
+        del a, b_
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "triangles/s", "n_gpus": 1,
@@ -204,8 +311,17 @@ def main():
         "hbm_effective_gbs": round(sum(specs[c]["bytes"] * specs[c]["launches"] for c in calls)
                                    / (elapsed / K) / 1e9, 1),
         "roofline": roof,
+        "tuning": {name: {"tile": list(r["best"][:2]), "fuse": r["best"][2]}
+                   for name, r in tuning.items()},
     }
+    if args.batched:
+        print("[bench] batched 64-frame mix", file=sys.stderr, flush=True)
+        out["batched"] = batched_bench()
+    if args.serving_seconds > 0:
+        print("[bench] serving stream", file=sys.stderr, flush=True)
+        out["serving"] = serving_bench(args.serving_seconds)
     if args.cpu_seconds > 0:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(frames_np, k, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,136 @@
+"""Autotuner for tile shapes and sweep fusion.
+
+For each stage (Laplacian, bilateral) and window size, candidate
+(tile_rows, tile_cols, fuse) shapes are timed with HIP events on a
+representative frame through the single-frame entry points, the fastest is
+installed with pl_tune_set, and the choice is cached in a JSON file keyed by
+the GPU architecture, stage, window size and frame size.  float32 results do
+not depend on the choice (the arithmetic of every output is the same for
+every tiling), so tuning only moves time.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+import paper_2007_12065_amd as pl
+
+LAP_CANDIDATES = {
+    3: [(16, 32, 4), (16, 64, 4), (32, 32, 4), (16, 16, 4), (8, 64, 2), (16, 32, 2), (8, 32, 1), (4, 64, 1)],
+    5: [(8, 32, 1), (4, 64, 1), (16, 32, 1), (8, 64, 2), (16, 32, 2), (16, 16, 2)],
+}
+BIL_CANDIDATES = {
+    3: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (8, 32, 2), (4, 32, 1)],
+    5: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (4, 32, 1)],
+}
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pl_tune.json")
+
+
+def arch_name(device=None) -> str:
+    p = torch.cuda.get_device_properties(device or 0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def _time(fn, reps: int) -> float:
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps * 1e3      # microseconds per call
+
+
+def tune_stage(stage: int, kernel: int, pts: torch.Tensor, iterations: int, reps: int = 30,
+               candidates=None) -> dict:
+    """Time each candidate shape for one stage and window size on `pts`
+    (a [M, N, 3] device frame); install and return the fastest."""
+    cands = candidates or (LAP_CANDIDATES if stage == pl.PL_STAGE_LAPLACIAN else BIL_CANDIDATES).get(
+        kernel, [(8, 32, 1)])
+    before = pl.pl_tune_get(stage, kernel)
+    if stage == pl.PL_STAGE_BILATERAL:
+        n, c = pl.pl_tri_normals(pts)
+        out = torch.empty_like(n)
+        call = lambda: pl.pl_bilateral(n, c, kernel, 0.1, 0.1, iterations, out=out)
+    else:
+        out = torch.empty_like(pts)
+        call = lambda: pl.pl_laplacian(pts, kernel, 1.0, iterations, out=out)
+    times = {}
+    for cfg in cands:
+        try:
+            pl.pl_tune_set(stage, kernel, *cfg)
+        except pl.PLError:
+            continue
+        times[cfg] = _time(call, reps)
+    if not times:
+        pl.pl_tune_set(stage, kernel, *before)
+        return {"best": before, "times_us": {}}
+    best = min(times, key=times.get)
+    pl.pl_tune_set(stage, kernel, *best)
+    return {"best": best, "times_us": {f"{a}x{b}/{f}": round(t, 2) for (a, b, f), t in times.items()},
+            "previous": before}
+
+
+def autotune(workloads, cache_path: str | None = DEFAULT_CACHE, reps: int = 30) -> dict:
+    """Tune every (stage, window size) the workloads use.  `workloads` is a
+    list of (pts device tensor, kernel_lap, iters_lap, kernel_bil, iters_bil);
+    the largest frame of each window size is the representative.  Results
+    are installed and, with a cache path, merged into the JSON cache."""
+    arch = arch_name()
+    reps_by = {}
+    for pts, kl, il, kb, ib in workloads:
+        for stage, k, it in ((pl.PL_STAGE_LAPLACIAN, kl, il), (pl.PL_STAGE_BILATERAL, kb, ib)):
+            key = (stage, k)
+            size = int(pts.shape[0]) * int(pts.shape[1])
+            if key not in reps_by or size > reps_by[key][1]:
+                reps_by[key] = (pts, size, max(it, 1))
+    report = {}
+    for (stage, k), (pts, size, it) in sorted(reps_by.items(), key=lambda x: x[0]):
+        r = tune_stage(stage, k, pts, it, reps)
+        name = ("laplacian" if stage == pl.PL_STAGE_LAPLACIAN else "bilateral") + f"_k{k}"
+        report[name] = dict(r, frame=list(pts.shape[:2]))
+    if cache_path:
+        save_cache(cache_path, arch, report)
+    return report
+
+
+def save_cache(path: str, arch: str, report: dict) -> None:
+    data = {}
+    if os.path.exists(path):
+        try:
+            data = json.load(open(path))
+        except (OSError, ValueError):
+            data = {}
+    data.setdefault(arch, {})
+    for name, r in report.items():
+        data[arch][name] = {"best": list(r["best"]), "frame": r.get("frame")}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> int:
+    """Install cached shapes for the current architecture; returns how many."""
+    if not os.path.exists(path):
+        return 0
+    try:
+        data = json.load(open(path)).get(arch_name(), {})
+    except (OSError, ValueError):
+        return 0
+    n = 0
+    for name, entry in data.items():
+        stage_name, k = name.rsplit("_k", 1)
+        stage = pl.PL_STAGE_LAPLACIAN if stage_name == "laplacian" else pl.PL_STAGE_BILATERAL
+        try:
+            pl.pl_tune_set(stage, int(k), *entry["best"])
+            n += 1
+        except (pl.PLError, ValueError, TypeError):
+            continue
+    return n

@@ -186,3 +186,24 @@ def test_batch_overlap_rejected(pl):
     assert pl._lib.pl_batch_workspace(arr, 2, 0) == 0
     assert "overlap" in pl._lib.pl_last_error().decode()
     b.close()
+
+
+def test_autotune_installs_a_candidate_and_keeps_results(pl, tmp_path):
+    import torch
+    from paper_2007_12065_amd import tune
+    pts = dev_t(make_frame("rgbd_small", 3))
+    ref = host(pl.pl_laplacian(pts, 3, 1.0, 3)).copy()
+    saved = [pl.pl_tune_get(0, 3), pl.pl_tune_get(1, 3)]
+    try:
+        cache = str(tmp_path / "tune.json")
+        rep = tune.autotune([(pts, 3, 3, 3, 2)], cache_path=cache, reps=3)
+        assert tuple(rep["laplacian_k3"]["best"]) in tune.LAP_CANDIDATES[3]
+        assert tuple(rep["bilateral_k3"]["best"]) in tune.BIL_CANDIDATES[3]
+        assert pl.pl_tune_get(0, 3) == tuple(rep["laplacian_k3"]["best"])
+        assert np.array_equal(host(pl.pl_laplacian(pts, 3, 1.0, 3)).view(np.uint8), ref.view(np.uint8))
+        pl.pl_tune_set(0, 3, *saved[0])
+        assert tune.load_cache(cache) == 2
+        assert pl.pl_tune_get(0, 3) == tuple(rep["laplacian_k3"]["best"])
+    finally:
+        pl.pl_tune_set(0, 3, *saved[0])
+        pl.pl_tune_set(1, 3, *saved[1])
