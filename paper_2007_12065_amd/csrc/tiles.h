@@ -81,21 +81,27 @@ __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, in
     __syncthreads();                 // LDS is reused by the next call in a persistent loop
 }
 
-// Block-wide exclusive scan of a packed triple of 10-bit counters (a chunk of
-// kTileBlock quads holds at most 512 triangles per row).
-__device__ __forceinline__ int mesh_block_scan(int x, int *total) {
-    __shared__ int wsum[kTileBlock / kWave];
+// Block-wide exclusive scan of three counters packed in 21-bit fields (a
+// pass of 1024 quads holds at most 2048 triangles per row).
+__device__ __forceinline__ unsigned long long mesh_block_scan(unsigned long long x,
+                                                             unsigned long long *total) {
+    __shared__ unsigned long long wsum[kTileBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    const int incl = wave_inclusive_scan(x);
+    unsigned long long incl = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const unsigned long long y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
     __syncthreads();
     if (lane == kWave - 1) wsum[wid] = incl;
     __syncthreads();
-    int before = 0, all = 0;
+    unsigned long long before = 0, all = 0;
 #pragma unroll
     for (int w = 0; w < kTileBlock / kWave; ++w) {
-        const int t = wsum[w];
-        before += w < wid ? t : 0;
+        const unsigned long long t = wsum[w];
+        before += w < wid ? t : 0ull;
         all += t;
     }
     *total = all;
@@ -104,9 +110,15 @@ __device__ __forceinline__ int mesh_block_scan(int x, int *total) {
 
 __device__ __forceinline__ int popc2(int c) { return (c & 1) + ((c >> 1) & 1); }
 
+constexpr int kEmitQ = 4;                        // consecutive quads per thread
+constexpr int kEmitChunk = kEmitQ * kTileBlock;  // quads per pass
+constexpr unsigned long long kField = (1ull << 21) - 1;
+
 // T_map, T and HE of quad row u.  The row's place in T is the sum of the
 // counts of the rows above it; the codes of rows u-1 and u+1 give the
-// indices of the Top and Bottom twins.  The last row writes |T|.
+// indices of the Top and Bottom twins.  Each thread owns four consecutive
+// quads of a 1024-quad pass (one block scan per pass, serial prefix inside
+// the thread).  The last row writes |T|.
 __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
                                               const int *__restrict__ row_count, int Mq, int N,
                                               int u, int32_t *__restrict__ tri_map,
@@ -130,54 +142,74 @@ __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
     const int basep = base0 + row_count[u];
     if (u == Mq - 1 && threadIdx.x == 0) *n_tri = basep;
     int carry0 = 0, carrym = 0, carryp = 0;
-    for (int v0 = 0; v0 < Nq; v0 += kTileBlock) {
-        const int v = v0 + threadIdx.x;
-        const bool in = v < Nq;
-        const int c0 = in ? cr0[v] : 0;
-        const int cm = (in && u > 0) ? crm[v] : 0;
-        const int cp = (in && u + 1 < Mq) ? crp[v] : 0;
-        const int n0 = popc2(c0);
-        int total;
-        const int ex = mesh_block_scan(n0 | (popc2(cm) << 10) | (popc2(cp) << 20), &total);
-        const int p0 = ex & 1023, pm = (ex >> 10) & 1023, pp = (ex >> 20) & 1023;
-        if (in) {
-            const int f = c0 & 1, s = (c0 >> 1) & 1;
-            const int rank0 = base0 + carry0 + p0;       // index of (u,v,0) if valid
-            const int rF = f ? rank0 : -1;
-            const int rS = s ? rank0 + f : -1;
-            const size_t q = (size_t)u * Nq + v;
-            *reinterpret_cast<int2 *>(tri_map + 2 * q) = make_int2(rF, rS);
-            const int i1 = u * N + v, i2 = i1 + 1, i3 = i1 + N + 1, i4 = i1 + N;
-            if (f && rF < cap) {
-                tris[3 * rF + 0] = i3; tris[3 * rF + 1] = i2; tris[3 * rF + 2] = i1;
-            }
-            if (s && rS < cap) {
-                tris[3 * rS + 0] = i1; tris[3 * rS + 1] = i4; tris[3 * rS + 2] = i3;
-            }
-            if (he) {
-                // Right = (u, v+1, 1), Top = (u-1, v, 1), Left = (u, v-1, 0),
-                // Bottom = (u+1, v, 0); indices from the prefix sums.
-                const int cr = v + 1 < Nq ? cr0[v + 1] : 0;
-                const int cl = v > 0 ? cr0[v - 1] : 0;
-                const int right = (cr & 2) ? rank0 + n0 + (cr & 1) : -1;
-                const int left = (cl & 1) ? rank0 - popc2(cl) : -1;
-                const int top = (cm & 2) ? basem + carrym + pm + (cm & 1) : -1;
-                const int bottom = (cp & 1) ? basep + carryp + pp : -1;
+    for (int v0 = 0; v0 < Nq; v0 += kEmitChunk) {
+        const int vb = v0 + kEmitQ * threadIdx.x;
+        int c0[kEmitQ], cm[kEmitQ], cp[kEmitQ];
+        int t0 = 0, tm = 0, tp = 0;
+#pragma unroll
+        for (int j = 0; j < kEmitQ; ++j) {
+            const int v = vb + j;
+            const bool in = v < Nq;
+            c0[j] = in ? cr0[v] : 0;
+            cm[j] = (in && u > 0) ? crm[v] : 0;
+            cp[j] = (in && u + 1 < Mq) ? crp[v] : 0;
+            t0 += popc2(c0[j]);
+            tm += popc2(cm[j]);
+            tp += popc2(cp[j]);
+        }
+        const int cl_first = (vb > 0 && vb - 1 < Nq) ? cr0[vb - 1] : 0;
+        const int cr_last = vb + kEmitQ < Nq ? cr0[vb + kEmitQ] : 0;
+        unsigned long long total;
+        const unsigned long long ex = mesh_block_scan(
+            (unsigned long long)t0 | ((unsigned long long)tm << 21) | ((unsigned long long)tp << 42),
+            &total);
+        int r0 = base0 + carry0 + (int)(ex & kField);        // index of the next triangle of row u
+        int rm = basem + carrym + (int)((ex >> 21) & kField);
+        int rp = basep + carryp + (int)((ex >> 42) & kField);
+#pragma unroll
+        for (int j = 0; j < kEmitQ; ++j) {
+            const int v = vb + j;
+            if (v < Nq) {
+                const int f = c0[j] & 1, s = (c0[j] >> 1) & 1;
+                const int rF = f ? r0 : -1;
+                const int rS = s ? r0 + f : -1;
+                const size_t q = (size_t)u * Nq + v;
+                *reinterpret_cast<int2 *>(tri_map + 2 * q) = make_int2(rF, rS);
+                const int i1 = u * N + v, i2 = i1 + 1, i3 = i1 + N + 1, i4 = i1 + N;
                 if (f && rF < cap) {
-                    he[3 * rF + 0] = right >= 0 ? 3 * right : -1;
-                    he[3 * rF + 1] = top >= 0 ? 3 * top + 1 : -1;
-                    he[3 * rF + 2] = s ? 3 * rS + 2 : -1;
+                    tris[3 * rF + 0] = i3; tris[3 * rF + 1] = i2; tris[3 * rF + 2] = i1;
                 }
                 if (s && rS < cap) {
-                    he[3 * rS + 0] = left >= 0 ? 3 * left : -1;
-                    he[3 * rS + 1] = bottom >= 0 ? 3 * bottom + 1 : -1;
-                    he[3 * rS + 2] = f ? 3 * rF + 2 : -1;
+                    tris[3 * rS + 0] = i1; tris[3 * rS + 1] = i4; tris[3 * rS + 2] = i3;
+                }
+                if (he) {
+                    // Right = (u, v+1, 1), Top = (u-1, v, 1), Left = (u, v-1, 0),
+                    // Bottom = (u+1, v, 0); indices from the running prefix sums.
+                    const int cr = j + 1 < kEmitQ ? c0[j + 1] : cr_last;
+                    const int cl = j > 0 ? c0[j - 1] : cl_first;
+                    const int right = (cr & 2) ? r0 + f + s + (cr & 1) : -1;
+                    const int left = (cl & 1) ? r0 - popc2(cl) : -1;
+                    const int top = (cm[j] & 2) ? rm + (cm[j] & 1) : -1;
+                    const int bottom = (cp[j] & 1) ? rp : -1;
+                    if (f && rF < cap) {
+                        he[3 * rF + 0] = right >= 0 ? 3 * right : -1;
+                        he[3 * rF + 1] = top >= 0 ? 3 * top + 1 : -1;
+                        he[3 * rF + 2] = s ? 3 * rS + 2 : -1;
+                    }
+                    if (s && rS < cap) {
+                        he[3 * rS + 0] = left >= 0 ? 3 * left : -1;
+                        he[3 * rS + 1] = bottom >= 0 ? 3 * bottom + 1 : -1;
+                        he[3 * rS + 2] = f ? 3 * rF + 2 : -1;
+                    }
                 }
             }
+            r0 += popc2(c0[j]);
+            rm += popc2(cm[j]);
+            rp += popc2(cp[j]);
         }
-        carry0 += total & 1023;
-        carrym += (total >> 10) & 1023;
-        carryp += (total >> 20) & 1023;
+        carry0 += (int)(total & kField);
+        carrym += (int)((total >> 21) & kField);
+        carryp += (int)((total >> 42) & kField);
     }
     __syncthreads();
 }

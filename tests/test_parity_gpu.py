@@ -85,7 +85,8 @@ def check_normals(gpu, ref, tol=NORMAL_ATOL):
 # ---------------------------------------------------------------- mesh
 
 MESH_GRIDS = [(2, 2, 0.0), (2, 3, 0.2), (3, 2, 0.2), (7, 7, 0.15), (5, 300, 0.1),
-              (300, 5, 0.1), (4, 600, 0.3), (33, 260, 0.05), (2, 1000, 0.5), (17, 513, 0.0)]
+              (300, 5, 0.1), (4, 600, 0.3), (33, 260, 0.05), (2, 1000, 0.5), (17, 513, 0.0),
+              (3, 1025, 0.1), (2, 1026, 0.0), (4, 2100, 0.2), (3, 3075, 0.05)]
 
 
 def mesh_compare(pl, pts, cap=None):
