@@ -53,25 +53,56 @@ def kernel_specs(k, M, N, n_tri_mean):
     formulas per output: Laplacian 17 per neighbour (difference 3, squared
     norm 5, inverse root 1, weight sum 1, weighted sum 6, + update), bilateral
     26 per neighbour pair (two squared differences 16, exponent 3, exp 1,
-    weighted sum 6)."""
+    weighted sum 6).  A launch runs F fused sweeps (the installed tuning)."""
+    import paper_2007_12065_amd as pl
     P = M * N
     T = 2 * (M - 1) * (N - 1)
     nb_lap = k.kernel_lap ** 2 - 1
     nb_bil = 2 * (k.kernel_bil ** 2 - 1)
-    from paper_2007_12065_amd import lap_fused_sweeps
-    F = lap_fused_sweeps(k.kernel_lap)
-    lap_launches = -(-k.iters_lap // F)
+    Fl = pl.lap_fused_sweeps(k.kernel_lap)
+    lap_launches = -(-k.iters_lap // Fl)
+    Fb = pl.pl_tune_get(pl.PL_STAGE_BILATERAL, k.kernel_bil)[2]
+    bil_launches = -(-k.iters_bil // Fb)
     return {
         "pl_laplacian": dict(kernel="k_laplacian", launches=lap_launches,
                              bytes=24 * P, flops=P * (k.iters_lap / lap_launches) * (17 * nb_lap + 7)),
         "pl_tri_normals": dict(kernel="k_tri_normals", launches=1, bytes=12 * P + 24 * T,
                                flops=T * 30),
-        "pl_bilateral": dict(kernel="k_bilateral", launches=k.iters_bil,
-                             bytes=36 * T + (4 * T + 12 * n_tri_mean) / k.iters_bil,
-                             flops=T * (26 * nb_bil + 10)),
-        "pl_mesh_opc": dict(kernel="k_mesh_*", launches=3,
-                            bytes=(12 * P + T // 2 + 4 * T + 24 * n_tri_mean) / 3, flops=0),
+        "pl_bilateral": dict(kernel="k_bilateral", launches=bil_launches,
+                             bytes=36 * T + (4 * T + 12 * n_tri_mean) / bil_launches,
+                             flops=T * (k.iters_bil / bil_launches) * (26 * nb_bil + 10)),
+        "pl_mesh_opc": dict(kernel="k_mesh_*", launches=2,
+                            bytes=(12 * P + T // 2 + 4 * T + 24 * n_tri_mean) / 2, flops=0),
     }
+
+
+def kernel_source_digest(files=("paper_2007_12065_amd/csrc/tiles.h", "paper_2007_12065_amd/csrc/common.h",
+                                "paper_2007_12065_amd/csrc/bilateral.hip",
+                                "paper_2007_12065_amd/csrc/laplacian.hip",
+                                "paper_2007_12065_amd/csrc/normals.hip")):
+    """SHA-256 over the sources the single-frame filter kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, launches_per_call):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy of known size), or
+    None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    r = rec.get(kernel)
+    if not r or r.get("source_digest") != kernel_source_digest():
+        return None
+    return r.get("bytes_per_launch")
 
 
 def cpu_baseline(frames_np, k, seconds):
@@ -284,7 +315,10 @@ def main():
                 "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
     roof.update({"kernel": sp["kernel"], "launch_us": round(launch_us[dom], 2),
                  "bytes_per_launch": int(sp["bytes"]), "flops_per_launch": int(sp["flops"]),
-                 "hbm_frac": round(byte_frac, 4), "traffic": None})
+                 "hbm_frac": round(byte_frac, 4),
+                 "traffic": measured_traffic(sp["kernel"], sp["launches"]),
+                 "peak_note": "published fp32 vector peak (packed); this code is built without "
+                              "packed FP32, whose ceiling is half (78.6 TFLOP/s)"})
 
     if args.copy_probe:
         # plain copy of known size for counter calibration: 256 MiB read and

@@ -194,7 +194,8 @@ pl_status pl_tune_set(pl_stage stage, int32_t kernel, int32_t tile_rows, int32_t
 /*
  * Batched path: a set of frames of any sizes and filter settings through the
  * whole pipeline (mesh, Laplacian, normals, bilateral, gather) with one
- * persistent launch per stage over a tile work-queue.  Each frame's outputs
+ * launch per stage (per sweep pass for the filters) over a tile queue built
+ * on the device from the active frames.  Each frame's outputs
  * are exactly those of the single-frame calls with the same parameters:
  *   pl_mesh_opc(pts, M, N, tri_valid, tri_map, triangles, halfedges,
  *               cap = 2(M-1)(N-1), n_tri)

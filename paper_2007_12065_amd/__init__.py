@@ -316,8 +316,7 @@ def pl_tune_set(stage: int, kernel: int, tile_rows: int, tile_cols: int, fuse: i
 
 
 class Batch:
-    """A batch of frames through the whole path with one persistent launch
-    per stage (pl_batch_* in include/pl.h).
+    """A batch of frames through the whole path with one launch per stage (pl_batch_* in include/pl.h).
 
     `frames` is a list of dicts with keys pts ([M, N, 3] float32 device
     tensor), kernel_lap, lam, iters_lap, kernel_bil, sigma_length,

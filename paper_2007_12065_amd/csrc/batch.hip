@@ -1,17 +1,17 @@
 // Batched path: many frames of different sizes and filter settings through
-// the whole pipeline with one persistent launch per stage.
+// the whole pipeline with one launch per stage (per sweep pass for the
+// filters), whatever the number of frames.
 //
 // Plan (pl_batch_create, host): validates every frame, lays out a workspace
 // holding one descriptor per frame, the per-pass source/destination tables
 // of the multi-sweep stages, each stage's per-frame tile counts and the
 // per-frame scratch (validity codes, row counts, ping-pong buffers), uploads
-// the tables once and picks a resident grid per kernel from the occupancy
-// API.
+// the tables once and sizes each launch for all frames active.
 //
 // Run (pl_batch_run, device only, graph-capturable), over the frames whose
 // entry in a device-side activity mask is non-zero:
-//   k_batch_prepare    per stage: prefix sums of the active frames' tile
-//                      counts, XCD segment bounds, zeroed queue counters
+//   k_batch_prepare    one workgroup per stage: prefix sums of the active
+//                      frames' tile counts (the stage's tile queue)
 //   k_batch_mesh_count tiles = (frame, quad row)        -> codes, row counts
 //   k_batch_mesh_emit  tiles = (frame, quad row)        -> T_map, T, HE, |T|
 //   k_batch_laplacian  one launch per sweep pass, tiles = (frame, point tile)
@@ -21,19 +21,22 @@
 // Every tile runs the same device body as the single-frame kernels
 // (tiles.h), so each frame's outputs equal its single-frame results.
 //
-// Work queue.  A stage's tiles are numbered frame by frame (active frames
-// only) and the range is cut into eight contiguous segments, one per XCD:
-// workgroup b starts on segment b mod 8 (the XCD it was dispatched to), so
-// neighbouring tiles, which share halo lines, meet in the same L2.  A
-// workgroup pops tiles with an atomic counter, maps the number back to
-// (frame, tile) by binary search over the prefix sums, and once its segment
-// is empty steals from the others in turn; each counter is bumped at most
-// grid-size times past its end, so every workgroup leaves the loop after at
-// most eight empty pops.
+// Tile queue.  A stage's tiles are numbered frame by frame over the active
+// frames only; the launch has one workgroup per tile of the whole batch and
+// the hardware dispatcher hands them out as CUs free up.  Workgroup b takes
+// tile number xcd_remap(b): the dispatcher deals workgroups round-robin over
+// the eight XCDs, so each XCD receives one contiguous eighth of the numbers
+// and neighbouring tiles, which share halo lines, meet in the same L2.  The
+// number is mapped back to (frame, tile) by binary search over the prefix
+// sums staged in LDS; numbers past the active total exit at once.  (A
+// persistent grid popping tiles from per-XCD atomic counters was measured
+// slower: contended device-scope atomics put a floor of several hundred
+// microseconds under every stage of a 64-frame batch.)
 #include "tiles.h"
 #include "tuning.h"
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -41,8 +44,6 @@
 namespace pl {
 
 namespace {
-
-constexpr int kQueues = kNumXcd;
 
 struct BFrame {
     const float *pts;
@@ -70,124 +71,91 @@ struct PassFrame {                 // one frame's part of one sweep pass
 struct QueueDev {                  // one stage's tile queue, in the workspace
     const int *count;              // [n] tiles of each frame in this stage
     int *start;                    // [n + 1] prefix over active frames (per run)
-    int *seg;                      // [kQueues + 1] segment bounds (per run)
-    int *counter;                  // [kQueues] (per run)
 };
 
-// Per run, for every queue: prefix sums over the active frames, equal
-// segments, zeroed counters.  One workgroup.
+// Per run, for every queue (one workgroup each): exclusive prefix sums of
+// the active frames' tile counts, the total in start[n].
 __global__ __launch_bounds__(kTileBlock) void k_batch_prepare(const QueueDev *__restrict__ qs,
-                                                             int nq, int n,
+                                                             int n,
                                                              const uint8_t *__restrict__ active) {
     __shared__ int wsum[kTileBlock / kWave];
     __shared__ int carry_s;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int k = 0; k < nq; ++k) {
-        const QueueDev Q = qs[k];
-        if (threadIdx.x == 0) carry_s = 0;
+    const QueueDev Q = qs[blockIdx.x];
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += kTileBlock) {
+        const int i = base + threadIdx.x;
+        const int x = (i < n && active[i]) ? Q.count[i] : 0;
+        const int incl = wave_inclusive_scan(x);
+        if (lane == kWave - 1) wsum[wid] = incl;
         __syncthreads();
-        for (int base = 0; base < n; base += kTileBlock) {
-            const int i = base + threadIdx.x;
-            const int x = (i < n && active[i]) ? Q.count[i] : 0;
-            const int incl = wave_inclusive_scan(x);
-            if (lane == kWave - 1) wsum[wid] = incl;
-            __syncthreads();
-            int before = 0, all = 0;
+        int before = 0, all = 0;
 #pragma unroll
-            for (int w = 0; w < kTileBlock / kWave; ++w) {
-                before += w < wid ? wsum[w] : 0;
-                all += wsum[w];
-            }
-            const int carry = carry_s;
-            if (i < n) Q.start[i] = carry + before + incl - x;
-            __syncthreads();
-            if (threadIdx.x == 0) carry_s = carry + all;
-            __syncthreads();
+        for (int w = 0; w < kTileBlock / kWave; ++w) {
+            before += w < wid ? wsum[w] : 0;
+            all += wsum[w];
         }
-        const int total = carry_s;
-        if (threadIdx.x == 0) Q.start[n] = total;
-        if (threadIdx.x <= kQueues)
-            Q.seg[threadIdx.x] = (int)(((long long)total * threadIdx.x) / kQueues);
-        if (threadIdx.x < kQueues) Q.counter[threadIdx.x] = 0;
+        const int carry = carry_s;
+        if (i < n) Q.start[i] = carry + before + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + all;
         __syncthreads();
     }
+    if (threadIdx.x == 0) Q.start[n] = carry_s;
 }
 
-// Pop the next tile for this workgroup: false when every segment is
-// exhausted.  `q` is the segment being drained (starts at blockIdx mod 8).
-__device__ __forceinline__ bool pop_tile(const QueueDev &Q, int n, int &q, int &tries,
-                                         int2 &tile) {
-    __shared__ int2 s_tile;
-    __shared__ int s_ok;
-    while (tries < kQueues) {
-        if (threadIdx.x == 0) {
-            const int i = atomicAdd(&Q.counter[q], 1);
-            const int lo_g = Q.seg[q], hi_g = Q.seg[q + 1];
-            s_ok = lo_g + i < hi_g;
-            if (s_ok) {
-                const int g = lo_g + i;
-                int lo = 0, hi = n;            // last frame with start <= g
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (Q.start[mid] <= g) lo = mid; else hi = mid;
-                }
-                s_tile = make_int2(lo, g - Q.start[lo]);
-            }
-        }
-        __syncthreads();
-        const int ok = s_ok;
-        const int2 t = s_tile;
-        __syncthreads();
-        if (ok) {
-            tile = t;
-            return true;
-        }
-        q = (q + 1) % kQueues;
-        ++tries;
+constexpr int kLdsFrames = 256;    // prefix sums staged in LDS up to this many frames
+
+// This workgroup's tile: false when its number is past the active total
+// (the whole workgroup then exits).
+__device__ __forceinline__ bool queue_tile(const QueueDev &Q, int n, int *s_start, int2 &t) {
+    for (int i = threadIdx.x; i <= n && i <= kLdsFrames; i += kTileBlock) s_start[i] = Q.start[i];
+    __syncthreads();
+    const int *start = n <= kLdsFrames ? s_start : Q.start;
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g >= start[n]) return false;
+    int lo = 0, hi = n;                       // last frame with start <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= g) lo = mid; else hi = mid;
     }
-    return false;
+    // uniform across the workgroup: frame descriptors then load into SGPRs
+    t = make_int2(__builtin_amdgcn_readfirstlane(lo), __builtin_amdgcn_readfirstlane(g - start[lo]));
+    return true;
 }
+
+#define PL_QUEUE_TILE(Q, n, t)                                              \
+    __shared__ int s_start_[kLdsFrames + 1];                                \
+    int2 t;                                                                 \
+    if (!queue_tile(Q, n, s_start_, t)) return;
 
 __global__ __launch_bounds__(kTileBlock) void k_batch_mesh_count(const BFrame *__restrict__ fr,
                                                                  QueueDev Q, int n) {
-    int q = blockIdx.x % kQueues, tries = 0;
-    int2 t;
-    while (pop_tile(Q, n, q, tries, t)) {
-        const BFrame &f = fr[t.x];
-        mesh_count_row(f.pts, f.N, t.y, f.codes, f.tri_valid, f.row_count);
-    }
+    PL_QUEUE_TILE(Q, n, t)
+    const BFrame &f = fr[t.x];
+    mesh_count_row(f.pts, f.N, t.y, f.codes, f.tri_valid, f.row_count);
 }
 
 __global__ __launch_bounds__(kTileBlock) void k_batch_mesh_emit(const BFrame *__restrict__ fr,
                                                                 QueueDev Q, int n) {
-    int q = blockIdx.x % kQueues, tries = 0;
-    int2 t;
-    while (pop_tile(Q, n, q, tries, t)) {
-        const BFrame &f = fr[t.x];
-        mesh_emit_row(f.codes, f.row_count, f.Mq, f.N, t.y, f.tri_map, f.triangles, f.halfedges,
-                      2 * f.Mq * f.Nq, f.n_tri);
-    }
+    PL_QUEUE_TILE(Q, n, t)
+    const BFrame &f = fr[t.x];
+    mesh_emit_row(f.codes, f.row_count, f.Mq, f.N, t.y, f.tri_map, f.triangles, f.halfedges,
+                  2 * f.Mq * f.Nq, f.n_tri);
 }
 
+template <int R>
 __global__ __launch_bounds__(kTileBlock) void k_batch_laplacian(const BFrame *__restrict__ fr,
                                                                 const PassFrame *__restrict__ pass,
                                                                 QueueDev Q, int n) {
     extern __shared__ float4 lds[];
-    int q = blockIdx.x % kQueues, tries = 0;
-    int2 t;
-    while (pop_tile(Q, n, q, tries, t)) {
-        const BFrame &f = fr[t.x];
-        const PassFrame &p = pass[t.x];
-        const float *src = static_cast<const float *>(p.src);
-        float *dst = static_cast<float *>(p.dst);
-        const int ty0 = (t.y / f.lap_tiles_x) * f.lap_th, tx0 = (t.y % f.lap_tiles_x) * f.lap_tw;
-        switch (f.Rl) {
-        case 1: lap_tile<1>(src, dst, f.M, f.N, f.lam, p.F, f.lap_th, f.lap_tw, ty0, tx0, lds); break;
-        case 2: lap_tile<2>(src, dst, f.M, f.N, f.lam, p.F, f.lap_th, f.lap_tw, ty0, tx0, lds); break;
-        case 3: lap_tile<3>(src, dst, f.M, f.N, f.lam, p.F, f.lap_th, f.lap_tw, ty0, tx0, lds); break;
-        default: lap_tile<4>(src, dst, f.M, f.N, f.lam, p.F, f.lap_th, f.lap_tw, ty0, tx0, lds); break;
-        }
-    }
+    PL_QUEUE_TILE(Q, n, t)
+    const BFrame &f = fr[t.x];
+    const PassFrame &p = pass[t.x];
+    const int ty0 = (t.y / f.lap_tiles_x) * f.lap_th, tx0 = (t.y % f.lap_tiles_x) * f.lap_tw;
+    lap_tile<R>(static_cast<const float *>(p.src), static_cast<float *>(p.dst), f.M, f.N, f.lam,
+                p.F, f.lap_th, f.lap_tw, ty0, tx0, lds);
 }
 
 constexpr int kNormalsChunk = 4 * kTileBlock;   // quads per normals tile
@@ -195,39 +163,29 @@ constexpr int kNormalsChunk = 4 * kTileBlock;   // quads per normals tile
 template <typename NT>
 __global__ __launch_bounds__(kTileBlock) void k_batch_normals(const BFrame *__restrict__ fr,
                                                               QueueDev Q, int n) {
-    int q = blockIdx.x % kQueues, tries = 0;
-    int2 t;
-    while (pop_tile(Q, n, q, tries, t)) {
-        const BFrame &f = fr[t.x];
-        const size_t Qn = (size_t)f.Mq * f.Nq;
-        const size_t q0 = (size_t)t.y * kNormalsChunk;
-        for (size_t qq = q0 + threadIdx.x; qq < Qn && qq < q0 + kNormalsChunk; qq += kTileBlock)
-            normals_quad<NT>(f.pts_out, f.N, f.Nq, qq, static_cast<NT *>(f.nraw), f.centroids);
+    PL_QUEUE_TILE(Q, n, t)
+    const BFrame &f = fr[t.x];
+    __shared__ NormalsStage st;
+    const size_t Qn = (size_t)f.Mq * f.Nq;
+    for (size_t q0 = (size_t)t.y * kNormalsChunk; q0 < Qn && q0 < (size_t)(t.y + 1) * kNormalsChunk;
+         q0 += kTileBlock) {
+        const int nq = (int)(Qn - q0 < (size_t)kTileBlock ? Qn - q0 : (size_t)kTileBlock);
+        normals_block<NT>(f.pts_out, f.N, f.Nq, q0, nq, static_cast<NT *>(f.nraw), f.centroids, st);
     }
 }
 
-template <typename NT>
-__global__ __launch_bounds__(kTileBlock) void k_batch_bilateral(const BFrame *__restrict__ fr,
+template <int R, typename NT>
+__global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_batch_bilateral(const BFrame *__restrict__ fr,
                                                                 const PassFrame *__restrict__ pass,
                                                                 QueueDev Q, int n) {
     extern __shared__ float4 lds[];
-    int q = blockIdx.x % kQueues, tries = 0;
-    int2 t;
-    while (pop_tile(Q, n, q, tries, t)) {
-        const BFrame &f = fr[t.x];
-        const PassFrame &p = pass[t.x];
-        const NT *src = static_cast<const NT *>(p.src);
-        NT *dst = static_cast<NT *>(p.dst);
-        const int32_t *tm = p.gather ? f.tri_map : nullptr;
-        NT *nT = static_cast<NT *>(f.normals_T);
-        const int qy0 = (t.y / f.bil_tiles_x) * f.bil_th, qx0 = (t.y % f.bil_tiles_x) * f.bil_tw;
-        switch (f.Rb) {
-        case 1: bil_tile<1, NT>(src, f.centroids, dst, f.Mq, f.Nq, f.ka, f.kb, p.F, f.bil_th, f.bil_tw, qy0, qx0, tm, nT, lds); break;
-        case 2: bil_tile<2, NT>(src, f.centroids, dst, f.Mq, f.Nq, f.ka, f.kb, p.F, f.bil_th, f.bil_tw, qy0, qx0, tm, nT, lds); break;
-        case 3: bil_tile<3, NT>(src, f.centroids, dst, f.Mq, f.Nq, f.ka, f.kb, p.F, f.bil_th, f.bil_tw, qy0, qx0, tm, nT, lds); break;
-        default: bil_tile<4, NT>(src, f.centroids, dst, f.Mq, f.Nq, f.ka, f.kb, p.F, f.bil_th, f.bil_tw, qy0, qx0, tm, nT, lds); break;
-        }
-    }
+    PL_QUEUE_TILE(Q, n, t)
+    const BFrame &f = fr[t.x];
+    const PassFrame &p = pass[t.x];
+    const int qy0 = (t.y / f.bil_tiles_x) * f.bil_th, qx0 = (t.y % f.bil_tiles_x) * f.bil_tw;
+    bil_tile<R, NT>(static_cast<const NT *>(p.src), f.centroids, static_cast<NT *>(p.dst), f.Mq,
+                    f.Nq, f.ka, f.kb, p.F, f.bil_th, f.bil_tw, qy0, qx0,
+                    p.gather ? f.tri_map : nullptr, static_cast<NT *>(f.normals_T), lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,16 +203,16 @@ struct Layout {                    // byte offsets inside the workspace
 
 struct HostQueue {
     std::vector<int> count;        // [n] tiles per frame
-    size_t off_count = 0, off_start = 0, off_seg = 0, off_counter = 0;
-    long max_tiles = 0;            // all frames active
+    size_t off_count = 0, off_start = 0;
+    long max_tiles = 0;            // all frames active: the launch's workgroups
     int grid = 0;
     size_t lds = 0;
 };
 
-struct Pass {
+struct Pass {                      // one sweep pass: one launch per window radius
     std::vector<PassFrame> tab;    // [n]
     size_t off = 0;
-    HostQueue q;
+    HostQueue q[kMaxRadius];       // q[R - 1]: the frames with window radius R
 };
 
 size_t nt_size(pl_dtype ndt) { return ndt == PL_F32 ? 4 : 2; }
@@ -270,6 +228,7 @@ struct pl_batch_s {
     pl_dtype ndt = PL_F32;
     uint8_t *ws = nullptr;
     size_t off_frames = 0, off_queues = 0, off_ones = 0;
+    int n_queues = 0;              // stage queues with any tile, in table order
     pl::HostQueue mc, me, nq;      // mesh count, mesh emit, normals
     std::vector<pl::Pass> lap, bil;
     hipGraphExec_t graph = nullptr;
@@ -281,8 +240,11 @@ namespace {
 
 std::vector<HostQueue *> all_queues(pl_batch_s &b) {
     std::vector<HostQueue *> qs = {&b.mc, &b.me, &b.nq};
-    for (auto &p : b.lap) qs.push_back(&p.q);
-    for (auto &p : b.bil) qs.push_back(&p.q);
+    for (auto *passes : {&b.lap, &b.bil})
+        for (auto &p : *passes)
+            for (HostQueue &q : p.q)
+                if (std::any_of(q.count.begin(), q.count.end(), [](int c) { return c > 0; }))
+                    qs.push_back(&q);
     return qs;
 }
 
@@ -309,7 +271,10 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
     b.bil.assign(maxbil, Pass());
     for (auto &p : b.lap) { p.tab.assign(n, PassFrame{}); p.off = L.take(sizeof(PassFrame) * n); }
     for (auto &p : b.bil) { p.tab.assign(n, PassFrame{}); p.off = L.take(sizeof(PassFrame) * n); }
-    for (HostQueue *q : all_queues(b)) q->count.assign(n, 0);
+    for (HostQueue *q : {&b.mc, &b.me, &b.nq}) q->count.assign(n, 0);
+    for (auto *passes : {&b.lap, &b.bil})
+        for (auto &p : *passes)
+            for (HostQueue &q : p.q) q.count.assign(n, 0);
     for (int i = 0; i < n; ++i) {
         const pl_frame &f = frames[i];
         const int Mq = f.M - 1, Nq = f.N - 1;
@@ -321,19 +286,18 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         const int ltiles = ((f.N + cl.tw - 1) / cl.tw) * ((f.M + cl.th - 1) / cl.th);
         const int btiles = ((Nq + cb.tw - 1) / cb.tw) * ((Mq + cb.th - 1) / cb.th);
         const int lp = passes_for(f.iters_lap, cl.fuse), bp = passes_for(f.iters_bil, cb.fuse);
-        for (int p = 0; p < lp; ++p) b.lap[p].q.count[i] = ltiles;
-        for (int p = 0; p < bp; ++p) b.bil[p].q.count[i] = btiles;
+        for (int p = 0; p < lp; ++p) b.lap[p].q[f.kernel_lap / 2 - 1].count[i] = ltiles;
+        for (int p = 0; p < bp; ++p) b.bil[p].q[f.kernel_bil / 2 - 1].count[i] = btiles;
     }
     const std::vector<HostQueue *> qs = all_queues(b);
     for (HostQueue *q : qs) {
         q->off_count = L.take(sizeof(int) * n);
         q->off_start = L.take(sizeof(int) * (n + 1));
-        q->off_seg = L.take(sizeof(int) * (kQueues + 1));
-        q->off_counter = L.take(sizeof(int) * kQueues);
         q->max_tiles = 0;
         for (int c : q->count) q->max_tiles += c;
     }
     b.off_queues = L.take(sizeof(QueueDev) * qs.size());
+    b.n_queues = (int)qs.size();
     b.off_ones = L.take(n);
     const size_t table_end = L.off;
     // per-frame scratch
@@ -412,9 +376,7 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
     for (HostQueue *q : qs) {
         std::memcpy(img.data() + q->off_count, q->count.data(), sizeof(int) * n);
         qd.push_back(QueueDev{reinterpret_cast<const int *>(base + q->off_count),
-                              reinterpret_cast<int *>(base + q->off_start),
-                              reinterpret_cast<int *>(base + q->off_seg),
-                              reinterpret_cast<int *>(base + q->off_counter)});
+                              reinterpret_cast<int *>(base + q->off_start)});
     }
     std::memcpy(img.data() + b.off_queues, qd.data(), sizeof(QueueDev) * qd.size());
     std::memset(img.data() + b.off_ones, 1, n);
@@ -428,25 +390,18 @@ namespace {
 
 QueueDev dev_queue(const pl_batch_s &b, const HostQueue &q) {
     return QueueDev{reinterpret_cast<const int *>(b.ws + q.off_count),
-                    reinterpret_cast<int *>(b.ws + q.off_start),
-                    reinterpret_cast<int *>(b.ws + q.off_seg),
-                    reinterpret_cast<int *>(b.ws + q.off_counter)};
+                    reinterpret_cast<int *>(b.ws + q.off_start)};
 }
 
-// Resident grid: occupancy x CUs, never more workgroups than tiles.
+// One workgroup per tile of the whole batch; kernels above 64 KiB of LDS
+// are allowed their size once here.
 pl_status size_grid(HostQueue &q, const void *kernel, size_t lds) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (pl_status st = hip_check(hipGetDevice(&dev), "hipGetDevice")) return st;
-    if (pl_status st = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
-                                 "hipDeviceGetAttribute"))
-        return st;
+    if (q.max_tiles > INT_MAX) {
+        set_error("batch has more than 2^31 - 1 tiles in one stage");
+        return PL_ERR_SHAPE;
+    }
     if (pl_status st = allow_lds(kernel, lds)) return st;
-    if (pl_status st = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel,
-                                                                              kTileBlock, lds),
-                                 "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
-        return st;
-    const long want = (long)std::max(per_cu, 1) * std::max(cus, 1);
-    q.grid = (int)std::max<long>(1, std::min<long>(want, q.max_tiles));
+    q.grid = (int)std::max<long>(1, q.max_tiles);
     q.lds = lds;
     return PL_OK;
 }
@@ -456,26 +411,32 @@ pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
     if (pl_status st = size_grid(b.mc, (const void *)k_batch_mesh_count, 0)) return st;
     if (pl_status st = size_grid(b.me, (const void *)k_batch_mesh_emit, 0)) return st;
     if (pl_status st = size_grid(b.nq, (const void *)k_batch_normals<NT>, 0)) return st;
-    for (size_t p = 0; p < b.lap.size(); ++p) {
-        size_t lds = 0;
-        for (int i = 0; i < b.n; ++i) {
-            if (!b.lap[p].q.count[i]) continue;
-            const int R = frames[i].kernel_lap / 2;
-            const TileCfg c = tile_cfg(kStageLaplacian, R);
-            lds = std::max(lds, lap_lds_bytes(R, b.lap[p].tab[i].F, c.th, c.tw));
+    static const void *const lap_k[kMaxRadius] = {
+        (const void *)k_batch_laplacian<1>, (const void *)k_batch_laplacian<2>,
+        (const void *)k_batch_laplacian<3>, (const void *)k_batch_laplacian<4>};
+    static const void *const bil_k[kMaxRadius] = {
+        (const void *)k_batch_bilateral<1, NT>, (const void *)k_batch_bilateral<2, NT>,
+        (const void *)k_batch_bilateral<3, NT>, (const void *)k_batch_bilateral<4, NT>};
+    for (Pass &p : b.lap)
+        for (int r = 0; r < kMaxRadius; ++r) {
+            size_t lds = 0;
+            for (int i = 0; i < b.n; ++i) {
+                if (!p.q[r].count[i]) continue;
+                const TileCfg c = tile_cfg(kStageLaplacian, r + 1);
+                lds = std::max(lds, lap_lds_bytes(r + 1, p.tab[i].F, c.th, c.tw));
+            }
+            if (pl_status st = size_grid(p.q[r], lap_k[r], lds)) return st;
         }
-        if (pl_status st = size_grid(b.lap[p].q, (const void *)k_batch_laplacian, lds)) return st;
-    }
-    for (size_t p = 0; p < b.bil.size(); ++p) {
-        size_t lds = 0;
-        for (int i = 0; i < b.n; ++i) {
-            if (!b.bil[p].q.count[i]) continue;
-            const int R = frames[i].kernel_bil / 2;
-            const TileCfg c = tile_cfg(kStageBilateral, R);
-            lds = std::max(lds, bil_lds_bytes(R, b.bil[p].tab[i].F, c.th, c.tw));
+    for (Pass &p : b.bil)
+        for (int r = 0; r < kMaxRadius; ++r) {
+            size_t lds = 0;
+            for (int i = 0; i < b.n; ++i) {
+                if (!p.q[r].count[i]) continue;
+                const TileCfg c = tile_cfg(kStageBilateral, r + 1);
+                lds = std::max(lds, bil_lds_bytes(r + 1, p.tab[i].F, c.th, c.tw));
+            }
+            if (pl_status st = size_grid(p.q[r], bil_k[r], lds)) return st;
         }
-        if (pl_status st = size_grid(b.bil[p].q, (const void *)k_batch_bilateral<NT>, lds)) return st;
-    }
     return PL_OK;
 }
 
@@ -483,10 +444,10 @@ template <typename NT>
 pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s) {
     const BFrame *fr = reinterpret_cast<const BFrame *>(b.ws + b.off_frames);
     const QueueDev *qs = reinterpret_cast<const QueueDev *>(b.ws + b.off_queues);
-    const int nq = 3 + (int)b.lap.size() + (int)b.bil.size();
+    const int nq = b.n_queues;
     const uint8_t *act = active ? active : b.ws + b.off_ones;
     const int n = b.n;
-    k_batch_prepare<<<1, kTileBlock, 0, s>>>(qs, nq, n, act);
+    k_batch_prepare<<<nq, kTileBlock, 0, s>>>(qs, n, act);
     if (pl_status st = hip_check(hipGetLastError(), "k_batch_prepare")) return st;
     k_batch_mesh_count<<<b.mc.grid, kTileBlock, 0, s>>>(fr, dev_queue(b, b.mc), n);
     if (pl_status st = hip_check(hipGetLastError(), "k_batch_mesh_count")) return st;
@@ -494,15 +455,37 @@ pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s) {
     if (pl_status st = hip_check(hipGetLastError(), "k_batch_mesh_emit")) return st;
     for (const Pass &p : b.lap) {
         const PassFrame *pt = reinterpret_cast<const PassFrame *>(b.ws + p.off);
-        k_batch_laplacian<<<p.q.grid, kTileBlock, p.q.lds, s>>>(fr, pt, dev_queue(b, p.q), n);
-        if (pl_status st = hip_check(hipGetLastError(), "k_batch_laplacian")) return st;
+        for (int r = 0; r < kMaxRadius; ++r) {
+            const HostQueue &q = p.q[r];
+            if (q.max_tiles == 0) continue;
+            const dim3 g(q.grid), blk(kTileBlock);
+            const QueueDev d = dev_queue(b, q);
+            switch (r + 1) {
+            case 1: k_batch_laplacian<1><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            case 2: k_batch_laplacian<2><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            case 3: k_batch_laplacian<3><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            default: k_batch_laplacian<4><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            }
+            if (pl_status st = hip_check(hipGetLastError(), "k_batch_laplacian")) return st;
+        }
     }
     k_batch_normals<NT><<<b.nq.grid, kTileBlock, 0, s>>>(fr, dev_queue(b, b.nq), n);
     if (pl_status st = hip_check(hipGetLastError(), "k_batch_normals")) return st;
     for (const Pass &p : b.bil) {
         const PassFrame *pt = reinterpret_cast<const PassFrame *>(b.ws + p.off);
-        k_batch_bilateral<NT><<<p.q.grid, kTileBlock, p.q.lds, s>>>(fr, pt, dev_queue(b, p.q), n);
-        if (pl_status st = hip_check(hipGetLastError(), "k_batch_bilateral")) return st;
+        for (int r = 0; r < kMaxRadius; ++r) {
+            const HostQueue &q = p.q[r];
+            if (q.max_tiles == 0) continue;
+            const dim3 g(q.grid), blk(kTileBlock);
+            const QueueDev d = dev_queue(b, q);
+            switch (r + 1) {
+            case 1: k_batch_bilateral<1, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            case 2: k_batch_bilateral<2, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            case 3: k_batch_bilateral<3, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            default: k_batch_bilateral<4, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            }
+            if (pl_status st = hip_check(hipGetLastError(), "k_batch_bilateral")) return st;
+        }
     }
     return PL_OK;
 }

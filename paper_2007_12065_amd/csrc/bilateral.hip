@@ -12,7 +12,7 @@ namespace pl {
 namespace {
 
 template <int R, typename NT>
-__global__ __launch_bounds__(kTileBlock) void k_bilateral(
+__global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_bilateral(
     const NT *__restrict__ nin, const float *__restrict__ cen, NT *__restrict__ nout, int Mq,
     int Nq, float ka, float kb, int F, int TQH, int TQW, int tiles_x, int ntiles,
     const int32_t *__restrict__ tri_map, NT *__restrict__ nT) {

@@ -1,6 +1,7 @@
 // Triangle centroids and normals over the implicit full mesh T_FC (Sec. 5.2),
-// one thread per quad (normals_quad in tiles.h).  Pure streaming work:
-// 12 B/point in, 2 x 12 B/triangle out (float32 normals).
+// one thread per quad, 256 consecutive quads per workgroup (normals_block in
+// tiles.h).  Pure streaming work: 12 B/point in, 2 x 12 B/triangle out
+// (float32 normals).
 #include "tiles.h"
 
 namespace pl {
@@ -12,8 +13,10 @@ __global__ __launch_bounds__(kTileBlock) void k_tri_normals(const float *__restr
                                                             int Nq, size_t Q,
                                                             NT *__restrict__ normals,
                                                             float *__restrict__ centroids) {
-    const size_t q = (size_t)blockIdx.x * kTileBlock + threadIdx.x;
-    if (q < Q) normals_quad<NT>(pts, N, Nq, q, normals, centroids);
+    __shared__ NormalsStage st;
+    const size_t q0 = (size_t)blockIdx.x * kTileBlock;
+    const int nq = (int)(Q - q0 < (size_t)kTileBlock ? Q - q0 : (size_t)kTileBlock);
+    normals_block<NT>(pts, N, Nq, q0, nq, normals, centroids, st);
 }
 
 }  // namespace

@@ -1,5 +1,5 @@
 // Per-tile device bodies shared by the single-frame kernels and the batched
-// persistent kernels, so that a frame gets bit-for-bit the same result
+// kernels, so that a frame gets bit-for-bit the same result
 // whichever way it is launched.  Tile shapes and the number of fused sweeps
 // are runtime values (LDS is dynamic), which lets the tuner pick them.
 #pragma once
@@ -19,8 +19,10 @@ constexpr int kTileBlock = 256;        // threads per workgroup for every tile b
 constexpr int kMeshChunk = 4 * kTileBlock;    // columns staged per pass
 
 // Validity codes of quad row u (bit 0: first triangle, bit 1: second) and the
-// row's triangle count.  All point loads of a 1024-column chunk are issued
-// before any is used; point validity is staged in LDS.
+// row's triangle count.  Points u and u+1 of a 1024-column chunk are read as
+// the contiguous float runs they are, consecutive lanes on consecutive words
+// (coalesced), and a NaN word clears its point's flag in LDS (every writer
+// stores the same 0).  A quad then reads its four corner flags.
 __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, int N, int u,
                                                uint8_t *__restrict__ codes,
                                                uint8_t *__restrict__ tri_valid,
@@ -29,24 +31,26 @@ __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, in
     __shared__ int red[kTileBlock / kWave];
     const int Nq = N - 1;
     const float *r0 = pts + (size_t)u * N * 3;
-    const float *r1 = r0 + (size_t)N * 3;
     int cnt = 0;
     for (int v0 = 0; v0 < Nq; v0 += kMeshChunk) {
-        float x[2][5], y[2][5], z[2][5];
+        const int np = min(kMeshChunk + 1, N - v0);        // points of this chunk per row
+        for (int k = threadIdx.x; k < np; k += kTileBlock) ok[0][k] = ok[1][k] = 1;
+        __syncthreads();
+        constexpr int kUnroll = 4;
+        const float *src = r0 + 3 * (size_t)v0;
+        for (int k0 = 0; k0 < 3 * np; k0 += kUnroll * kTileBlock) {
+            float w[2][kUnroll];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            const int v = v0 + threadIdx.x + j * kTileBlock;
-            const bool in = (j < 4 || threadIdx.x == 0) && v < N && v <= v0 + kMeshChunk;
-            x[0][j] = in ? r0[3 * v] : 0.f; y[0][j] = in ? r0[3 * v + 1] : 0.f; z[0][j] = in ? r0[3 * v + 2] : 0.f;
-            x[1][j] = in ? r1[3 * v] : 0.f; y[1][j] = in ? r1[3 * v + 1] : 0.f; z[1][j] = in ? r1[3 * v + 2] : 0.f;
-        }
+            for (int j = 0; j < kUnroll; ++j) {
+                const int k = k0 + j * kTileBlock + threadIdx.x;
+                w[0][j] = k < 3 * np ? src[k] : 0.f;
+                w[1][j] = k < 3 * np ? src[3 * (size_t)N + k] : 0.f;
+            }
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            const int l = threadIdx.x + j * kTileBlock;
-            if (j < 4 || threadIdx.x == 0) {
-#pragma unroll
-                for (int r = 0; r < 2; ++r)
-                    ok[r][l] = !(is_nan_bits(x[r][j]) || is_nan_bits(y[r][j]) || is_nan_bits(z[r][j]));
+            for (int j = 0; j < kUnroll; ++j) {
+                const int k = k0 + j * kTileBlock + threadIdx.x;
+                if (is_nan_bits(w[0][j])) ok[0][k / 3] = 0;
+                if (is_nan_bits(w[1][j])) ok[1][k / 3] = 0;
             }
         }
         __syncthreads();
@@ -54,16 +58,14 @@ __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, in
         for (int j = 0; j < 4; ++j) {
             const int l = threadIdx.x + j * kTileBlock;
             const int v = v0 + l;
-            if (v < Nq) {
+            if (v < Nq && l < kMeshChunk) {
                 const int p1 = ok[0][l], p2 = ok[0][l + 1], p3 = ok[1][l + 1], p4 = ok[1][l];
                 const int f = p1 & p2 & p3;          // first triangle (p3, p2, p1)
                 const int s = p1 & p3 & p4;          // second triangle (p1, p4, p3)
                 const size_t q = (size_t)u * Nq + v;
                 codes[q] = (uint8_t)(f | (s << 1));
-                if (tri_valid) {
-                    tri_valid[2 * q] = (uint8_t)f;
-                    tri_valid[2 * q + 1] = (uint8_t)s;
-                }
+                if (tri_valid)
+                    *reinterpret_cast<uint16_t *>(tri_valid + 2 * q) = (uint16_t)(f | (s << 8));
                 cnt += f + s;
             }
         }
@@ -78,7 +80,6 @@ __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, in
         for (int w = 0; w < kTileBlock / kWave; ++w) t += red[w];
         row_count[u] = t;
     }
-    __syncthreads();                 // LDS is reused by the next call in a persistent loop
 }
 
 // Block-wide exclusive scan of three counters packed in 21-bit fields (a
@@ -114,11 +115,22 @@ constexpr int kEmitQ = 4;                        // consecutive quads per thread
 constexpr int kEmitChunk = kEmitQ * kTileBlock;  // quads per pass
 constexpr unsigned long long kField = (1ull << 21) - 1;
 
+// Cooperative copy of `count` staged ints to global memory: consecutive
+// lanes write consecutive words, so every store instruction is coalesced.
+__device__ __forceinline__ void emit_flush(const int *stage, int32_t *__restrict__ dst, int count) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < count; k += kTileBlock) dst[k] = stage[k];
+    __syncthreads();
+}
+
 // T_map, T and HE of quad row u.  The row's place in T is the sum of the
 // counts of the rows above it; the codes of rows u-1 and u+1 give the
 // indices of the Top and Bottom twins.  Each thread owns four consecutive
 // quads of a 1024-quad pass (one block scan per pass, serial prefix inside
-// the thread).  The last row writes |T|.
+// the thread).  A thread's outputs are strided in memory (up to 96 bytes per
+// lane), so each of the pass's three contiguous output ranges -- its T_map
+// entries, its rows of T, its rows of HE -- is assembled in LDS and then
+// written with coalesced stores.  The last row writes |T|.
 __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
                                               const int *__restrict__ row_count, int Mq, int N,
                                               int u, int32_t *__restrict__ tri_map,
@@ -126,6 +138,7 @@ __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
                                               int32_t *__restrict__ he, int cap,
                                               int32_t *__restrict__ n_tri) {
     __shared__ int red[kTileBlock / kWave];
+    __shared__ int stage[3 * 2 * kEmitChunk];
     const int Nq = N - 1;
     const uint8_t *cr0 = codes + (size_t)u * Nq;
     const uint8_t *crm = u > 0 ? cr0 - Nq : cr0;        // row u-1
@@ -163,55 +176,79 @@ __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
         const unsigned long long ex = mesh_block_scan(
             (unsigned long long)t0 | ((unsigned long long)tm << 21) | ((unsigned long long)tp << 42),
             &total);
-        int r0 = base0 + carry0 + (int)(ex & kField);        // index of the next triangle of row u
-        int rm = basem + carrym + (int)((ex >> 21) & kField);
-        int rp = basep + carryp + (int)((ex >> 42) & kField);
+        const int pass0 = base0 + carry0;                    // first triangle of this pass
+        const int r00 = pass0 + (int)(ex & kField);          // this thread's first triangle
+        const int rm0 = basem + carrym + (int)((ex >> 21) & kField);
+        const int rp0 = basep + carryp + (int)((ex >> 42) & kField);
+        const int nq = min(kEmitChunk, Nq - v0);              // quads in this pass
+        const int nt = (int)(total & kField);                 // triangles in this pass
+        const int nw = max(0, min(nt, cap - pass0));          // of them below cap
+
+        // T_map: two entries per quad, -1 for an invalid triangle
+        {
+            int r0 = r00;
 #pragma unroll
-        for (int j = 0; j < kEmitQ; ++j) {
-            const int v = vb + j;
-            if (v < Nq) {
-                const int f = c0[j] & 1, s = (c0[j] >> 1) & 1;
-                const int rF = f ? r0 : -1;
-                const int rS = s ? r0 + f : -1;
-                const size_t q = (size_t)u * Nq + v;
-                *reinterpret_cast<int2 *>(tri_map + 2 * q) = make_int2(rF, rS);
-                const int i1 = u * N + v, i2 = i1 + 1, i3 = i1 + N + 1, i4 = i1 + N;
-                if (f && rF < cap) {
-                    tris[3 * rF + 0] = i3; tris[3 * rF + 1] = i2; tris[3 * rF + 2] = i1;
+            for (int j = 0; j < kEmitQ; ++j) {
+                const int v = vb + j;
+                if (v < Nq) {
+                    const int f = c0[j] & 1, s = (c0[j] >> 1) & 1;
+                    stage[2 * (v - v0)] = f ? r0 : -1;
+                    stage[2 * (v - v0) + 1] = s ? r0 + f : -1;
                 }
-                if (s && rS < cap) {
-                    tris[3 * rS + 0] = i1; tris[3 * rS + 1] = i4; tris[3 * rS + 2] = i3;
-                }
-                if (he) {
-                    // Right = (u, v+1, 1), Top = (u-1, v, 1), Left = (u, v-1, 0),
-                    // Bottom = (u+1, v, 0); indices from the running prefix sums.
-                    const int cr = j + 1 < kEmitQ ? c0[j + 1] : cr_last;
-                    const int cl = j > 0 ? c0[j - 1] : cl_first;
-                    const int right = (cr & 2) ? r0 + f + s + (cr & 1) : -1;
-                    const int left = (cl & 1) ? r0 - popc2(cl) : -1;
-                    const int top = (cm[j] & 2) ? rm + (cm[j] & 1) : -1;
-                    const int bottom = (cp[j] & 1) ? rp : -1;
-                    if (f && rF < cap) {
-                        he[3 * rF + 0] = right >= 0 ? 3 * right : -1;
-                        he[3 * rF + 1] = top >= 0 ? 3 * top + 1 : -1;
-                        he[3 * rF + 2] = s ? 3 * rS + 2 : -1;
-                    }
-                    if (s && rS < cap) {
-                        he[3 * rS + 0] = left >= 0 ? 3 * left : -1;
-                        he[3 * rS + 1] = bottom >= 0 ? 3 * bottom + 1 : -1;
-                        he[3 * rS + 2] = f ? 3 * rF + 2 : -1;
-                    }
-                }
+                r0 += popc2(c0[j]);
             }
-            r0 += popc2(c0[j]);
-            rm += popc2(cm[j]);
-            rp += popc2(cp[j]);
+            emit_flush(stage, tri_map + 2 * ((size_t)u * Nq + v0), 2 * nq);
         }
-        carry0 += (int)(total & kField);
+        // T: first triangle (p3, p2, p1), second (p1, p4, p3)
+        {
+            int r0 = r00;
+#pragma unroll
+            for (int j = 0; j < kEmitQ; ++j) {
+                const int v = vb + j;
+                const int f = c0[j] & 1, s = (c0[j] >> 1) & 1;
+                const int i1 = u * N + v, i2 = i1 + 1, i3 = i1 + N + 1, i4 = i1 + N;
+                const int a = 3 * (r0 - pass0);
+                if (f) { stage[a] = i3; stage[a + 1] = i2; stage[a + 2] = i1; }
+                if (s) { stage[a + 3 * f] = i1; stage[a + 3 * f + 1] = i4; stage[a + 3 * f + 2] = i3; }
+                r0 += f + s;
+            }
+            emit_flush(stage, tris + 3 * (size_t)pass0, 3 * nw);
+        }
+        // HE: Right = (u, v+1, 1), Top = (u-1, v, 1), Left = (u, v-1, 0),
+        // Bottom = (u+1, v, 0); twin indices from the running prefix sums
+        if (he) {
+            int r0 = r00, rm = rm0, rp = rp0;
+#pragma unroll
+            for (int j = 0; j < kEmitQ; ++j) {
+                const int f = c0[j] & 1, s = (c0[j] >> 1) & 1;
+                const int cr = j + 1 < kEmitQ ? c0[j + 1] : cr_last;
+                const int cl = j > 0 ? c0[j - 1] : cl_first;
+                const int right = (cr & 2) ? r0 + f + s + (cr & 1) : -1;
+                const int left = (cl & 1) ? r0 - popc2(cl) : -1;
+                const int top = (cm[j] & 2) ? rm + (cm[j] & 1) : -1;
+                const int bottom = (cp[j] & 1) ? rp : -1;
+                const int rF = r0, rS = r0 + f;
+                const int a = 3 * (r0 - pass0);
+                if (f) {
+                    stage[a] = right >= 0 ? 3 * right : -1;
+                    stage[a + 1] = top >= 0 ? 3 * top + 1 : -1;
+                    stage[a + 2] = s ? 3 * rS + 2 : -1;
+                }
+                if (s) {
+                    stage[a + 3 * f] = left >= 0 ? 3 * left : -1;
+                    stage[a + 3 * f + 1] = bottom >= 0 ? 3 * bottom + 1 : -1;
+                    stage[a + 3 * f + 2] = f ? 3 * rF + 2 : -1;
+                }
+                r0 += f + s;
+                rm += popc2(cm[j]);
+                rp += popc2(cp[j]);
+            }
+            emit_flush(stage, he + 3 * (size_t)pass0, 3 * nw);
+        }
+        carry0 += nt;
         carrym += (int)((total >> 21) & kField);
         carryp += (int)((total >> 42) & kField);
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -324,7 +361,6 @@ struct V3 {
     float x, y, z;
 };
 
-__device__ __forceinline__ V3 ld3(const float *p) { return V3{p[0], p[1], p[2]}; }
 __device__ __forceinline__ bool ok3(const V3 &a) {
     return !(is_nan_bits(a.x) || is_nan_bits(a.y) || is_nan_bits(a.z));
 }
@@ -350,25 +386,73 @@ __device__ __forceinline__ void tri_geom(const V3 &a, const V3 &b, const V3 &c, 
     }
 }
 
-template <typename NT>
-__device__ __forceinline__ void normals_quad(const float *__restrict__ pts, int N, int Nq, size_t q,
-                                             NT *__restrict__ normals,
-                                             float *__restrict__ centroids) {
-    const int u = (int)(q / Nq), v = (int)(q - (size_t)u * Nq);
-    const float *r0 = pts + 3 * ((size_t)u * N + v);
-    const float *r1 = r0 + 3 * (size_t)N;
-    const V3 p1 = ld3(r0), p2 = ld3(r0 + 3), p3 = ld3(r1 + 3), p4 = ld3(r1);
+// Centroids and normals of both triangles of a quad with corners p1 = (u, v),
+// p2 = (u, v+1), p3 = (u+1, v+1), p4 = (u+1, v); NaN for a missing triangle.
+__device__ __forceinline__ void quad_geom(const V3 &p1, const V3 &p2, const V3 &p3, const V3 &p4,
+                                          V3 &c0, V3 &n0, V3 &c1, V3 &n1) {
     const bool v1 = ok3(p1), v2 = ok3(p2), v3 = ok3(p3), v4 = ok3(p4);
     const V3 nan3{qnan(), qnan(), qnan()};
-    V3 c0 = nan3, n0 = nan3, c1 = nan3, n1 = nan3;
+    c0 = nan3; n0 = nan3; c1 = nan3; n1 = nan3;
     if (v1 & v2 & v3) tri_geom(p3, p2, p1, c0, n0);     // first triangle
     if (v1 & v3 & v4) tri_geom(p1, p4, p3, c1, n1);     // second triangle
-    float *co = centroids + 6 * q;
-    co[0] = c0.x; co[1] = c0.y; co[2] = c0.z;
-    co[3] = c1.x; co[4] = c1.y; co[5] = c1.z;
-    NT *no = normals + 6 * q;
-    st_f(no + 0, n0.x); st_f(no + 1, n0.y); st_f(no + 2, n0.z);
-    st_f(no + 3, n1.x); st_f(no + 4, n1.y); st_f(no + 5, n1.z);
+}
+
+// Up to kTileBlock consecutive quads [q0, q0 + nq), one per thread, q0 a
+// multiple of kTileBlock.  Quad q = (u, v) has its top corners at point
+// index q + u, so the block's top corners are one contiguous run of points
+// and its bottom corners the run N points further; both runs are read with
+// coalesced word loads into LDS (at most 2 kTileBlock points each, reached
+// only when N = 2).  A quad's outputs (6 centroid floats, 6 normals) would be
+// 24-byte strided per thread, so both are assembled in the same LDS and
+// written with coalesced 8-byte (float32) or 4-byte (float16 pairs) stores.
+struct NormalsStage {
+    float f[2][3 * 2 * kTileBlock];
+};
+
+template <typename NT>
+__device__ __forceinline__ void normals_block(const float *__restrict__ pts, int N, int Nq, size_t q0,
+                                              int nq, NT *__restrict__ normals,
+                                              float *__restrict__ centroids, NormalsStage &st) {
+    const size_t ua = q0 / Nq, ub = (q0 + nq - 1) / Nq;
+    const size_t P0 = q0 + ua;                              // top-left corner of quad q0
+    const int L = (int)(nq + 1 + (ub - ua));                // points per run
+    const float *top = pts + 3 * P0, *bot = top + 3 * (size_t)N;
+    for (int k = threadIdx.x; k < 3 * L; k += kTileBlock) {
+        st.f[0][k] = top[k];
+        st.f[1][k] = bot[k];
+    }
+    __syncthreads();
+    V3 c0, n0, c1, n1;
+    if ((int)threadIdx.x < nq) {
+        const unsigned q = (unsigned)q0 + threadIdx.x;      // 6 Q < 2^31 (shape check)
+        const int o = 3 * (int)(q + q / (unsigned)Nq - (unsigned)P0);
+        const float *t = st.f[0] + o, *b = st.f[1] + o;
+        quad_geom(V3{t[0], t[1], t[2]}, V3{t[3], t[4], t[5]}, V3{b[3], b[4], b[5]},
+                  V3{b[0], b[1], b[2]}, c0, n0, c1, n1);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nq) {
+        float *co = st.f[0] + 6 * threadIdx.x;
+        co[0] = c0.x; co[1] = c0.y; co[2] = c0.z;
+        co[3] = c1.x; co[4] = c1.y; co[5] = c1.z;
+        NT *no = reinterpret_cast<NT *>(st.f[1]) + 6 * threadIdx.x;
+        st_f(no + 0, n0.x); st_f(no + 1, n0.y); st_f(no + 2, n0.z);
+        st_f(no + 3, n1.x); st_f(no + 4, n1.y); st_f(no + 5, n1.z);
+    }
+    __syncthreads();
+    const float2 *sc2 = reinterpret_cast<const float2 *>(st.f[0]);
+    float2 *gc2 = reinterpret_cast<float2 *>(centroids + 6 * q0);
+    for (int k = threadIdx.x; k < 3 * nq; k += kTileBlock) gc2[k] = sc2[k];
+    if (sizeof(NT) == 4) {
+        const float2 *s2 = reinterpret_cast<const float2 *>(st.f[1]);
+        float2 *g2 = reinterpret_cast<float2 *>(normals + 6 * q0);
+        for (int k = threadIdx.x; k < 3 * nq; k += kTileBlock) g2[k] = s2[k];
+    } else {
+        const uint32_t *s1 = reinterpret_cast<const uint32_t *>(st.f[1]);
+        uint32_t *g1 = reinterpret_cast<uint32_t *>(normals + 6 * q0);
+        for (int k = threadIdx.x; k < 3 * nq; k += kTileBlock) g1[k] = s1[k];
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -383,11 +467,29 @@ __device__ __forceinline__ void normals_quad(const float *__restrict__ pts, int 
 // float32 values) before scaling; expanding them or pre-scaling the
 // centroids saves instructions but costs ~1e-5 relative weight accuracy.
 //
-// Eq. 6 renormalises, so a common factor of the weights cancels.  Since
-// e >= 0 no weight exceeds 1; if the whole neighbourhood is so far away that
-// the total weight drops below 2^-60, that triangle is recomputed with every
-// exponent shifted by the smallest one (the same value in exact arithmetic),
-// which keeps the largest term at 1.  Only the lanes that need it take it.
+// Eq. 6 renormalises, so a common factor of the weights cancels: both
+// triangles of a quad take w = 2^(m - e) with m = min(e01, 52), e01 the pair
+// exponent between the two (the same value in exact arithmetic).  The other
+// triangle of a quad is usually as close as its nearest neighbour, so the
+// largest weights stay near 1; with e >= 0 no weight exceeds 2^52, which keeps
+// the sums and the squared norm of Eq. 6 finite for windows up to 9 x 9
+// (160 neighbours).  If the total still drops below 2^-60 (every neighbour
+// far beyond the quad's own pair), that triangle is recomputed with every
+// exponent shifted by the smallest one, which puts the largest term at 1.
+// Only the lanes that need it take it.
+//
+// Symmetric pairs.  e(i, j) = e(j, i), bit for bit (the differences only
+// change sign), so a quad pair needs its four exponents once.  The window's
+// displacements split into D+ (dy = 0, dx > 0, or dy > 0) and their negatives;
+// a triangle sums its terms in the fixed order: for each d of D+, the two
+// triangles of quad a+d, then the two of quad a-d.  In the last sweep of a
+// tile, each displacement d takes two phases: every tile quad a computes the
+// exponents to a+d, uses them, and leaves them in LDS; the quads of the
+// upstream halo (those with a+d in the tile) do the same; then every tile
+// quad reads the exponents of a-d from LDS.  Each side applies its own shift
+// and exp.  The direct form (both neighbours computed by the quad itself,
+// same order, same bits) serves intermediate sweeps and tiles too large for
+// one quad per thread.
 //
 // Off-grid quads and triangles with a NaN normal or centroid are staged with
 // an infinite centroid and a zero normal: infinite exponent, weight exactly 0,
@@ -395,14 +497,31 @@ __device__ __forceinline__ void normals_quad(const float *__restrict__ pts, int 
 // input bits).  Float16-stored normals produced by an intermediate sweep are
 // re-rounded to float16, as if stored between launches, so results do not
 // depend on F.  F = 0 copies the tile (and gathers).
-// LDS: 3 * 2 * (TQH + 2RF) * (TQW + 2RF) float4 (centroids, two normal
-// buffers); with F <= 1 the second normal buffer is not used.
+// LDS: (TQH + 2RF) * (TQW + 2RF) float4 times 5 (centroids and normals of
+// both triangles, the exchanged exponents) or, with F > 1, times 6 (a second
+// normal buffer, which also holds the exponents in the last sweep).
 // ---------------------------------------------------------------------------
 
 constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
-
+// register budget of the bilateral kernels: at least 6 waves per SIMD
+// (<= 80 VGPRs), more than the LDS of a typical tile lets reside anyway
+constexpr int kBilWavesPerSimd = 6;
+constexpr float kBilShiftCap = 52.f;
 __host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW) {
-    return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F);
+    return (F > 1 ? 6 : 5) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F);
+}
+
+// Quads of the upstream halo of a TQH x TQW tile (those a quad of the tile
+// reaches through some -d, d in D+): R rows above the tile, R + TQW + R
+// wide, then R columns on either side of the tile's rows.
+__host__ __device__ constexpr int bil_upstream(int R, int TQH, int TQW) {
+    return R * (TQW + 2 * R) + 2 * R * TQH;
+}
+
+// The symmetric last sweep needs one tile quad and at most one halo quad
+// per thread.
+__host__ __device__ constexpr bool bil_symmetric(int R, int TQH, int TQW) {
+    return TQH * TQW <= kTileBlock && bil_upstream(R, TQH, TQW) <= kTileBlock;
 }
 
 template <typename NT> __device__ __forceinline__ float round_storage(float x);
@@ -429,14 +548,28 @@ struct BilAcc {
     float x, y, z, w;
 };
 
-__device__ __forceinline__ void bil_accumulate(BilAcc &s, const BilOwn &o, const float4 c,
-                                               const float4 n) {
-    const float w = __builtin_amdgcn_exp2f(-bil_pair_e(o, c, n));
+// s += 2^(m - e) * n
+__device__ __forceinline__ void bil_add(BilAcc &s, float m, float e, const float4 n) {
+    const float w = __builtin_amdgcn_exp2f(m - e);
     s.w += w;
     s.x = fmaf(w, n.x, s.x);
     s.y = fmaf(w, n.y, s.y);
     s.z = fmaf(w, n.z, s.z);
 }
+
+// The i-th displacement of D+: dy = 0, dx = 1..R, then dy = 1..R, dx = -R..R.
+template <int R>
+__device__ __forceinline__ void bil_dplus(int i, int &dy, int &dx) {
+    if (i < R) {
+        dy = 0;
+        dx = i + 1;
+    } else {
+        const int j = i - R;
+        dy = 1 + j / (2 * R + 1);
+        dx = j % (2 * R + 1) - R;
+    }
+}
+template <int R> constexpr int bil_ndplus() { return 2 * R * R + 2 * R; }
 
 template <int R>
 __device__ __forceinline__ BilAcc bil_shifted_sum(const BilOwn o, const float4 *sc,
@@ -463,12 +596,7 @@ __device__ __forceinline__ BilAcc bil_shifted_sum(const BilOwn o, const float4 *
             if (dy == 0 && dx == 0) continue;
             for (int kk = 0; kk < 2; ++kk) {
                 const int b = a0 + dy * pitch + dx + kk * plane;
-                const float4 n = sn[b];
-                const float w = __builtin_amdgcn_exp2f(m - bil_pair_e(o, sc[b], n));
-                s.w += w;
-                s.x = fmaf(w, n.x, s.x);
-                s.y = fmaf(w, n.y, s.y);
-                s.z = fmaf(w, n.z, s.z);
+                bil_add(s, m, bil_pair_e(o, sc[b], sn[b]), sn[b]);
             }
         }
     return s;
@@ -483,37 +611,136 @@ __device__ __forceinline__ float4 bil_finish(BilAcc s, float4 cur) {
                        round_storage<NT>(s.z * k), cur.w);
 }
 
-// Filter both triangles of the quad at LDS index a; usable flags live in the
-// centroids' fourth lane.
+// The own triangles of the quad at LDS index a and their common shift.
+struct BilQuad {
+    float4 c0, c1, n0, n1;
+    BilOwn o0, o1;
+    float m;
+};
+
+__device__ __forceinline__ BilQuad bil_quad(const float4 *sc, const float4 *sn, int a, int plane,
+                                            float ka, float kb) {
+    BilQuad q;
+    q.c0 = sc[a]; q.c1 = sc[plane + a];
+    q.n0 = sn[a]; q.n1 = sn[plane + a];
+    q.o0 = BilOwn{q.c0.x, q.c0.y, q.c0.z, q.n0.x, q.n0.y, q.n0.z, ka, kb};
+    q.o1 = BilOwn{q.c1.x, q.c1.y, q.c1.z, q.n1.x, q.n1.y, q.n1.z, ka, kb};
+    // e01 is symmetric; NaN (both missing) or +inf (one missing) gives the cap
+    q.m = fminf(bil_pair_e(q.o0, q.c1, q.n1), kBilShiftCap);
+    return q;
+}
+
+// Fallback for underflowed sums, Eq. 6, missing triangles copied through.
+template <int R, typename NT>
+__device__ __forceinline__ void bil_close(const BilQuad &q, BilAcc s0, BilAcc s1, const float4 *sc,
+                                          const float4 *sn, int a, int pitch, int plane,
+                                          float4 &r0, float4 &r1) {
+    const bool ok0 = q.c0.w != 0.f, ok1 = q.c1.w != 0.f;
+    if (ok0 && !(s0.w >= kBilUnderflow)) s0 = bil_shifted_sum<R>(q.o0, sc, sn, a, pitch, plane);
+    if (ok1 && !(s1.w >= kBilUnderflow)) s1 = bil_shifted_sum<R>(q.o1, sc, sn, a, pitch, plane);
+    r0 = ok0 ? bil_finish<NT>(s0, q.n0) : q.n0;
+    r1 = ok1 ? bil_finish<NT>(s1, q.n1) : q.n1;
+}
+
+// Direct form: both triangles of the quad at LDS index a, every neighbour
+// computed here, in the canonical order.
 template <int R, typename NT>
 __device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *sn, int a,
                                                 int pitch, int plane, float ka, float kb,
                                                 float4 &r0, float4 &r1) {
-    const float4 c0 = sc[a], c1 = sc[plane + a];
-    const float4 n0 = sn[a], n1 = sn[plane + a];
-    const BilOwn o0{c0.x, c0.y, c0.z, n0.x, n0.y, n0.z, ka, kb};
-    const BilOwn o1{c1.x, c1.y, c1.z, n1.x, n1.y, n1.z, ka, kb};
+    const BilQuad q = bil_quad(sc, sn, a, plane, ka, kb);
     BilAcc s0{0.f, 0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f, 0.f};
-    // one window row per iteration keeps only that row's neighbours live
 #pragma unroll 1
-    for (int dy = -R; dy <= R; ++dy) {
+    for (int i = 0; i < bil_ndplus<R>(); ++i) {
+        int dy, dx;
+        bil_dplus<R>(i, dy, dx);
+        const int off = dy * pitch + dx;
 #pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-            if (dy == 0 && dx == 0) continue;     // the own quad is not a neighbour
+        for (int side = 0; side < 2; ++side) {        // quad a + d, then quad a - d
+            const int b = side == 0 ? a + off : a - off;
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
-                const int b = a + dy * pitch + dx + kk * plane;
-                const float4 c = sc[b], n = sn[b];
-                bil_accumulate(s0, o0, c, n);
-                bil_accumulate(s1, o1, c, n);
+                const float4 c = sc[b + kk * plane], n = sn[b + kk * plane];
+                bil_add(s0, q.m, bil_pair_e(q.o0, c, n), n);
+                bil_add(s1, q.m, bil_pair_e(q.o1, c, n), n);
             }
         }
     }
-    const bool ok0 = c0.w != 0.f, ok1 = c1.w != 0.f;
-    if (ok0 && !(s0.w >= kBilUnderflow)) s0 = bil_shifted_sum<R>(o0, sc, sn, a, pitch, plane);
-    if (ok1 && !(s1.w >= kBilUnderflow)) s1 = bil_shifted_sum<R>(o1, sc, sn, a, pitch, plane);
-    r0 = ok0 ? bil_finish<NT>(s0, n0) : n0;
-    r1 = ok1 ? bil_finish<NT>(s1, n1) : n1;
+    bil_close<R, NT>(q, s0, s1, sc, sn, a, pitch, plane, r0, r1);
+}
+
+// Symmetric form of a tile's last sweep (see above): thread t owns tile quad
+// t (when t < TQH * TQW) and upstream halo quad t (when t < the halo count);
+// E holds one float4 of exponents per LDS quad.  Every thread of the
+// workgroup must call this (it synchronises).  Returns the filtered pair of
+// the thread's tile quad in r0, r1.
+template <int R, typename NT>
+__device__ __forceinline__ void bil_sweep_symmetric(const float4 *sc, const float4 *sn, float4 *E,
+                                                    int W, int plane, int halo, int TQH, int TQW,
+                                                    float ka, float kb, float4 &r0, float4 &r1) {
+    const int t = threadIdx.x;
+    const bool own = t < TQH * TQW;
+    const int ty = own ? t / TQW : 0, tx = own ? t - ty * TQW : 0;
+    const int a = (ty + halo) * W + tx + halo;
+    // upstream halo quad of this thread, in LDS coordinates (hy, hx)
+    const int nH = bil_upstream(R, TQH, TQW);
+    const bool hal = t < nH;
+    int hy = 0, hx = 0;
+    if (hal) {
+        const int top = R * (TQW + 2 * R);
+        if (t < top) {
+            hy = halo - R + t / (TQW + 2 * R);
+            hx = halo - R + t % (TQW + 2 * R);
+        } else {
+            const int j = t - top, side = j % (2 * R);
+            hy = halo + j / (2 * R);
+            hx = side < R ? halo - R + side : halo + TQW + (side - R);
+        }
+    }
+    const int h = hy * W + hx;
+    const BilQuad q = bil_quad(sc, sn, a, plane, ka, kb);
+    BilAcc s0{0.f, 0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int i = 0; i < bil_ndplus<R>(); ++i) {
+        int dy, dx;
+        bil_dplus<R>(i, dy, dx);
+        const int off = dy * W + dx;
+        if (own) {                                   // quad a + d: use and publish
+            const int b = a + off;
+            const float4 cb0 = sc[b], cb1 = sc[plane + b], nb0 = sn[b], nb1 = sn[plane + b];
+            const float e00 = bil_pair_e(q.o0, cb0, nb0), e01 = bil_pair_e(q.o0, cb1, nb1);
+            const float e10 = bil_pair_e(q.o1, cb0, nb0), e11 = bil_pair_e(q.o1, cb1, nb1);
+            bil_add(s0, q.m, e00, nb0);
+            bil_add(s0, q.m, e01, nb1);
+            bil_add(s1, q.m, e10, nb0);
+            bil_add(s1, q.m, e11, nb1);
+            E[a] = make_float4(e00, e01, e10, e11);
+        }
+        if (hal) {                                   // halo quad h whose h + d is in the tile
+            const int by = hy + dy - halo, bx = hx + dx - halo;
+            if (by >= 0 && by < TQH && bx >= 0 && bx < TQW) {
+                const float4 c0 = sc[h], c1 = sc[plane + h], n0 = sn[h], n1 = sn[plane + h];
+                const BilOwn g0{c0.x, c0.y, c0.z, n0.x, n0.y, n0.z, ka, kb};
+                const BilOwn g1{c1.x, c1.y, c1.z, n1.x, n1.y, n1.z, ka, kb};
+                const int b = h + off;
+                const float4 cb0 = sc[b], cb1 = sc[plane + b], nb0 = sn[b], nb1 = sn[plane + b];
+                E[h] = make_float4(bil_pair_e(g0, cb0, nb0), bil_pair_e(g0, cb1, nb1),
+                                   bil_pair_e(g1, cb0, nb0), bil_pair_e(g1, cb1, nb1));
+            }
+        }
+        __syncthreads();
+        if (own) {                                   // quad a - d: exponents from its owner
+            const int b = a - off;
+            const float4 e = E[b];                   // e(b_k', a_k) at [2 k' + k]
+            const float4 nb0 = sn[b], nb1 = sn[plane + b];
+            bil_add(s0, q.m, e.x, nb0);
+            bil_add(s0, q.m, e.z, nb1);
+            bil_add(s1, q.m, e.y, nb0);
+            bil_add(s1, q.m, e.w, nb1);
+        }
+        __syncthreads();
+    }
+    if (own) bil_close<R, NT>(q, s0, s1, sc, sn, a, W, plane, r0, r1);
 }
 
 template <int R, typename NT>
@@ -526,7 +753,7 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     const int H = TQH + 2 * halo, W = TQW + 2 * halo, S = H * W;
     float4 *s_c = lds;                  // [2][S] centroids, w = 1 if usable
     float4 *s_n = lds + 2 * S;          // [2][S] normals
-    float4 *s_m = lds + 4 * S;          // [2][S] second normal buffer (F > 1)
+    float4 *s_m = lds + 4 * S;          // [S] exponents (F = 1) or [2][S] second normals (F > 1)
     const float inf = __builtin_inff();
     const int oy = qy0 - halo, ox = qx0 - halo;
 
@@ -577,6 +804,9 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     }
 
     // last sweep (or the copy when F = 0): the tile itself, to global memory
+    const bool sym = F > 0 && bil_symmetric(R, TQH, TQW);
+    float4 rs0, rs1;
+    if (sym) bil_sweep_symmetric<R, NT>(s_c, cur, nxt, W, S, halo, TQH, TQW, ka, kb, rs0, rs1);
     for (int idx = threadIdx.x; idx < TQH * TQW; idx += kTileBlock) {
         const int ty = idx / TQW, tx = idx - ty * TQW;
         const int qy = qy0 + ty, qx = qx0 + tx;
@@ -586,7 +816,12 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
         if (F > 0) {
             const int a = (ty + halo) * W + tx + halo;
             float4 r[2];
-            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r[0], r[1]);
+            if (sym) {
+                r[0] = rs0;
+                r[1] = rs1;
+            } else {
+                bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r[0], r[1]);
+            }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 if (s_c[k * S + a].w != 0.f) {

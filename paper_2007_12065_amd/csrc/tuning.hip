@@ -18,7 +18,8 @@ TileCfg g_cfg[kNumStages][kMaxRadius + 1] = {
     {{0, 0, 0}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}},
 };
 
-constexpr size_t kLdsMax = 160 * 1024;        // gfx950 LDS per workgroup
+// gfx950 LDS per workgroup, less room for the batched kernels' static LDS
+constexpr size_t kLdsMax = 156 * 1024;
 
 }  // namespace
 

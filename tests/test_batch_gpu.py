@@ -1,4 +1,4 @@
-"""The batched path (one persistent launch per stage over mixed frames) gives
+"""The batched path (one launch per stage over mixed frames) gives
 every frame exactly its single-frame result, replays correctly from a HIP
 graph, and float32 outputs do not depend on tile shapes or sweep fusion."""
 import numpy as np
@@ -83,6 +83,28 @@ def test_batch_equals_single_frames(pl, dtype_name):
     b.close()
 
 
+def test_batch_more_frames_than_the_lds_table(pl):
+    # past 256 frames the tile lookup searches the prefix sums in global
+    # memory; frames on both sides of that bound, with a sparse active mask
+    import torch
+    rng = np.random.default_rng(12)
+    specs = []
+    for i in range(300):
+        M, N = int(rng.integers(2, 14)), int(rng.integers(2, 70))
+        k = int(rng.choice([3, 5]))
+        specs.append(spec(random_grid(M, N, 500 + i, nan_frac=0.1), k, 1.0, int(rng.integers(0, 4)),
+                          k, 0.1, 0.1, int(rng.integers(0, 3))))
+    print("[case] batch of 300 small frames", flush=True)
+    b = pl.Batch(specs, torch.float32)
+    mask = torch.tensor([1 if i % 3 == 0 else 0 for i in range(300)], dtype=torch.uint8,
+                        device="cuda:0")
+    b.run(mask)
+    torch.cuda.synchronize()
+    for i in list(range(0, 30, 3)) + list(range(249, 300, 3)):
+        assert_frame_equal(b.outputs[i], single(pl, specs[i], torch.float32), f"frame {i}")
+    b.close()
+
+
 def test_batch_graph_replay(pl):
     import torch
     specs = mixed_specs()[:6]
@@ -159,21 +181,31 @@ def test_tiling_invariance(pl):
     ref_lap = host(pl.pl_laplacian(pts, 5, 1.0, 4)).copy()
     n, c = pl.pl_tri_normals(dev_t(make_frame("rgbd", 32)))
     ref_bil = host(pl.pl_bilateral(n, c, 3, 0.1, 0.1, 3)[0]).copy()
-    saved = [pl.pl_tune_get(0, 5), pl.pl_tune_get(1, 3)]
+    saved = [pl.pl_tune_get(0, 5), pl.pl_tune_get(1, 3), pl.pl_tune_get(1, 5)]
     try:
         for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 128, 4), (32, 8, 3)]:
             print("[case] laplacian tile", th, tw, fu, flush=True)
             pl.pl_tune_set(0, 5, th, tw, fu)
             assert np.array_equal(host(pl.pl_laplacian(pts, 5, 1.0, 4)).view(np.uint8),
                                   ref_lap.view(np.uint8))
-        for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 32, 3), (2, 128, 1)]:
+        # (16, 32, *) tiles exceed one quad per thread: their last sweep takes
+        # the direct form, the others the symmetric exchange; same bits
+        for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 32, 3), (2, 128, 1), (16, 32, 1), (16, 32, 2)]:
             print("[case] bilateral tile", th, tw, fu, flush=True)
             pl.pl_tune_set(1, 3, th, tw, fu)
             assert np.array_equal(host(pl.pl_bilateral(n, c, 3, 0.1, 0.1, 3)[0]).view(np.uint8),
                                   ref_bil.view(np.uint8))
+        n5, c5 = pl.pl_tri_normals(pts)
+        ref5 = host(pl.pl_bilateral(n5, c5, 5, 0.1, 0.1, 3)[0]).copy()
+        for th, tw, fu in [(16, 32, 1), (4, 64, 2), (16, 16, 1)]:
+            print("[case] bilateral 5x5 tile", th, tw, fu, flush=True)
+            pl.pl_tune_set(1, 5, th, tw, fu)
+            assert np.array_equal(host(pl.pl_bilateral(n5, c5, 5, 0.1, 0.1, 3)[0]).view(np.uint8),
+                                  ref5.view(np.uint8))
     finally:
         pl.pl_tune_set(0, 5, *saved[0])
         pl.pl_tune_set(1, 3, *saved[1])
+        pl.pl_tune_set(1, 5, *saved[2])
 
 
 def test_batch_overlap_rejected(pl):
