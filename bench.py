@@ -40,6 +40,9 @@ def parse():
                     help="also run a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also measure the 64-frame mixed batch (0 = skip)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON tuning cache: load it if present, else tune and write it "
+                         "(default: tune in-process, nothing written)")
     ap.add_argument("--serving-seconds", type=float, default=6.0,
                     help="measured seconds of the Poisson serving run after 1 s warm-up (0 = skip)")
     return ap.parse_args()
@@ -137,10 +140,12 @@ def angle_stats(got, ref):
     return {"p50": float(np.median(a)), "p99": float(np.percentile(a, 99)), "max": float(a.max())}
 
 
-def batched_bench(reps=20):
+def batched_bench(reps=20, tune_cache=None):
     """The 64-frame mix (16x 120x160, 24x 480x640, 16x 64x1024, 8x 128x2048):
     plain per-frame float32 path vs one batch plan (graph replay), float32
-    and float16 normals.  Angular error of a sample against the FP64 oracle."""
+    and float16 normals, with the batched path's tile shapes tuned on this
+    mix (or loaded from the cache).  Angular error of a sample against the
+    FP64 oracle."""
     import numpy as np
     import torch
 
@@ -156,6 +161,15 @@ def batched_bench(reps=20):
                           iters_lap=k.iters_lap, kernel_bil=k.kernel_bil, sigma_length=k.sigma_length,
                           sigma_angle=k.sigma_angle, iters_bil=k.iters_bil))
     T = sum(2 * (f.shape[0] - 1) * (f.shape[1] - 1) for f, _ in host)
+    from paper_2007_12065_amd import tune
+    cached = {}
+    if tune_cache and os.path.exists(tune_cache):
+        cached = {k: v for k, v in json.load(open(tune_cache)).get(tune.arch_name(), {}).items()
+                  if k.startswith("batch_")}
+    if cached:
+        batch_tuning = {k: {"best": tuple(v["best"])} for k, v in cached.items()}
+    else:
+        batch_tuning = tune.autotune_batch(specs, cache_path=tune_cache, reps=10)
     plans = [pl.FramePlan(f.shape[0], f.shape[1], k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
                           k.sigma_length, k.sigma_angle, k.iters_bil, torch.float32, dev)
              for f, k in host]
@@ -175,6 +189,8 @@ def batched_bench(reps=20):
             p.run(sp["pts"])
     t_plain = timed(plain)
     out = {"frames": len(specs), "triangles": T,
+           "tuning": {name: {"tile": list(r["best"][:2]), "fuse": r["best"][2]}
+                      for name, r in batch_tuning.items()},
            "plain_f32": {"ms": round(t_plain * 1e3, 3), "triangles_per_s": T / t_plain}}
     sample = [0, 16, 40, 56]          # one frame of each kind for the error report
     for name, dt in (("batched_f32", torch.float32), ("batched_f16", torch.float16)):
@@ -253,8 +269,12 @@ def main():
     # 480x640 frames, 5x5 on the LiDAR frames of the batched and served mixes)
     from paper_2007_12065_amd import tune
     lidar = torch.from_numpy(make_frame("lidar128", 7)).to(dev)
-    tuning = tune.autotune([(frames[0], k.kernel_lap, k.iters_lap, k.kernel_bil, k.iters_bil),
-                            (lidar, 5, 4, 5, 3)], cache_path=None, reps=20)
+    if args.tune_cache and os.path.exists(args.tune_cache) and tune.load_cache(args.tune_cache) > 0:
+        tuning = {name: {"best": tuple(v["best"])}
+                  for name, v in json.load(open(args.tune_cache)).get(tune.arch_name(), {}).items()}
+    else:
+        tuning = tune.autotune([(frames[0], k.kernel_lap, k.iters_lap, k.kernel_bil, k.iters_bil),
+                                (lidar, 5, 4, 5, 3)], cache_path=args.tune_cache, reps=20)
     print(f"[bench] {sets} frame sets ready; warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
 
@@ -350,7 +370,7 @@ def main():
     }
     if args.batched:
         print("[bench] batched 64-frame mix", file=sys.stderr, flush=True)
-        out["batched"] = batched_bench()
+        out["batched"] = batched_bench(tune_cache=args.tune_cache)
     if args.serving_seconds > 0:
         print("[bench] serving stream", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(args.serving_seconds)

@@ -179,13 +179,22 @@ pl_status pl_bilateral(const void *normals_in, const float *centroids, pl_dtype 
  * the bilateral) and fuses up to `fuse` sweeps per launch.  float32 results
  * do not depend on these values (the arithmetic of every output is the same
  * whatever the tiling), and float16 results do not depend on `fuse`.  The
- * table is process-wide; pl_tune_set is meant for a tuner run before work
- * is enqueued (it does not affect launches already enqueued).
+ * single-frame calls read the PL_STAGE_LAPLACIAN / PL_STAGE_BILATERAL
+ * entries; batch plans read the PL_STAGE_BATCH_* entries when they are
+ * created (a launch over many frames favours other shapes than one over a
+ * single frame).  The table is process-wide; pl_tune_set is meant for a
+ * tuner run before work is enqueued (it does not affect launches already
+ * enqueued or plans already created).
  * kernel      odd window size, 3..9.
- * tile_rows * tile_cols <= 16384; the LDS the shape needs must fit 160 KB.
+ * tile_rows * tile_cols <= 16384; the LDS the shape needs must fit 156 KB.
  * Returns PL_ERR_KERNEL / PL_ERR_ARG for an invalid request.
  */
-typedef enum { PL_STAGE_LAPLACIAN = 0, PL_STAGE_BILATERAL = 1 } pl_stage;
+typedef enum {
+    PL_STAGE_LAPLACIAN = 0,
+    PL_STAGE_BILATERAL = 1,
+    PL_STAGE_BATCH_LAPLACIAN = 2,
+    PL_STAGE_BATCH_BILATERAL = 3
+} pl_stage;
 pl_status pl_tune_get(pl_stage stage, int32_t kernel, int32_t *tile_rows, int32_t *tile_cols,
                       int32_t *fuse);
 pl_status pl_tune_set(pl_stage stage, int32_t kernel, int32_t tile_rows, int32_t tile_cols,

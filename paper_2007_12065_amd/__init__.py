@@ -77,7 +77,7 @@ _lib.pl_batch_replay.restype = _i32
 _lib.pl_batch_destroy.argtypes = [_vp]
 _lib.pl_batch_destroy.restype = None
 
-PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL = 0, 1
+PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL, PL_STAGE_BATCH_LAPLACIAN, PL_STAGE_BATCH_BILATERAL = 0, 1, 2, 3
 
 EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc",
            "pl_laplacian_workspace", "pl_laplacian_fused_sweeps", "pl_laplacian", "pl_tri_normals",

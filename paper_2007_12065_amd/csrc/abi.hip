@@ -99,6 +99,12 @@ using namespace pl;
         if (pl_status _s = (x)) return _s; \
     } while (0)
 
+static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
+                  (int)PL_STAGE_BILATERAL == (int)pl::kStageBilateral &&
+                  (int)PL_STAGE_BATCH_LAPLACIAN == (int)pl::kStageBatchLaplacian &&
+                  (int)PL_STAGE_BATCH_BILATERAL == (int)pl::kStageBatchBilateral,
+              "pl_stage and the tuning table's stages must agree");
+
 extern "C" {
 
 __attribute__((visibility("default"))) int32_t pl_version(void) { return 100; }
@@ -266,12 +272,11 @@ __attribute__((visibility("default"))) pl_status pl_tune_get(pl_stage stage, int
                                                              int32_t *tile_cols, int32_t *fuse) {
     g_err[0] = 0;
     PL_TRY(check_kernel(kernel));
-    if (stage != PL_STAGE_LAPLACIAN && stage != PL_STAGE_BILATERAL) {
+    if (stage < PL_STAGE_LAPLACIAN || stage > PL_STAGE_BATCH_BILATERAL) {
         set_error("unknown stage %d", (int)stage);
         return PL_ERR_ARG;
     }
-    const TileCfg c = tile_cfg(stage == PL_STAGE_LAPLACIAN ? kStageLaplacian : kStageBilateral,
-                               kernel / 2);
+    const TileCfg c = tile_cfg(static_cast<Stage>(stage), kernel / 2);
     if (tile_rows) *tile_rows = c.th;
     if (tile_cols) *tile_cols = c.tw;
     if (fuse) *fuse = c.fuse;
@@ -283,12 +288,12 @@ __attribute__((visibility("default"))) pl_status pl_tune_set(pl_stage stage, int
                                                              int32_t tile_cols, int32_t fuse) {
     g_err[0] = 0;
     PL_TRY(check_kernel(kernel));
-    if (stage != PL_STAGE_LAPLACIAN && stage != PL_STAGE_BILATERAL) {
+    if (stage < PL_STAGE_LAPLACIAN || stage > PL_STAGE_BATCH_BILATERAL) {
         set_error("unknown stage %d", (int)stage);
         return PL_ERR_ARG;
     }
-    if (!set_tile_cfg(stage == PL_STAGE_LAPLACIAN ? kStageLaplacian : kStageBilateral,
-                      kernel / 2, TileCfg{tile_rows, tile_cols, fuse})) {
+    if (!set_tile_cfg(static_cast<Stage>(stage), kernel / 2,
+                      TileCfg{tile_rows, tile_cols, fuse})) {
         set_error("tile %d x %d with %d fused sweeps is outside the kernels' limits", tile_rows,
                   tile_cols, fuse);
         return PL_ERR_ARG;

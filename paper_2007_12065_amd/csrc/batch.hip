@@ -264,8 +264,8 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
     int maxlap = 0, maxbil = 0;
     for (int i = 0; i < n; ++i) {
         const pl_frame &f = frames[i];
-        maxlap = std::max(maxlap, passes_for(f.iters_lap, tile_cfg(kStageLaplacian, f.kernel_lap / 2).fuse));
-        maxbil = std::max(maxbil, passes_for(f.iters_bil, tile_cfg(kStageBilateral, f.kernel_bil / 2).fuse));
+        maxlap = std::max(maxlap, passes_for(f.iters_lap, tile_cfg(kStageBatchLaplacian, f.kernel_lap / 2).fuse));
+        maxbil = std::max(maxbil, passes_for(f.iters_bil, tile_cfg(kStageBatchBilateral, f.kernel_bil / 2).fuse));
     }
     b.lap.assign(maxlap, Pass());
     b.bil.assign(maxbil, Pass());
@@ -281,8 +281,8 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         b.mc.count[i] = Mq;
         b.me.count[i] = Mq;
         b.nq.count[i] = (int)(((size_t)Mq * Nq + kNormalsChunk - 1) / kNormalsChunk);
-        const TileCfg cl = tile_cfg(kStageLaplacian, f.kernel_lap / 2);
-        const TileCfg cb = tile_cfg(kStageBilateral, f.kernel_bil / 2);
+        const TileCfg cl = tile_cfg(kStageBatchLaplacian, f.kernel_lap / 2);
+        const TileCfg cb = tile_cfg(kStageBatchBilateral, f.kernel_bil / 2);
         const int ltiles = ((f.N + cl.tw - 1) / cl.tw) * ((f.M + cl.th - 1) / cl.th);
         const int btiles = ((Nq + cb.tw - 1) / cb.tw) * ((Mq + cb.th - 1) / cb.th);
         const int lp = passes_for(f.iters_lap, cl.fuse), bp = passes_for(f.iters_bil, cb.fuse);
@@ -309,8 +309,8 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         const size_t T = 2 * Q;
         o_codes[i] = L.take(Q);
         o_rows[i] = L.take(sizeof(int) * (f.M - 1));
-        const int lp = passes_for(f.iters_lap, tile_cfg(kStageLaplacian, f.kernel_lap / 2).fuse);
-        const int bp = passes_for(f.iters_bil, tile_cfg(kStageBilateral, f.kernel_bil / 2).fuse);
+        const int lp = passes_for(f.iters_lap, tile_cfg(kStageBatchLaplacian, f.kernel_lap / 2).fuse);
+        const int bp = passes_for(f.iters_bil, tile_cfg(kStageBatchBilateral, f.kernel_bil / 2).fuse);
         if (lp > 1) o_lap[i] = L.take(12 * (size_t)f.M * f.N);
         o_nraw[i] = L.take(3 * T * nt_size(ndt));
         if (bp > 1) o_bil[i] = L.take(3 * T * nt_size(ndt));
@@ -343,7 +343,7 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         d.lam = f.lambda;
         d.ka = log2e / (2.0f * f.sigma_length * f.sigma_length);
         d.kb = log2e / (2.0f * f.sigma_angle * f.sigma_angle);
-        const TileCfg cl = tile_cfg(kStageLaplacian, d.Rl), cb = tile_cfg(kStageBilateral, d.Rb);
+        const TileCfg cl = tile_cfg(kStageBatchLaplacian, d.Rl), cb = tile_cfg(kStageBatchBilateral, d.Rb);
         d.lap_th = cl.th; d.lap_tw = cl.tw; d.lap_tiles_x = (f.N + cl.tw - 1) / cl.tw;
         d.bil_th = cb.th; d.bil_tw = cb.tw; d.bil_tiles_x = (f.N - 1 + cb.tw - 1) / cb.tw;
         // sweep passes, the last of each stage landing in the caller's output
@@ -422,7 +422,7 @@ pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
             size_t lds = 0;
             for (int i = 0; i < b.n; ++i) {
                 if (!p.q[r].count[i]) continue;
-                const TileCfg c = tile_cfg(kStageLaplacian, r + 1);
+                const TileCfg c = tile_cfg(kStageBatchLaplacian, r + 1);
                 lds = std::max(lds, lap_lds_bytes(r + 1, p.tab[i].F, c.th, c.tw));
             }
             if (pl_status st = size_grid(p.q[r], lap_k[r], lds)) return st;
@@ -432,7 +432,7 @@ pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
             size_t lds = 0;
             for (int i = 0; i < b.n; ++i) {
                 if (!p.q[r].count[i]) continue;
-                const TileCfg c = tile_cfg(kStageBilateral, r + 1);
+                const TileCfg c = tile_cfg(kStageBatchBilateral, r + 1);
                 lds = std::max(lds, bil_lds_bytes(r + 1, p.tab[i].F, c.th, c.tw));
             }
             if (pl_status st = size_grid(p.q[r], bil_k[r], lds)) return st;

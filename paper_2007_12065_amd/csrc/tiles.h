@@ -19,10 +19,8 @@ constexpr int kTileBlock = 256;        // threads per workgroup for every tile b
 constexpr int kMeshChunk = 4 * kTileBlock;    // columns staged per pass
 
 // Validity codes of quad row u (bit 0: first triangle, bit 1: second) and the
-// row's triangle count.  Points u and u+1 of a 1024-column chunk are read as
-// the contiguous float runs they are, consecutive lanes on consecutive words
-// (coalesced), and a NaN word clears its point's flag in LDS (every writer
-// stores the same 0).  A quad then reads its four corner flags.
+// row's triangle count.  All point loads of a 1024-column chunk are issued
+// before any is used; point validity is staged in LDS.
 __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, int N, int u,
                                                uint8_t *__restrict__ codes,
                                                uint8_t *__restrict__ tri_valid,
@@ -31,26 +29,24 @@ __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, in
     __shared__ int red[kTileBlock / kWave];
     const int Nq = N - 1;
     const float *r0 = pts + (size_t)u * N * 3;
+    const float *r1 = r0 + (size_t)N * 3;
     int cnt = 0;
     for (int v0 = 0; v0 < Nq; v0 += kMeshChunk) {
-        const int np = min(kMeshChunk + 1, N - v0);        // points of this chunk per row
-        for (int k = threadIdx.x; k < np; k += kTileBlock) ok[0][k] = ok[1][k] = 1;
-        __syncthreads();
-        constexpr int kUnroll = 4;
-        const float *src = r0 + 3 * (size_t)v0;
-        for (int k0 = 0; k0 < 3 * np; k0 += kUnroll * kTileBlock) {
-            float w[2][kUnroll];
+        float x[2][5], y[2][5], z[2][5];
 #pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                const int k = k0 + j * kTileBlock + threadIdx.x;
-                w[0][j] = k < 3 * np ? src[k] : 0.f;
-                w[1][j] = k < 3 * np ? src[3 * (size_t)N + k] : 0.f;
-            }
+        for (int j = 0; j < 5; ++j) {
+            const int v = v0 + threadIdx.x + j * kTileBlock;
+            const bool in = (j < 4 || threadIdx.x == 0) && v < N && v <= v0 + kMeshChunk;
+            x[0][j] = in ? r0[3 * v] : 0.f; y[0][j] = in ? r0[3 * v + 1] : 0.f; z[0][j] = in ? r0[3 * v + 2] : 0.f;
+            x[1][j] = in ? r1[3 * v] : 0.f; y[1][j] = in ? r1[3 * v + 1] : 0.f; z[1][j] = in ? r1[3 * v + 2] : 0.f;
+        }
 #pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                const int k = k0 + j * kTileBlock + threadIdx.x;
-                if (is_nan_bits(w[0][j])) ok[0][k / 3] = 0;
-                if (is_nan_bits(w[1][j])) ok[1][k / 3] = 0;
+        for (int j = 0; j < 5; ++j) {
+            const int l = threadIdx.x + j * kTileBlock;
+            if (j < 4 || threadIdx.x == 0) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+                    ok[r][l] = !(is_nan_bits(x[r][j]) || is_nan_bits(y[r][j]) || is_nan_bits(z[r][j]));
             }
         }
         __syncthreads();
@@ -58,14 +54,16 @@ __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, in
         for (int j = 0; j < 4; ++j) {
             const int l = threadIdx.x + j * kTileBlock;
             const int v = v0 + l;
-            if (v < Nq && l < kMeshChunk) {
+            if (v < Nq) {
                 const int p1 = ok[0][l], p2 = ok[0][l + 1], p3 = ok[1][l + 1], p4 = ok[1][l];
                 const int f = p1 & p2 & p3;          // first triangle (p3, p2, p1)
                 const int s = p1 & p3 & p4;          // second triangle (p1, p4, p3)
                 const size_t q = (size_t)u * Nq + v;
                 codes[q] = (uint8_t)(f | (s << 1));
-                if (tri_valid)
-                    *reinterpret_cast<uint16_t *>(tri_valid + 2 * q) = (uint16_t)(f | (s << 8));
+                if (tri_valid) {
+                    tri_valid[2 * q] = (uint8_t)f;
+                    tri_valid[2 * q + 1] = (uint8_t)s;
+                }
                 cnt += f + s;
             }
         }
@@ -413,18 +411,31 @@ template <typename NT>
 __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int N, int Nq, size_t q0,
                                               int nq, NT *__restrict__ normals,
                                               float *__restrict__ centroids, NormalsStage &st) {
-    const size_t ua = q0 / Nq, ub = (q0 + nq - 1) / Nq;
+    // 6 Q < 2^31 (shape check): 32-bit index arithmetic
+    const unsigned ua = (unsigned)q0 / (unsigned)Nq, ub = ((unsigned)q0 + nq - 1) / (unsigned)Nq;
     const size_t P0 = q0 + ua;                              // top-left corner of quad q0
     const int L = (int)(nq + 1 + (ub - ua));                // points per run
     const float *top = pts + 3 * P0, *bot = top + 3 * (size_t)N;
-    for (int k = threadIdx.x; k < 3 * L; k += kTileBlock) {
-        st.f[0][k] = top[k];
-        st.f[1][k] = bot[k];
+    constexpr int kLoads = 3 * 2 * kTileBlock / kTileBlock;   // all in flight at once
+    float wt[kLoads], wb[kLoads];
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+        const int k = j * kTileBlock + threadIdx.x;
+        wt[j] = k < 3 * L ? top[k] : 0.f;
+        wb[j] = k < 3 * L ? bot[k] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+        const int k = j * kTileBlock + threadIdx.x;
+        if (k < 3 * L) {
+            st.f[0][k] = wt[j];
+            st.f[1][k] = wb[j];
+        }
     }
     __syncthreads();
     V3 c0, n0, c1, n1;
     if ((int)threadIdx.x < nq) {
-        const unsigned q = (unsigned)q0 + threadIdx.x;      // 6 Q < 2^31 (shape check)
+        const unsigned q = (unsigned)q0 + threadIdx.x;
         const int o = 3 * (int)(q + q / (unsigned)Nq - (unsigned)P0);
         const float *t = st.f[0] + o, *b = st.f[1] + o;
         quad_geom(V3{t[0], t[1], t[2]}, V3{t[3], t[4], t[5]}, V3{b[3], b[4], b[5]},
@@ -478,18 +489,11 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // exponent shifted by the smallest one, which puts the largest term at 1.
 // Only the lanes that need it take it.
 //
-// Symmetric pairs.  e(i, j) = e(j, i), bit for bit (the differences only
-// change sign), so a quad pair needs its four exponents once.  The window's
-// displacements split into D+ (dy = 0, dx > 0, or dy > 0) and their negatives;
-// a triangle sums its terms in the fixed order: for each d of D+, the two
-// triangles of quad a+d, then the two of quad a-d.  In the last sweep of a
-// tile, each displacement d takes two phases: every tile quad a computes the
-// exponents to a+d, uses them, and leaves them in LDS; the quads of the
-// upstream halo (those with a+d in the tile) do the same; then every tile
-// quad reads the exponents of a-d from LDS.  Each side applies its own shift
-// and exp.  The direct form (both neighbours computed by the quad itself,
-// same order, same bits) serves intermediate sweeps and tiles too large for
-// one quad per thread.
+// Summation order.  The window's displacements split into D+ (dy = 0 and
+// dx > 0, or dy > 0) and their negatives; a triangle sums its terms in a
+// fixed order: for each d of D+, the two triangles of quad a+d, then the two
+// of quad a-d.  The order is the same for every tile shape and fusion depth,
+// so float32 results are too.
 //
 // Off-grid quads and triangles with a NaN normal or centroid are staged with
 // an infinite centroid and a zero normal: infinite exponent, weight exactly 0,
@@ -497,9 +501,8 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // input bits).  Float16-stored normals produced by an intermediate sweep are
 // re-rounded to float16, as if stored between launches, so results do not
 // depend on F.  F = 0 copies the tile (and gathers).
-// LDS: (TQH + 2RF) * (TQW + 2RF) float4 times 5 (centroids and normals of
-// both triangles, the exchanged exponents) or, with F > 1, times 6 (a second
-// normal buffer, which also holds the exponents in the last sweep).
+// LDS: (TQH + 2RF) * (TQW + 2RF) float4 times 4 (centroids and normals of
+// both triangles) or, with F > 1, times 6 (a second normal buffer).
 // ---------------------------------------------------------------------------
 
 constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
@@ -508,20 +511,7 @@ constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
 constexpr int kBilWavesPerSimd = 6;
 constexpr float kBilShiftCap = 52.f;
 __host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW) {
-    return (F > 1 ? 6 : 5) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F);
-}
-
-// Quads of the upstream halo of a TQH x TQW tile (those a quad of the tile
-// reaches through some -d, d in D+): R rows above the tile, R + TQW + R
-// wide, then R columns on either side of the tile's rows.
-__host__ __device__ constexpr int bil_upstream(int R, int TQH, int TQW) {
-    return R * (TQW + 2 * R) + 2 * R * TQH;
-}
-
-// The symmetric last sweep needs one tile quad and at most one halo quad
-// per thread.
-__host__ __device__ constexpr bool bil_symmetric(int R, int TQH, int TQW) {
-    return TQH * TQW <= kTileBlock && bil_upstream(R, TQH, TQW) <= kTileBlock;
+    return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F);
 }
 
 template <typename NT> __device__ __forceinline__ float round_storage(float x);
@@ -642,8 +632,7 @@ __device__ __forceinline__ void bil_close(const BilQuad &q, BilAcc s0, BilAcc s1
     r1 = ok1 ? bil_finish<NT>(s1, q.n1) : q.n1;
 }
 
-// Direct form: both triangles of the quad at LDS index a, every neighbour
-// computed here, in the canonical order.
+// Both triangles of the quad at LDS index a, in the fixed summation order.
 template <int R, typename NT>
 __device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *sn, int a,
                                                 int pitch, int plane, float ka, float kb,
@@ -669,80 +658,6 @@ __device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *
     bil_close<R, NT>(q, s0, s1, sc, sn, a, pitch, plane, r0, r1);
 }
 
-// Symmetric form of a tile's last sweep (see above): thread t owns tile quad
-// t (when t < TQH * TQW) and upstream halo quad t (when t < the halo count);
-// E holds one float4 of exponents per LDS quad.  Every thread of the
-// workgroup must call this (it synchronises).  Returns the filtered pair of
-// the thread's tile quad in r0, r1.
-template <int R, typename NT>
-__device__ __forceinline__ void bil_sweep_symmetric(const float4 *sc, const float4 *sn, float4 *E,
-                                                    int W, int plane, int halo, int TQH, int TQW,
-                                                    float ka, float kb, float4 &r0, float4 &r1) {
-    const int t = threadIdx.x;
-    const bool own = t < TQH * TQW;
-    const int ty = own ? t / TQW : 0, tx = own ? t - ty * TQW : 0;
-    const int a = (ty + halo) * W + tx + halo;
-    // upstream halo quad of this thread, in LDS coordinates (hy, hx)
-    const int nH = bil_upstream(R, TQH, TQW);
-    const bool hal = t < nH;
-    int hy = 0, hx = 0;
-    if (hal) {
-        const int top = R * (TQW + 2 * R);
-        if (t < top) {
-            hy = halo - R + t / (TQW + 2 * R);
-            hx = halo - R + t % (TQW + 2 * R);
-        } else {
-            const int j = t - top, side = j % (2 * R);
-            hy = halo + j / (2 * R);
-            hx = side < R ? halo - R + side : halo + TQW + (side - R);
-        }
-    }
-    const int h = hy * W + hx;
-    const BilQuad q = bil_quad(sc, sn, a, plane, ka, kb);
-    BilAcc s0{0.f, 0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-    for (int i = 0; i < bil_ndplus<R>(); ++i) {
-        int dy, dx;
-        bil_dplus<R>(i, dy, dx);
-        const int off = dy * W + dx;
-        if (own) {                                   // quad a + d: use and publish
-            const int b = a + off;
-            const float4 cb0 = sc[b], cb1 = sc[plane + b], nb0 = sn[b], nb1 = sn[plane + b];
-            const float e00 = bil_pair_e(q.o0, cb0, nb0), e01 = bil_pair_e(q.o0, cb1, nb1);
-            const float e10 = bil_pair_e(q.o1, cb0, nb0), e11 = bil_pair_e(q.o1, cb1, nb1);
-            bil_add(s0, q.m, e00, nb0);
-            bil_add(s0, q.m, e01, nb1);
-            bil_add(s1, q.m, e10, nb0);
-            bil_add(s1, q.m, e11, nb1);
-            E[a] = make_float4(e00, e01, e10, e11);
-        }
-        if (hal) {                                   // halo quad h whose h + d is in the tile
-            const int by = hy + dy - halo, bx = hx + dx - halo;
-            if (by >= 0 && by < TQH && bx >= 0 && bx < TQW) {
-                const float4 c0 = sc[h], c1 = sc[plane + h], n0 = sn[h], n1 = sn[plane + h];
-                const BilOwn g0{c0.x, c0.y, c0.z, n0.x, n0.y, n0.z, ka, kb};
-                const BilOwn g1{c1.x, c1.y, c1.z, n1.x, n1.y, n1.z, ka, kb};
-                const int b = h + off;
-                const float4 cb0 = sc[b], cb1 = sc[plane + b], nb0 = sn[b], nb1 = sn[plane + b];
-                E[h] = make_float4(bil_pair_e(g0, cb0, nb0), bil_pair_e(g0, cb1, nb1),
-                                   bil_pair_e(g1, cb0, nb0), bil_pair_e(g1, cb1, nb1));
-            }
-        }
-        __syncthreads();
-        if (own) {                                   // quad a - d: exponents from its owner
-            const int b = a - off;
-            const float4 e = E[b];                   // e(b_k', a_k) at [2 k' + k]
-            const float4 nb0 = sn[b], nb1 = sn[plane + b];
-            bil_add(s0, q.m, e.x, nb0);
-            bil_add(s0, q.m, e.z, nb1);
-            bil_add(s1, q.m, e.y, nb0);
-            bil_add(s1, q.m, e.w, nb1);
-        }
-        __syncthreads();
-    }
-    if (own) bil_close<R, NT>(q, s0, s1, sc, sn, a, W, plane, r0, r1);
-}
-
 template <int R, typename NT>
 __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float *__restrict__ cen,
                                          NT *__restrict__ nout, int Mq, int Nq, float ka, float kb,
@@ -753,7 +668,7 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     const int H = TQH + 2 * halo, W = TQW + 2 * halo, S = H * W;
     float4 *s_c = lds;                  // [2][S] centroids, w = 1 if usable
     float4 *s_n = lds + 2 * S;          // [2][S] normals
-    float4 *s_m = lds + 4 * S;          // [S] exponents (F = 1) or [2][S] second normals (F > 1)
+    float4 *s_m = lds + 4 * S;          // [2][S] second normal buffer (F > 1)
     const float inf = __builtin_inff();
     const int oy = qy0 - halo, ox = qx0 - halo;
 
@@ -804,9 +719,6 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     }
 
     // last sweep (or the copy when F = 0): the tile itself, to global memory
-    const bool sym = F > 0 && bil_symmetric(R, TQH, TQW);
-    float4 rs0, rs1;
-    if (sym) bil_sweep_symmetric<R, NT>(s_c, cur, nxt, W, S, halo, TQH, TQW, ka, kb, rs0, rs1);
     for (int idx = threadIdx.x; idx < TQH * TQW; idx += kTileBlock) {
         const int ty = idx / TQW, tx = idx - ty * TQW;
         const int qy = qy0 + ty, qx = qx0 + tx;
@@ -816,12 +728,7 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
         if (F > 0) {
             const int a = (ty + halo) * W + tx + halo;
             float4 r[2];
-            if (sym) {
-                r[0] = rs0;
-                r[1] = rs1;
-            } else {
-                bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r[0], r[1]);
-            }
+            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r[0], r[1]);
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 if (s_c[k * S + a].w != 0.f) {

@@ -6,7 +6,14 @@
 
 namespace pl {
 
-enum Stage { kStageLaplacian = 0, kStageBilateral = 1, kNumStages = 2 };
+enum Stage {
+    kStageLaplacian = 0,
+    kStageBilateral = 1,
+    kStageBatchLaplacian = 2,      // the batched path's entries
+    kStageBatchBilateral = 3,
+    kNumStages = 4
+};
+inline bool is_laplacian(Stage s) { return s == kStageLaplacian || s == kStageBatchLaplacian; }
 constexpr int kMaxRadius = 4;                 // kernel sizes 3, 5, 7, 9
 
 struct TileCfg {

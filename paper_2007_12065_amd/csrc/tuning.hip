@@ -16,6 +16,10 @@ TileCfg g_cfg[kNumStages][kMaxRadius + 1] = {
     {{0, 0, 0}, {16, 32, 4}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}},
     // bilateral
     {{0, 0, 0}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}},
+    // batched Laplacian
+    {{0, 0, 0}, {16, 32, 4}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}},
+    // batched bilateral
+    {{0, 0, 0}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}},
 };
 
 // gfx950 LDS per workgroup, less room for the batched kernels' static LDS
@@ -24,8 +28,8 @@ constexpr size_t kLdsMax = 156 * 1024;
 }  // namespace
 
 size_t cfg_lds_bytes(Stage s, int R, TileCfg c) {
-    return s == kStageLaplacian ? lap_lds_bytes(R, c.fuse, c.th, c.tw)
-                                : bil_lds_bytes(R, c.fuse, c.th, c.tw);
+    return is_laplacian(s) ? lap_lds_bytes(R, c.fuse, c.th, c.tw)
+                           : bil_lds_bytes(R, c.fuse, c.th, c.tw);
 }
 
 TileCfg tile_cfg(Stage s, int R) {

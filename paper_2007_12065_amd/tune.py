@@ -4,9 +4,11 @@ For each stage (Laplacian, bilateral) and window size, candidate
 (tile_rows, tile_cols, fuse) shapes are timed with HIP events on a
 representative frame through the single-frame entry points, the fastest is
 installed with pl_tune_set, and the choice is cached in a JSON file keyed by
-the GPU architecture, stage, window size and frame size.  float32 results do
-not depend on the choice (the arithmetic of every output is the same for
-every tiling), so tuning only moves time.
+the GPU architecture, stage, window size and frame size.  The batched path
+has table entries of its own (PL_STAGE_BATCH_*), tuned by timing graph
+replays of a whole batch plan per candidate.  float32 results do not depend
+on the choice (the arithmetic of every output is the same for every tiling),
+so tuning only moves time.
 """
 from __future__ import annotations
 
@@ -26,6 +28,11 @@ BIL_CANDIDATES = {
     5: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (4, 32, 1)],
 }
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pl_tune.json")
+
+
+STAGE_NAMES = {pl.PL_STAGE_LAPLACIAN: "laplacian", pl.PL_STAGE_BILATERAL: "bilateral",
+               pl.PL_STAGE_BATCH_LAPLACIAN: "batch_laplacian",
+               pl.PL_STAGE_BATCH_BILATERAL: "batch_bilateral"}
 
 
 def arch_name(device=None) -> str:
@@ -92,8 +99,54 @@ def autotune(workloads, cache_path: str | None = DEFAULT_CACHE, reps: int = 30) 
     report = {}
     for (stage, k), (pts, size, it) in sorted(reps_by.items(), key=lambda x: x[0]):
         r = tune_stage(stage, k, pts, it, reps)
-        name = ("laplacian" if stage == pl.PL_STAGE_LAPLACIAN else "bilateral") + f"_k{k}"
+        name = STAGE_NAMES[stage] + f"_k{k}"
         report[name] = dict(r, frame=list(pts.shape[:2]))
+    if cache_path:
+        save_cache(cache_path, arch, report)
+    return report
+
+
+def tune_batch_stage(stage: int, kernel: int, frames: list, reps: int = 10,
+                     normal_dtype=None) -> dict:
+    """Time each candidate shape for a batched stage (PL_STAGE_BATCH_*) by
+    graph replays of a plan over `frames` (Batch frame dicts); install and
+    return the fastest.  Plans read the table when created, so each
+    candidate gets its own plan."""
+    normal_dtype = normal_dtype or torch.float32
+    lap = stage == pl.PL_STAGE_BATCH_LAPLACIAN
+    cands = (LAP_CANDIDATES if lap else BIL_CANDIDATES).get(kernel, [(8, 32, 1)])
+    before = pl.pl_tune_get(stage, kernel)
+    times = {}
+    for cfg in cands:
+        try:
+            pl.pl_tune_set(stage, kernel, *cfg)
+        except pl.PLError:
+            continue
+        b = pl.Batch(frames, normal_dtype)
+        try:
+            b.run()
+            b.capture()
+            times[cfg] = _time(b.replay, reps)
+        finally:
+            b.close()
+    if not times:
+        pl.pl_tune_set(stage, kernel, *before)
+        return {"best": before, "times_us": {}}
+    best = min(times, key=times.get)
+    pl.pl_tune_set(stage, kernel, *best)
+    return {"best": best, "times_us": {f"{a}x{b}/{f}": round(t, 2) for (a, b, f), t in times.items()},
+            "previous": before}
+
+
+def autotune_batch(frames: list, cache_path: str | None = DEFAULT_CACHE, reps: int = 10) -> dict:
+    """Tune the batched path's entries for every window size `frames` use
+    (Batch frame dicts), on the whole batch; cached like autotune()."""
+    arch = arch_name()
+    report = {}
+    for stage, key in ((pl.PL_STAGE_BATCH_LAPLACIAN, "kernel_lap"), (pl.PL_STAGE_BATCH_BILATERAL, "kernel_bil")):
+        for k in sorted({int(f[key]) for f in frames}):
+            r = tune_batch_stage(stage, k, frames, reps)
+            report[STAGE_NAMES[stage] + f"_k{k}"] = dict(r, frame=[len(frames)])
     if cache_path:
         save_cache(cache_path, arch, report)
     return report
@@ -125,9 +178,12 @@ def load_cache(path: str = DEFAULT_CACHE) -> int:
     except (OSError, ValueError):
         return 0
     n = 0
+    by_name = {v: k for k, v in STAGE_NAMES.items()}
     for name, entry in data.items():
         stage_name, k = name.rsplit("_k", 1)
-        stage = pl.PL_STAGE_LAPLACIAN if stage_name == "laplacian" else pl.PL_STAGE_BILATERAL
+        if stage_name not in by_name:
+            continue
+        stage = by_name[stage_name]
         try:
             pl.pl_tune_set(stage, int(k), *entry["best"])
             n += 1

@@ -97,3 +97,26 @@ def test_normals_and_bilateral_argument_errors(pl):
     assert bil(tm=C + 65536) == -1            # gather without a destination
     assert bil(nout=A) == -4
     assert bil(it=2) == -5
+
+
+def test_tuning_table_stages(pl):
+    # four independent tables: single-frame and batched, Laplacian and bilateral
+    saved = {(s, k): pl.pl_tune_get(s, k) for s in range(4) for k in (3, 5)}
+    try:
+        for s in range(4):
+            pl.pl_tune_set(s, 3, 4 + s, 32, 1)
+        for s in range(4):
+            assert pl.pl_tune_get(s, 3) == (4 + s, 32, 1)
+        assert pl.pl_tune_get(pl.PL_STAGE_BATCH_BILATERAL, 5) == saved[(3, 5)]
+        with pytest.raises(pl.PLError):
+            pl.pl_tune_set(4, 3, 8, 32, 1)                   # no such stage
+        with pytest.raises(pl.PLError):
+            pl.pl_tune_set(pl.PL_STAGE_BATCH_LAPLACIAN, 3, 8, 32, 0)   # fuse < 1
+        with pytest.raises(pl.PLError):
+            pl.pl_tune_set(pl.PL_STAGE_BATCH_BILATERAL, 9, 128, 128, 4)  # LDS too large
+        with pytest.raises(pl.PLError):
+            pl.pl_tune_get(0, 4)                              # even window
+        assert pl.pl_tune_get(pl.PL_STAGE_BATCH_LAPLACIAN, 3) == (6, 32, 1)
+    finally:
+        for (s, k), v in saved.items():
+            pl.pl_tune_set(s, k, *v)

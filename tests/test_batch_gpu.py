@@ -105,6 +105,27 @@ def test_batch_more_frames_than_the_lds_table(pl):
     b.close()
 
 
+@pytest.mark.parametrize("dtype_name", ["float32", "float16"])
+def test_batch_of_full_size_frames_equals_single_frames(pl, dtype_name):
+    # four 480x640 (3x3) and four 128x2048 (5x5) frames: thousands of tiles
+    # per radius in each batched launch
+    import torch
+    dtype = getattr(torch, dtype_name)
+    specs = []
+    for kind, seed in [("rgbd", 41), ("rgbd", 42), ("rgbd", 43), ("rgbd", 44),
+                       ("lidar128", 45), ("lidar128", 46), ("lidar128", 47), ("lidar128", 48)]:
+        k = KINDS[kind]
+        specs.append(spec(make_frame(kind, seed), k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
+                          k.sigma_length, k.sigma_angle, k.iters_bil))
+    print("[case] full-size batch,", dtype_name, flush=True)
+    b = pl.Batch(specs, dtype)
+    b.run()
+    torch.cuda.synchronize()
+    for i, sp in enumerate(specs):
+        assert_frame_equal(b.outputs[i], single(pl, sp, dtype), f"frame {i}")
+    b.close()
+
+
 def test_batch_graph_replay(pl):
     import torch
     specs = mixed_specs()[:6]
@@ -188,20 +209,23 @@ def test_tiling_invariance(pl):
             pl.pl_tune_set(0, 5, th, tw, fu)
             assert np.array_equal(host(pl.pl_laplacian(pts, 5, 1.0, 4)).view(np.uint8),
                                   ref_lap.view(np.uint8))
-        # (16, 32, *) tiles exceed one quad per thread: their last sweep takes
-        # the direct form, the others the symmetric exchange; same bits
         for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 32, 3), (2, 128, 1), (16, 32, 1), (16, 32, 2)]:
             print("[case] bilateral tile", th, tw, fu, flush=True)
             pl.pl_tune_set(1, 3, th, tw, fu)
             assert np.array_equal(host(pl.pl_bilateral(n, c, 3, 0.1, 0.1, 3)[0]).view(np.uint8),
                                   ref_bil.view(np.uint8))
-        n5, c5 = pl.pl_tri_normals(pts)
-        ref5 = host(pl.pl_bilateral(n5, c5, 5, 0.1, 0.1, 3)[0]).copy()
-        for th, tw, fu in [(16, 32, 1), (4, 64, 2), (16, 16, 1)]:
-            print("[case] bilateral 5x5 tile", th, tw, fu, flush=True)
-            pl.pl_tune_set(1, 5, th, tw, fu)
-            assert np.array_equal(host(pl.pl_bilateral(n5, c5, 5, 0.1, 0.1, 3)[0]).view(np.uint8),
-                                  ref5.view(np.uint8))
+        # a 1100 x 1100 frame (thousands of tiles), 3x3 and 5x5
+        big = dev_t(random_grid(1100, 1100, 33, nan_frac=0.05, noise=0.01))
+        nb, cb = pl.pl_tri_normals(big)
+        for k in (3, 5):
+            pl.pl_tune_set(1, k, 8, 32, 1)
+            refb = host(pl.pl_bilateral(nb, cb, k, 0.1, 0.1, 2)[0]).copy()
+            for th, tw, fu in [(16, 32, 1), (16, 32, 2), (4, 64, 1), (16, 16, 2)]:
+                print(f"[case] bilateral {k}x{k} 1100x1100 tile", th, tw, fu, flush=True)
+                pl.pl_tune_set(1, k, th, tw, fu)
+                assert np.array_equal(host(pl.pl_bilateral(nb, cb, k, 0.1, 0.1, 2)[0]).view(np.uint8),
+                                      refb.view(np.uint8))
+            pl.pl_tune_set(1, k, *saved[1 if k == 3 else 2])
     finally:
         pl.pl_tune_set(0, 5, *saved[0])
         pl.pl_tune_set(1, 3, *saved[1])
@@ -239,3 +263,33 @@ def test_autotune_installs_a_candidate_and_keeps_results(pl, tmp_path):
     finally:
         pl.pl_tune_set(0, 3, *saved[0])
         pl.pl_tune_set(1, 3, *saved[1])
+
+
+def test_autotune_batch_stages(pl, tmp_path):
+    import torch
+    from paper_2007_12065_amd import tune
+    specs = [mixed_specs()[0], mixed_specs()[2]]          # 3x3 and 5x5 frames
+    saved = {(s, k): pl.pl_tune_get(s, k) for s in (2, 3) for k in (3, 5)}
+    try:
+        cache = str(tmp_path / "tune.json")
+        rep = tune.autotune_batch(specs, cache_path=cache, reps=2)
+        assert set(rep) == {"batch_laplacian_k3", "batch_laplacian_k5", "batch_bilateral_k3",
+                            "batch_bilateral_k5"}
+        for name, r in rep.items():
+            k = int(name[-1])
+            cands = tune.LAP_CANDIDATES if "laplacian" in name else tune.BIL_CANDIDATES
+            assert tuple(r["best"]) in cands[k]
+        assert pl.pl_tune_get(pl.PL_STAGE_BATCH_BILATERAL, 5) == tuple(rep["batch_bilateral_k5"]["best"])
+        b = pl.Batch(specs, torch.float32)
+        b.run()
+        torch.cuda.synchronize()
+        for i, sp in enumerate(specs):
+            assert_frame_equal(b.outputs[i], single(pl, sp, torch.float32), f"tuned frame {i}")
+        b.close()
+        for (s, k), v in saved.items():
+            pl.pl_tune_set(s, k, *v)
+        assert tune.load_cache(cache) == 4
+        assert pl.pl_tune_get(pl.PL_STAGE_BATCH_BILATERAL, 5) == tuple(rep["batch_bilateral_k5"]["best"])
+    finally:
+        for (s, k), v in saved.items():
+            pl.pl_tune_set(s, k, *v)
