@@ -16,6 +16,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-Wall", "-Wno-unused-function",
+    # no implicit contraction: the kernels write every fused multiply-add as
+    # fmaf, so a tile body gives the same bits in every kernel it is inlined in
+    "-ffp-contract=off",
     # keep the compiler from emitting packed FP32 (v_pk_*_f32) instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

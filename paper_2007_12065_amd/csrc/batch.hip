@@ -15,8 +15,10 @@
 //   k_batch_mesh_count tiles = (frame, quad row)        -> codes, row counts
 //   k_batch_mesh_emit  tiles = (frame, quad row)        -> T_map, T, HE, |T|
 //   k_batch_laplacian  one launch per sweep pass, tiles = (frame, point tile)
-//   k_batch_normals    tiles = (frame, 1024 quads)      -> raw normals, centroids
 //   k_batch_bilateral  one launch per sweep pass, tiles = (frame, quad tile);
+//                      the first pass computes the raw normals and centroids
+//                      from the smoothed points while staging its tiles (and
+//                      writes the centroids), so there is no normals stage;
 //                      the frame's last pass gathers onto T
 // Every tile runs the same device body as the single-frame kernels
 // (tiles.h), so each frame's outputs equal its single-frame results.
@@ -48,7 +50,7 @@ namespace {
 struct BFrame {
     const float *pts;
     float *pts_out, *lap_tmp;
-    void *nraw, *normals, *bil_tmp;
+    void *normals, *bil_tmp;
     float *centroids;
     uint8_t *tri_valid, *codes;
     int32_t *tri_map, *triangles, *halfedges, *n_tri;
@@ -158,23 +160,8 @@ __global__ __launch_bounds__(kTileBlock) void k_batch_laplacian(const BFrame *__
                 p.F, f.lap_th, f.lap_tw, ty0, tx0, lds);
 }
 
-constexpr int kNormalsChunk = 4 * kTileBlock;   // quads per normals tile
-
-template <typename NT>
-__global__ __launch_bounds__(kTileBlock) void k_batch_normals(const BFrame *__restrict__ fr,
-                                                              QueueDev Q, int n) {
-    PL_QUEUE_TILE(Q, n, t)
-    const BFrame &f = fr[t.x];
-    __shared__ NormalsStage st;
-    const size_t Qn = (size_t)f.Mq * f.Nq;
-    for (size_t q0 = (size_t)t.y * kNormalsChunk; q0 < Qn && q0 < (size_t)(t.y + 1) * kNormalsChunk;
-         q0 += kTileBlock) {
-        const int nq = (int)(Qn - q0 < (size_t)kTileBlock ? Qn - q0 : (size_t)kTileBlock);
-        normals_block<NT>(f.pts_out, f.N, f.Nq, q0, nq, static_cast<NT *>(f.nraw), f.centroids, st);
-    }
-}
-
-template <int R, typename NT>
+// FromPts: the first pass (raw normals and centroids from the points).
+template <int R, typename NT, bool FromPts>
 __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_batch_bilateral(const BFrame *__restrict__ fr,
                                                                 const PassFrame *__restrict__ pass,
                                                                 QueueDev Q, int n) {
@@ -183,9 +170,10 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_batch_bilatera
     const BFrame &f = fr[t.x];
     const PassFrame &p = pass[t.x];
     const int qy0 = (t.y / f.bil_tiles_x) * f.bil_th, qx0 = (t.y % f.bil_tiles_x) * f.bil_tw;
-    bil_tile<R, NT>(static_cast<const NT *>(p.src), f.centroids, static_cast<NT *>(p.dst), f.Mq,
-                    f.Nq, f.ka, f.kb, p.F, f.bil_th, f.bil_tw, qy0, qx0,
-                    p.gather ? f.tri_map : nullptr, static_cast<NT *>(f.normals_T), lds);
+    bil_tile<R, NT, FromPts>(FromPts ? nullptr : static_cast<const NT *>(p.src), f.centroids,
+                             static_cast<NT *>(p.dst), f.Mq, f.Nq, f.ka, f.kb, p.F, f.bil_th,
+                             f.bil_tw, qy0, qx0, p.gather ? f.tri_map : nullptr,
+                             static_cast<NT *>(f.normals_T), lds, f.pts_out, f.centroids);
 }
 
 // ---------------------------------------------------------------------------
@@ -229,7 +217,7 @@ struct pl_batch_s {
     uint8_t *ws = nullptr;
     size_t off_frames = 0, off_queues = 0, off_ones = 0;
     int n_queues = 0;              // stage queues with any tile, in table order
-    pl::HostQueue mc, me, nq;      // mesh count, mesh emit, normals
+    pl::HostQueue mc, me;          // mesh count, mesh emit
     std::vector<pl::Pass> lap, bil;
     hipGraphExec_t graph = nullptr;
 };
@@ -239,7 +227,7 @@ namespace pl {
 namespace {
 
 std::vector<HostQueue *> all_queues(pl_batch_s &b) {
-    std::vector<HostQueue *> qs = {&b.mc, &b.me, &b.nq};
+    std::vector<HostQueue *> qs = {&b.mc, &b.me};
     for (auto *passes : {&b.lap, &b.bil})
         for (auto &p : *passes)
             for (HostQueue &q : p.q)
@@ -271,7 +259,7 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
     b.bil.assign(maxbil, Pass());
     for (auto &p : b.lap) { p.tab.assign(n, PassFrame{}); p.off = L.take(sizeof(PassFrame) * n); }
     for (auto &p : b.bil) { p.tab.assign(n, PassFrame{}); p.off = L.take(sizeof(PassFrame) * n); }
-    for (HostQueue *q : {&b.mc, &b.me, &b.nq}) q->count.assign(n, 0);
+    for (HostQueue *q : {&b.mc, &b.me}) q->count.assign(n, 0);
     for (auto *passes : {&b.lap, &b.bil})
         for (auto &p : *passes)
             for (HostQueue &q : p.q) q.count.assign(n, 0);
@@ -280,7 +268,6 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         const int Mq = f.M - 1, Nq = f.N - 1;
         b.mc.count[i] = Mq;
         b.me.count[i] = Mq;
-        b.nq.count[i] = (int)(((size_t)Mq * Nq + kNormalsChunk - 1) / kNormalsChunk);
         const TileCfg cl = tile_cfg(kStageBatchLaplacian, f.kernel_lap / 2);
         const TileCfg cb = tile_cfg(kStageBatchBilateral, f.kernel_bil / 2);
         const int ltiles = ((f.N + cl.tw - 1) / cl.tw) * ((f.M + cl.th - 1) / cl.th);
@@ -302,7 +289,7 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
     const size_t table_end = L.off;
     // per-frame scratch
     std::vector<BFrame> bf(n);
-    std::vector<size_t> o_codes(n), o_rows(n), o_lap(n, 0), o_nraw(n), o_bil(n, 0);
+    std::vector<size_t> o_codes(n), o_rows(n), o_lap(n, 0), o_bil(n, 0);
     for (int i = 0; i < n; ++i) {
         const pl_frame &f = frames[i];
         const size_t Q = (size_t)(f.M - 1) * (f.N - 1);
@@ -312,7 +299,6 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         const int lp = passes_for(f.iters_lap, tile_cfg(kStageBatchLaplacian, f.kernel_lap / 2).fuse);
         const int bp = passes_for(f.iters_bil, tile_cfg(kStageBatchBilateral, f.kernel_bil / 2).fuse);
         if (lp > 1) o_lap[i] = L.take(12 * (size_t)f.M * f.N);
-        o_nraw[i] = L.take(3 * T * nt_size(ndt));
         if (bp > 1) o_bil[i] = L.take(3 * T * nt_size(ndt));
     }
     if (!plan) return L.off;
@@ -325,7 +311,6 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         d.codes = base + o_codes[i];
         d.row_count = reinterpret_cast<int *>(base + o_rows[i]);
         d.lap_tmp = o_lap[i] ? reinterpret_cast<float *>(base + o_lap[i]) : nullptr;
-        d.nraw = base + o_nraw[i];
         d.bil_tmp = o_bil[i] ? static_cast<void *>(base + o_bil[i]) : nullptr;
         d.pts = f.pts;
         d.pts_out = f.pts_out;
@@ -359,7 +344,7 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         }
         const int bp = passes_for(f.iters_bil, cb.fuse);
         left = f.iters_bil;
-        src = d.nraw;
+        src = f.pts_out;                 // first pass: from the smoothed points
         for (int p = 0; p < bp; ++p) {
             const int F = left < cb.fuse ? left : cb.fuse;
             left -= F;
@@ -410,13 +395,14 @@ template <typename NT>
 pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
     if (pl_status st = size_grid(b.mc, (const void *)k_batch_mesh_count, 0)) return st;
     if (pl_status st = size_grid(b.me, (const void *)k_batch_mesh_emit, 0)) return st;
-    if (pl_status st = size_grid(b.nq, (const void *)k_batch_normals<NT>, 0)) return st;
     static const void *const lap_k[kMaxRadius] = {
         (const void *)k_batch_laplacian<1>, (const void *)k_batch_laplacian<2>,
         (const void *)k_batch_laplacian<3>, (const void *)k_batch_laplacian<4>};
-    static const void *const bil_k[kMaxRadius] = {
-        (const void *)k_batch_bilateral<1, NT>, (const void *)k_batch_bilateral<2, NT>,
-        (const void *)k_batch_bilateral<3, NT>, (const void *)k_batch_bilateral<4, NT>};
+    static const void *const bil_k[2][kMaxRadius] = {
+        {(const void *)k_batch_bilateral<1, NT, false>, (const void *)k_batch_bilateral<2, NT, false>,
+         (const void *)k_batch_bilateral<3, NT, false>, (const void *)k_batch_bilateral<4, NT, false>},
+        {(const void *)k_batch_bilateral<1, NT, true>, (const void *)k_batch_bilateral<2, NT, true>,
+         (const void *)k_batch_bilateral<3, NT, true>, (const void *)k_batch_bilateral<4, NT, true>}};
     for (Pass &p : b.lap)
         for (int r = 0; r < kMaxRadius; ++r) {
             size_t lds = 0;
@@ -427,15 +413,16 @@ pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
             }
             if (pl_status st = size_grid(p.q[r], lap_k[r], lds)) return st;
         }
-    for (Pass &p : b.bil)
+    for (size_t pi = 0; pi < b.bil.size(); ++pi)
         for (int r = 0; r < kMaxRadius; ++r) {
+            Pass &p = b.bil[pi];
             size_t lds = 0;
             for (int i = 0; i < b.n; ++i) {
                 if (!p.q[r].count[i]) continue;
                 const TileCfg c = tile_cfg(kStageBatchBilateral, r + 1);
                 lds = std::max(lds, bil_lds_bytes(r + 1, p.tab[i].F, c.th, c.tw));
             }
-            if (pl_status st = size_grid(p.q[r], bil_k[r], lds)) return st;
+            if (pl_status st = size_grid(p.q[r], bil_k[pi == 0][r], lds)) return st;
         }
     return PL_OK;
 }
@@ -469,20 +456,28 @@ pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s) {
             if (pl_status st = hip_check(hipGetLastError(), "k_batch_laplacian")) return st;
         }
     }
-    k_batch_normals<NT><<<b.nq.grid, kTileBlock, 0, s>>>(fr, dev_queue(b, b.nq), n);
-    if (pl_status st = hip_check(hipGetLastError(), "k_batch_normals")) return st;
-    for (const Pass &p : b.bil) {
+    for (size_t pi = 0; pi < b.bil.size(); ++pi) {
+        const Pass &p = b.bil[pi];
         const PassFrame *pt = reinterpret_cast<const PassFrame *>(b.ws + p.off);
         for (int r = 0; r < kMaxRadius; ++r) {
             const HostQueue &q = p.q[r];
             if (q.max_tiles == 0) continue;
             const dim3 g(q.grid), blk(kTileBlock);
             const QueueDev d = dev_queue(b, q);
-            switch (r + 1) {
-            case 1: k_batch_bilateral<1, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
-            case 2: k_batch_bilateral<2, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
-            case 3: k_batch_bilateral<3, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
-            default: k_batch_bilateral<4, NT><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+            if (pi == 0) {
+                switch (r + 1) {
+                case 1: k_batch_bilateral<1, NT, true><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                case 2: k_batch_bilateral<2, NT, true><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                case 3: k_batch_bilateral<3, NT, true><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                default: k_batch_bilateral<4, NT, true><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                }
+            } else {
+                switch (r + 1) {
+                case 1: k_batch_bilateral<1, NT, false><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                case 2: k_batch_bilateral<2, NT, false><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                case 3: k_batch_bilateral<3, NT, false><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                default: k_batch_bilateral<4, NT, false><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
+                }
             }
             if (pl_status st = hip_check(hipGetLastError(), "k_batch_bilateral")) return st;
         }

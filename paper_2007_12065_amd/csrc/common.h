@@ -55,7 +55,17 @@ __device__ __forceinline__ int wave_sum(int x) {
 __device__ __forceinline__ float ld_f(const float *p) { return *p; }
 __device__ __forceinline__ float ld_f(const __half *p) { return __half2float(*p); }
 __device__ __forceinline__ void st_f(float *p, float v) { *p = v; }
-__device__ __forceinline__ void st_f(__half *p, float v) { *p = __float2half_rn(v); }
+// The value as a rounded float32, opaque to the optimiser (an empty asm with
+// a VGPR operand, no instruction): without it the compiler may fuse the
+// product that produced v into the float->half conversion (v_fma_mix*),
+// rounding once to half instead of to float and then to half -- and do so in
+// some inlining contexts only, so that one tile body would give different
+// float16 bits in different kernels.
+__device__ __forceinline__ float f32_rounded(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ void st_f(__half *p, float v) { *p = __float2half_rn(f32_rounded(v)); }
 
 // ---- host side -----------------------------------------------------------
 

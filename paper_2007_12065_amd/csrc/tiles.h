@@ -372,9 +372,10 @@ __device__ __forceinline__ void tri_geom(const V3 &a, const V3 &b, const V3 &c, 
     cen.z = (a.z + b.z + c.z) * third;
     const float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
     const float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
-    const float nx = e1y * e2z - e1z * e2y;
-    const float ny = e1z * e2x - e1x * e2z;
-    const float nz = e1x * e2y - e1y * e2x;
+    // explicit fused forms: the same bits wherever this is inlined
+    const float nx = fmaf(e1y, e2z, -(e1z * e2y));
+    const float ny = fmaf(e1z, e2x, -(e1x * e2z));
+    const float nz = fmaf(e1x, e2y, -(e1y * e2x));
     const float l2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
     if (l2 > 0.f) {
         const float k = __builtin_amdgcn_rsqf(l2);
@@ -393,6 +394,15 @@ __device__ __forceinline__ void quad_geom(const V3 &p1, const V3 &p2, const V3 &
     c0 = nan3; n0 = nan3; c1 = nan3; n1 = nan3;
     if (v1 & v2 & v3) tri_geom(p3, p2, p1, c0, n0);     // first triangle
     if (v1 & v3 & v4) tri_geom(p1, p4, p3, c1, n1);     // second triangle
+}
+
+// Quad (qy, qx) of a frame with N points per row: centroids and normals.
+__device__ __forceinline__ void quad_geom_at(const float *__restrict__ pts, int N, int qy, int qx,
+                                             V3 &c0, V3 &n0, V3 &c1, V3 &n1) {
+    const float *r0 = pts + 3 * ((size_t)qy * N + qx);
+    const float *r1 = r0 + 3 * (size_t)N;
+    quad_geom(V3{r0[0], r0[1], r0[2]}, V3{r0[3], r0[4], r0[5]}, V3{r1[3], r1[4], r1[5]},
+              V3{r1[0], r1[1], r1[2]}, c0, n0, c1, n1);
 }
 
 // Up to kTileBlock consecutive quads [q0, q0 + nq), one per thread, q0 a
@@ -517,7 +527,7 @@ __host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQ
 template <typename NT> __device__ __forceinline__ float round_storage(float x);
 template <> __device__ __forceinline__ float round_storage<float>(float x) { return x; }
 template <> __device__ __forceinline__ float round_storage<__half>(float x) {
-    return __half2float(__float2half_rn(x));
+    return __half2float(__float2half_rn(f32_rounded(x)));
 }
 
 struct BilOwn {
@@ -658,12 +668,18 @@ __device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *
     bil_close<R, NT>(q, s0, s1, sc, sn, a, pitch, plane, r0, r1);
 }
 
-template <int R, typename NT>
+// FromPts: the raw normals and centroids are not read but computed here from
+// the (smoothed) points `pts` exactly as normals_quad computes and stores
+// them (normals rounded to NT), and the tile's centroids are written to
+// `cen` -- the batched path's first pass, which then needs no normals
+// stage.  Otherwise nin / cen are the stored raw normals and centroids.
+template <int R, typename NT, bool FromPts = false>
 __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float *__restrict__ cen,
                                          NT *__restrict__ nout, int Mq, int Nq, float ka, float kb,
                                          int F, int TQH, int TQW, int qy0, int qx0,
                                          const int32_t *__restrict__ tri_map, NT *__restrict__ nT,
-                                         float4 *lds) {
+                                         float4 *lds, const float *__restrict__ pts = nullptr,
+                                         float *__restrict__ cen_out = nullptr) {
     const int halo = R * F;
     const int H = TQH + 2 * halo, W = TQW + 2 * halo, S = H * W;
     float4 *s_c = lds;                  // [2][S] centroids, w = 1 if usable
@@ -681,8 +697,17 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
             if (qy >= 0 && qy < Mq && qx >= 0 && qx < Nq) {
                 const size_t q = (size_t)qy * Nq + qx;
                 float n[6], c[6];
+                if constexpr (FromPts) {
+                    V3 g[4];
+                    quad_geom_at(pts, Nq + 1, qy, qx, g[0], g[1], g[2], g[3]);
+                    c[0] = g[0].x; c[1] = g[0].y; c[2] = g[0].z; c[3] = g[2].x; c[4] = g[2].y; c[5] = g[2].z;
+                    n[0] = round_storage<NT>(g[1].x); n[1] = round_storage<NT>(g[1].y);
+                    n[2] = round_storage<NT>(g[1].z); n[3] = round_storage<NT>(g[3].x);
+                    n[4] = round_storage<NT>(g[3].y); n[5] = round_storage<NT>(g[3].z);
+                } else {
 #pragma unroll
-                for (int i = 0; i < 6; ++i) { n[i] = ld_f(nin + 6 * q + i); c[i] = cen[6 * q + i]; }
+                    for (int i = 0; i < 6; ++i) { n[i] = ld_f(nin + 6 * q + i); c[i] = cen[6 * q + i]; }
+                }
                 bool ok0 = true, ok1 = true;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
@@ -725,6 +750,20 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
         if (qy >= Mq || qx >= Nq) continue;
         const size_t q = (size_t)qy * Nq + qx;
         NT v[6];
+        NT raw[6];                           // raw normals as stored (FromPts)
+        if constexpr (FromPts) {
+            V3 c0, n0, c1, n1;
+            quad_geom_at(pts, Nq + 1, qy, qx, c0, n0, c1, n1);
+            cen_out[6 * q + 0] = c0.x; cen_out[6 * q + 1] = c0.y; cen_out[6 * q + 2] = c0.z;
+            cen_out[6 * q + 3] = c1.x; cen_out[6 * q + 4] = c1.y; cen_out[6 * q + 5] = c1.z;
+            st_f(&raw[0], n0.x); st_f(&raw[1], n0.y); st_f(&raw[2], n0.z);
+            st_f(&raw[3], n1.x); st_f(&raw[4], n1.y); st_f(&raw[5], n1.z);
+        }
+        // the stored raw normal i of this quad
+        auto raw_at = [&](int i) -> NT {
+            if constexpr (FromPts) return raw[i];
+            else return nin[6 * q + i];
+        };
         if (F > 0) {
             const int a = (ty + halo) * W + tx + halo;
             float4 r[2];
@@ -734,14 +773,14 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
                 if (s_c[k * S + a].w != 0.f) {
                     st_f(&v[3 * k], r[k].x); st_f(&v[3 * k + 1], r[k].y); st_f(&v[3 * k + 2], r[k].z);
                 } else {                       // missing triangle: input bits unchanged
-                    v[3 * k] = nin[6 * q + 3 * k];
-                    v[3 * k + 1] = nin[6 * q + 3 * k + 1];
-                    v[3 * k + 2] = nin[6 * q + 3 * k + 2];
+                    v[3 * k] = raw_at(3 * k);
+                    v[3 * k + 1] = raw_at(3 * k + 1);
+                    v[3 * k + 2] = raw_at(3 * k + 2);
                 }
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) v[i] = nin[6 * q + i];
+            for (int i = 0; i < 6; ++i) v[i] = raw_at(i);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) nout[6 * q + i] = v[i];
