@@ -12,6 +12,10 @@ continuous batching on one GPU.
 * Continuous batching.  The next step is enqueued as soon as requests are
   waiting, while earlier steps may still be on the GPU: frames that arrive
   during a step join the next one instead of waiting for the queue to drain.
+* Input copies.  A frame's points are copied into its slot on a copy stream
+  of their own, so the copies of the next step overlap the running step;
+  the step waits for its copies by event.  Frames may come from pinned host
+  memory (the copy crosses PCIe) or already sit in device memory.
 * Latency.  Arrival (host clock) to the completion of the frame's step,
   taken from a GPU event's timestamp on the same clock.
 
@@ -42,6 +46,17 @@ class FrameClass:
     sigma_length: float
     sigma_angle: float
     iters_bil: int
+
+
+def frame_sources(torch, frames: dict) -> dict:
+    """Per class, the frames requests copy from: device tensors are used as
+    they are, host arrays are pinned (so copies are asynchronous)."""
+    out = {}
+    for k, v in frames.items():
+        out[k] = [f if isinstance(f, torch.Tensor) and f.is_cuda else
+                  (f if isinstance(f, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(f))).pin_memory()
+                  for f in v]
+    return out
 
 
 def slot_bytes(c: FrameClass, normal_bytes: int = 2, lap_fuse: int = 4, bil_fuse: int = 1) -> int:
@@ -128,7 +143,8 @@ class Request:
     status: str = ""
 
 
-def run_stream(reqs: list, pool: SlotPool, executor, clock, sleep, max_inflight: int = 2) -> dict:
+def run_stream(reqs: list, pool: SlotPool, executor, clock, sleep, max_inflight: int = 2,
+               on_done=None) -> dict:
     """Continuous batching over an arrival-ordered request list.
 
     `executor` provides: n (frames the current plan spans),
@@ -136,9 +152,12 @@ def run_stream(reqs: list, pool: SlotPool, executor, clock, sleep, max_inflight:
     ready(handle) -> bool, wait(handle) -> completion time (same clock as
     arrivals), and rebuild() (re-plan after the pool grew; called with no
     step in flight).  `clock()` gives seconds since the stream started and
-    `sleep(dt)` waits.  Every request ends ADMITTED with a completion time or
-    REJECTED; the loop always terminates."""
-    waiting = collections.deque()
+    `sleep(dt)` waits.  `on_done(request, slot)`, if given, runs when a
+    request's step has completed and before its slot is released (its
+    outputs are still in the slot).  Every request ends ADMITTED with a
+    completion time or REJECTED; the loop always terminates."""
+    waiting = collections.OrderedDict()       # class -> FIFO of waiting requests
+    nwait = 0
     inflight = collections.deque()            # (handle, [(slot, request)])
     nxt = 0
     stats = {"steps": 0, "plan_rebuilds": 0, "max_step": 0}
@@ -149,50 +168,62 @@ def run_stream(reqs: list, pool: SlotPool, executor, clock, sleep, max_inflight:
             done = executor.wait(h)
             for s, r in members:
                 r.done = done
+                if on_done is not None:
+                    on_done(r, s)
                 pool.release(s)
             block_one = False
 
-    while nxt < len(reqs) or waiting or inflight:
+    while nxt < len(reqs) or nwait or inflight:
         now = clock()
         while nxt < len(reqs) and reqs[nxt].arrival <= now:
-            waiting.append(reqs[nxt])
+            waiting.setdefault(reqs[nxt].cls, collections.deque()).append(reqs[nxt])
+            nwait += 1
             nxt += 1
         retire(False)
-        if waiting and len(inflight) >= max_inflight:
+        if nwait and len(inflight) >= max_inflight:
             retire(True)                      # a step slot frees when the oldest ends
             continue
-        admitted, still, grew = [], collections.deque(), False
-        while waiting:
-            r = waiting.popleft()
-            st, s = pool.acquire(r.cls)
-            if st == ADMITTED:
-                grew |= s.index >= executor.n
-                admitted.append((s, r))
-            elif st == REJECTED:
-                r.status = REJECTED
-            else:
-                still.append(r)
-        waiting = still
+        # admission: per class, in arrival order, while the class gets slots
+        # (a slot depends only on the class, so the first refusal ends the class)
+        admitted, grew = [], False
+        for cls, q in waiting.items():
+            while q:
+                st, s = pool.acquire(cls)
+                if st == ADMITTED:
+                    r = q.popleft()
+                    grew |= s.index >= executor.n
+                    admitted.append((s, r))
+                elif st == REJECTED:      # the class can never fit
+                    for r in q:
+                        r.status = REJECTED
+                    nwait -= len(q)
+                    q.clear()
+                else:
+                    break
+        nwait -= len(admitted)
         if grew:
             while inflight:                   # let the GPU drain, then re-plan
                 retire(True)
             executor.rebuild()
             stats["plan_rebuilds"] += 1
         if admitted:
+            admitted.sort(key=lambda sr: sr[1].rid)
             for _, r in admitted:
                 r.admitted = now
                 r.status = ADMITTED
             inflight.append((executor.launch(admitted), admitted))
             stats["steps"] += 1
             stats["max_step"] = max(stats["max_step"], len(admitted))
-        elif waiting and inflight:
+        elif nwait and inflight:
             retire(True)                      # waiting for slots: they free when a step ends
-        elif waiting:
+        elif nwait:
             # nothing in flight and nothing admissible: every slot is free and
             # the budget is spent on other classes, so these can never run
-            for r in waiting:
-                r.status = REJECTED
-            waiting.clear()
+            for q in waiting.values():
+                for r in q:
+                    r.status = REJECTED
+                q.clear()
+            nwait = 0
         else:
             # idle: until the next arrival, polling in-flight steps meanwhile
             gap = reqs[nxt].arrival - clock() if nxt < len(reqs) else float("inf")
@@ -215,7 +246,7 @@ class GpuBatchExecutor:
         self.dev = device
         self.classes = classes
         self.ndtype = normal_dtype
-        self.host = {k: [torch.from_numpy(f).pin_memory() for f in v] for k, v in host_frames.items()}
+        self.host = frame_sources(torch, host_frames)
         self.inputs = []                      # device input tensor per slot
         self.slot_cls = []
         self.batch = None
@@ -223,6 +254,7 @@ class GpuBatchExecutor:
         self.ring = 0
         self.max_inflight = max_inflight
         self.stream = torch.cuda.current_stream(device)
+        self.copy_stream = torch.cuda.Stream(device)      # default priority
         self.ref = None
 
     def alloc(self, cls: str) -> None:
@@ -247,6 +279,7 @@ class GpuBatchExecutor:
         # when that step has been retired
         self.mask_host = [torch.zeros(self.n, dtype=torch.uint8).pin_memory()
                           for _ in range(self.max_inflight + 1)]
+        self.mask_np = [m.numpy() for m in self.mask_host]   # host views of the pinned masks
         self.batch.capture(self.mask_dev)
 
     def start_clock(self) -> None:
@@ -256,12 +289,27 @@ class GpuBatchExecutor:
         self.ref.synchronize()
 
     def launch(self, members):
-        buf = self.mask_host[self.ring]
+        buf, view = self.mask_host[self.ring], self.mask_np[self.ring]
         self.ring = (self.ring + 1) % len(self.mask_host)
-        buf.zero_()
-        for s, r in members:
-            buf[s.index] = 1
-            self.inputs[s.index].copy_(self.host[r.cls][r.frame], non_blocking=True)
+        view[:] = 0
+        view[[s.index for s, _ in members]] = 1
+        # a slot is refilled only after the step that last used it retired,
+        # so these copies may overlap the steps still on the GPU; device-side
+        # sources go in one fused copy, host sources one DMA each
+        dsts, srcs = [], []
+        with self.torch.cuda.stream(self.copy_stream):
+            for s, r in members:
+                src = self.host[r.cls][r.frame]
+                if src.is_cuda:
+                    dsts.append(self.inputs[s.index])
+                    srcs.append(src)
+                else:
+                    self.inputs[s.index].copy_(src, non_blocking=True)
+            if dsts:
+                self.torch._foreach_copy_(dsts, srcs, non_blocking=True)
+            copied = self.torch.cuda.Event()
+            copied.record(self.copy_stream)
+        self.stream.wait_event(copied)
         self.mask_dev.copy_(buf, non_blocking=True)
         self.batch.replay()
         ev = self.torch.cuda.Event(enable_timing=True)
@@ -295,9 +343,11 @@ class Server:
         self.pool = SlotPool(budget_bytes, per, allocate=self.exe.alloc)
         self.max_inflight = max_inflight
 
-    def presize(self, counts: dict) -> None:
+    def presize(self, counts: dict, freeze: bool = False) -> None:
         """Create `counts[cls]` slots of each class up front (within the
-        budget) and build the plan; the pool may still grow later."""
+        budget) and build the plan; the pool may still grow later, unless
+        `freeze` (then the budget shrinks to the slots just made: no plan
+        rebuild can interrupt serving)."""
         for cls, k in counts.items():
             got = []
             for _ in range(k):
@@ -307,17 +357,24 @@ class Server:
                 got.append(s)
             for s in got:
                 self.pool.release(s)
+        if freeze:
+            self.pool.budget = self.pool.used
         self.exe.rebuild()
 
-    def serve(self, times, kinds, warmup_s: float = 1.0, pool_index=None) -> dict:
+    def serve(self, times, kinds, warmup_s: float = 1.0, pool_index=None, on_done=None) -> dict:
         """Serve arrivals at `times` (s) of classes `kinds`; requests arriving
-        before `warmup_s` are served but not measured."""
+        before `warmup_s` are served but not measured.  `on_done(request,
+        outputs)` receives each completed request with the dict of its
+        slot's device outputs (valid until the call returns)."""
         reqs = [Request(i, k, float(t), (i if pool_index is None else pool_index[i]) % len(self.exe.host[k]))
                 for i, (t, k) in enumerate(zip(times, kinds))]
         self.exe.start_clock()
         t0 = time.perf_counter()
+        cb = None
+        if on_done is not None:
+            cb = lambda r, s: on_done(r, self.exe.batch.outputs[s.index])
         stats = run_stream(reqs, self.pool, self.exe, lambda: time.perf_counter() - t0,
-                           time.sleep, self.max_inflight)
+                           time.sleep, self.max_inflight, cb)
         stats.update(slots=len(self.pool.slots), slot_bytes=self.pool.used)
         return summarize(reqs, warmup_s, self.classes, extra=stats)
 
@@ -325,7 +382,10 @@ class Server:
 class PlainServer:
     """The same arrival stream through the plain per-frame float32 path:
     frames are processed one at a time in arrival order (one resident
-    buffer set per class, four ABI calls per frame)."""
+    buffer set per class, four ABI calls per frame).  Each frame's input is
+    copied on the compute stream ahead of its calls: a per-frame copy stream
+    (as the batched server uses per step) measured slower here, the loop
+    being bound by its per-frame host work."""
 
     def __init__(self, classes: dict, host_frames: dict, device=None):
         import torch
@@ -334,7 +394,7 @@ class PlainServer:
         self.torch, self.pl = torch, pl
         self.dev = torch.device("cuda:0") if device is None else torch.device(device)
         self.classes = classes
-        self.host = {k: [torch.from_numpy(f).pin_memory() for f in v] for k, v in host_frames.items()}
+        self.host = frame_sources(torch, host_frames)
         self.inp = {k: torch.zeros((c.M, c.N, 3), dtype=torch.float32, device=self.dev)
                     for k, c in classes.items()}
         self.plan = {k: pl.FramePlan(c.M, c.N, c.kernel_lap, c.lam, c.iters_lap, c.kernel_bil,

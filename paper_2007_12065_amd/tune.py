@@ -20,12 +20,15 @@ import torch
 import paper_2007_12065_amd as pl
 
 LAP_CANDIDATES = {
-    3: [(16, 32, 4), (16, 64, 4), (32, 32, 4), (16, 16, 4), (8, 64, 2), (16, 32, 2), (8, 32, 1), (4, 64, 1)],
-    5: [(8, 32, 1), (4, 64, 1), (16, 32, 1), (8, 64, 2), (16, 32, 2), (16, 16, 2)],
+    3: [(16, 32, 4), (16, 64, 4), (32, 32, 4), (16, 16, 4), (8, 64, 2), (16, 32, 2), (32, 32, 2),
+        (32, 16, 2), (16, 16, 2), (8, 32, 1), (4, 64, 1), (32, 32, 1)],
+    5: [(8, 32, 1), (4, 64, 1), (16, 32, 1), (8, 64, 2), (16, 32, 2), (16, 16, 2), (32, 32, 2),
+        (16, 16, 4), (32, 32, 1)],
 }
 BIL_CANDIDATES = {
-    3: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (8, 32, 2), (4, 32, 1)],
-    5: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (4, 32, 1)],
+    3: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (8, 32, 2), (4, 32, 1), (8, 64, 1),
+        (2, 128, 1)],
+    5: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (4, 32, 1), (8, 64, 1)],
 }
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pl_tune.json")
 
