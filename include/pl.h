@@ -232,10 +232,22 @@ pl_status pl_tune_set(pl_stage stage, int32_t kernel, int32_t tile_rows, int32_t
  *                     their previous outputs.  Device-only work: no
  *                     allocation, no synchronisation, legal under capture.
  * pl_batch_capture    records pl_batch_run(active) into a HIP graph owned by
- *                     the plan (replacing any previous one); pl_batch_replay
- *                     launches it on `stream`.  The graph reads the mask's
- *                     contents at replay time, so one graph serves any subset
- *                     of the plan's frames.
+ *                     the plan (replacing the previous such graph);
+ *                     pl_batch_replay launches it on `stream`.  The graph
+ *                     reads the mask's contents at replay time, so one graph
+ *                     serves any subset of the plan's frames.
+ * pl_batch_capture_bounded  the same for replays in which at most
+ *                     `max_active` (>= 1) frames are active: every launch is
+ *                     sized for the max_active frames with the most tiles in
+ *                     its stage, so a step over few frames does not dispatch
+ *                     the idle frames' workgroups.  The plan keeps one graph
+ *                     per bound (capturing a bound again replaces it; bounds
+ *                     above the frame count mean all frames).
+ * pl_batch_replay_bounded   launches the graph with the smallest captured
+ *                     bound >= n_active (PL_ERR_ARG if there is none).  The
+ *                     caller guarantees that at most n_active frames are
+ *                     active in the mask: tiles past a launch's workgroups
+ *                     would go unprocessed.
  * pl_batch_destroy    releases the host-side plan (and its graph).
  * Runs of one plan must not overlap in time (they share the queue counters
  * and scratch in `ws`).
@@ -266,6 +278,9 @@ pl_status pl_batch_create(const pl_frame *frames, int32_t n, pl_dtype ndt, void 
 pl_status pl_batch_run(pl_batch batch, const uint8_t *active, hipStream_t stream);
 pl_status pl_batch_capture(pl_batch batch, const uint8_t *active, hipStream_t stream);
 pl_status pl_batch_replay(pl_batch batch, hipStream_t stream);
+pl_status pl_batch_capture_bounded(pl_batch batch, const uint8_t *active, int32_t max_active,
+                                   hipStream_t stream);
+pl_status pl_batch_replay_bounded(pl_batch batch, int32_t n_active, hipStream_t stream);
 void pl_batch_destroy(pl_batch batch);
 
 #ifdef __cplusplus

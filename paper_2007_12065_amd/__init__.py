@@ -74,6 +74,10 @@ _lib.pl_batch_capture.argtypes = [_vp, _vp, _vp]
 _lib.pl_batch_capture.restype = _i32
 _lib.pl_batch_replay.argtypes = [_vp, _vp]
 _lib.pl_batch_replay.restype = _i32
+_lib.pl_batch_capture_bounded.argtypes = [_vp, _vp, _i32, _vp]
+_lib.pl_batch_capture_bounded.restype = _i32
+_lib.pl_batch_replay_bounded.argtypes = [_vp, _i32, _vp]
+_lib.pl_batch_replay_bounded.restype = _i32
 _lib.pl_batch_destroy.argtypes = [_vp]
 _lib.pl_batch_destroy.restype = None
 
@@ -83,7 +87,8 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_laplacian_workspace", "pl_laplacian_fused_sweeps", "pl_laplacian", "pl_tri_normals",
            "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
            "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
-           "pl_batch_replay", "pl_batch_destroy"]
+           "pl_batch_replay", "pl_batch_capture_bounded", "pl_batch_replay_bounded",
+           "pl_batch_destroy"]
 
 
 class PLError(RuntimeError):
@@ -381,21 +386,33 @@ class Batch:
             _dev_tensor(active, torch.uint8, "active")
         _check(_lib.pl_batch_run(self._h, _ptr(active), _stream(self.device)), "pl_batch_run")
 
-    def capture(self, active: torch.Tensor | None = None) -> None:
+    def capture(self, active: torch.Tensor | None = None, max_active: int | None = None) -> None:
         """Record run(active) into a HIP graph owned by the plan; the graph
-        reads the mask's contents at each replay.  Capture happens on a
-        private stream (the legacy default stream cannot be captured);
-        nothing executes while recording."""
+        reads the mask's contents at each replay.  With `max_active`, the
+        graph is sized for replays with at most that many active frames
+        (pl_batch_capture_bounded); the plan keeps one graph per bound.
+        Capture happens on a private stream (the legacy default stream
+        cannot be captured); nothing executes while recording."""
         if active is not None:
             _dev_tensor(active, torch.uint8, "active")
         self._cap_active = active
         self._cap_stream = torch.cuda.Stream(self.device)
         h = ctypes.c_void_p(self._cap_stream.cuda_stream)
-        _check(_lib.pl_batch_capture(self._h, _ptr(active), h), "pl_batch_capture")
+        if max_active is None:
+            _check(_lib.pl_batch_capture(self._h, _ptr(active), h), "pl_batch_capture")
+        else:
+            _check(_lib.pl_batch_capture_bounded(self._h, _ptr(active), int(max_active), h),
+                   "pl_batch_capture_bounded")
 
-    def replay(self) -> None:
-        """Launch the captured graph on the current stream."""
-        _check(_lib.pl_batch_replay(self._h, _stream(self.device)), "pl_batch_replay")
+    def replay(self, n_active: int | None = None) -> None:
+        """Launch the captured graph on the current stream; with `n_active`,
+        the graph of the smallest captured bound >= n_active (the caller
+        guarantees that at most n_active frames are active)."""
+        if n_active is None:
+            _check(_lib.pl_batch_replay(self._h, _stream(self.device)), "pl_batch_replay")
+        else:
+            _check(_lib.pl_batch_replay_bounded(self._h, int(n_active), _stream(self.device)),
+                   "pl_batch_replay_bounded")
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -447,7 +447,7 @@ __attribute__((visibility("default"))) pl_status pl_batch_capture(pl_batch batch
         set_error("batch is NULL");
         return PL_ERR_ARG;
     }
-    return batch_capture(batch, active, stream);
+    return batch_capture(batch, active, batch_size(batch), stream);
 }
 
 __attribute__((visibility("default"))) pl_status pl_batch_replay(pl_batch batch,
@@ -457,7 +457,34 @@ __attribute__((visibility("default"))) pl_status pl_batch_replay(pl_batch batch,
         set_error("batch is NULL");
         return PL_ERR_ARG;
     }
-    return batch_replay(batch, stream);
+    return batch_replay(batch, batch_size(batch), stream);
+}
+
+__attribute__((visibility("default"))) pl_status pl_batch_capture_bounded(pl_batch batch,
+                                                                          const uint8_t *active,
+                                                                          int32_t max_active,
+                                                                          hipStream_t stream) {
+    g_err[0] = 0;
+    if (!batch) {
+        set_error("batch is NULL");
+        return PL_ERR_ARG;
+    }
+    if (max_active < 1) {
+        set_error("max_active must be at least 1, got %d", max_active);
+        return PL_ERR_ARG;
+    }
+    return batch_capture(batch, active, max_active, stream);
+}
+
+__attribute__((visibility("default"))) pl_status pl_batch_replay_bounded(pl_batch batch,
+                                                                         int32_t n_active,
+                                                                         hipStream_t stream) {
+    g_err[0] = 0;
+    if (!batch) {
+        set_error("batch is NULL");
+        return PL_ERR_ARG;
+    }
+    return batch_replay(batch, n_active, stream);
 }
 
 __attribute__((visibility("default"))) void pl_batch_destroy(pl_batch batch) {

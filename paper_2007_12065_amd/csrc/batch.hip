@@ -40,6 +40,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -193,6 +194,7 @@ struct HostQueue {
     std::vector<int> count;        // [n] tiles per frame
     size_t off_count = 0, off_start = 0;
     long max_tiles = 0;            // all frames active: the launch's workgroups
+    std::vector<long> top;         // [k]: tiles of the k frames with the most (k = 0..n)
     int grid = 0;
     size_t lds = 0;
 };
@@ -219,7 +221,7 @@ struct pl_batch_s {
     int n_queues = 0;              // stage queues with any tile, in table order
     pl::HostQueue mc, me;          // mesh count, mesh emit
     std::vector<pl::Pass> lap, bil;
-    hipGraphExec_t graph = nullptr;
+    std::map<int, hipGraphExec_t> graphs;   // bound on active frames -> captured run
 };
 
 namespace pl {
@@ -282,6 +284,10 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         q->off_start = L.take(sizeof(int) * (n + 1));
         q->max_tiles = 0;
         for (int c : q->count) q->max_tiles += c;
+        std::vector<int> sorted(q->count);
+        std::sort(sorted.begin(), sorted.end(), [](int a, int c) { return a > c; });
+        q->top.assign(n + 1, 0);
+        for (int k = 0; k < n; ++k) q->top[k + 1] = q->top[k] + sorted[k];
     }
     b.off_queues = L.take(sizeof(QueueDev) * qs.size());
     b.n_queues = (int)qs.size();
@@ -427,8 +433,14 @@ pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
     return PL_OK;
 }
 
+// Workgroups of a queue's launch when at most `bound` frames are active.
+int bounded_grid(const HostQueue &q, int bound) {
+    const long t = q.top[std::min<size_t>((size_t)std::max(bound, 0), q.top.size() - 1)];
+    return (int)std::max<long>(1, std::min<long>(t, q.grid));
+}
+
 template <typename NT>
-pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s) {
+pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s, int bound) {
     const BFrame *fr = reinterpret_cast<const BFrame *>(b.ws + b.off_frames);
     const QueueDev *qs = reinterpret_cast<const QueueDev *>(b.ws + b.off_queues);
     const int nq = b.n_queues;
@@ -436,16 +448,16 @@ pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s) {
     const int n = b.n;
     k_batch_prepare<<<nq, kTileBlock, 0, s>>>(qs, n, act);
     if (pl_status st = hip_check(hipGetLastError(), "k_batch_prepare")) return st;
-    k_batch_mesh_count<<<b.mc.grid, kTileBlock, 0, s>>>(fr, dev_queue(b, b.mc), n);
+    k_batch_mesh_count<<<bounded_grid(b.mc, bound), kTileBlock, 0, s>>>(fr, dev_queue(b, b.mc), n);
     if (pl_status st = hip_check(hipGetLastError(), "k_batch_mesh_count")) return st;
-    k_batch_mesh_emit<<<b.me.grid, kTileBlock, 0, s>>>(fr, dev_queue(b, b.me), n);
+    k_batch_mesh_emit<<<bounded_grid(b.me, bound), kTileBlock, 0, s>>>(fr, dev_queue(b, b.me), n);
     if (pl_status st = hip_check(hipGetLastError(), "k_batch_mesh_emit")) return st;
     for (const Pass &p : b.lap) {
         const PassFrame *pt = reinterpret_cast<const PassFrame *>(b.ws + p.off);
         for (int r = 0; r < kMaxRadius; ++r) {
             const HostQueue &q = p.q[r];
             if (q.max_tiles == 0) continue;
-            const dim3 g(q.grid), blk(kTileBlock);
+            const dim3 g(bounded_grid(q, bound)), blk(kTileBlock);
             const QueueDev d = dev_queue(b, q);
             switch (r + 1) {
             case 1: k_batch_laplacian<1><<<g, blk, q.lds, s>>>(fr, pt, d, n); break;
@@ -462,7 +474,7 @@ pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s) {
         for (int r = 0; r < kMaxRadius; ++r) {
             const HostQueue &q = p.q[r];
             if (q.max_tiles == 0) continue;
-            const dim3 g(q.grid), blk(kTileBlock);
+            const dim3 g(bounded_grid(q, bound)), blk(kTileBlock);
             const QueueDev d = dev_queue(b, q);
             if (pi == 0) {
                 switch (r + 1) {
@@ -516,41 +528,48 @@ pl_status batch_create(const pl_frame *frames, int n, pl_dtype ndt, void *ws, hi
 int batch_size(const pl_batch_s *b) { return b->n; }
 
 pl_status batch_run(const pl_batch_s *b, const uint8_t *active, hipStream_t s) {
-    return b->ndt == PL_F32 ? run_batch<float>(*b, active, s) : run_batch<__half>(*b, active, s);
+    return b->ndt == PL_F32 ? run_batch<float>(*b, active, s, b->n)
+                            : run_batch<__half>(*b, active, s, b->n);
 }
 
-pl_status batch_capture(pl_batch_s *b, const uint8_t *active, hipStream_t s) {
-    if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
+pl_status batch_capture(pl_batch_s *b, const uint8_t *active, int bound, hipStream_t s) {
+    bound = std::max(1, std::min(bound, b->n));
+    auto old = b->graphs.find(bound);
+    if (old != b->graphs.end()) {
+        (void)hipGraphExecDestroy(old->second);
+        b->graphs.erase(old);
     }
     hipGraph_t g = nullptr;
     if (pl_status st = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal),
                                  "hipStreamBeginCapture"))
         return st;
-    const pl_status run_st = batch_run(b, active, s);
+    const pl_status run_st = b->ndt == PL_F32 ? run_batch<float>(*b, active, s, bound)
+                                              : run_batch<__half>(*b, active, s, bound);
     const pl_status end_st = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
     if (run_st || end_st) {
         if (g) (void)hipGraphDestroy(g);
         return run_st ? run_st : end_st;
     }
-    const pl_status inst = hip_check(hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0),
+    hipGraphExec_t exec = nullptr;
+    const pl_status inst = hip_check(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0),
                                      "hipGraphInstantiate");
     (void)hipGraphDestroy(g);
+    if (inst == PL_OK) b->graphs[bound] = exec;
     return inst;
 }
 
-pl_status batch_replay(const pl_batch_s *b, hipStream_t s) {
-    if (!b->graph) {
-        set_error("the batch has no captured graph (call pl_batch_capture first)");
+pl_status batch_replay(const pl_batch_s *b, int n_active, hipStream_t s) {
+    auto it = b->graphs.lower_bound(std::max(n_active, 1));
+    if (it == b->graphs.end()) {
+        set_error("no captured graph of this batch allows %d active frames", n_active);
         return PL_ERR_ARG;
     }
-    return hip_check(hipGraphLaunch(b->graph, s), "hipGraphLaunch");
+    return hip_check(hipGraphLaunch(it->second, s), "hipGraphLaunch");
 }
 
 void batch_destroy(pl_batch_s *b) {
     if (!b) return;
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     delete b;
 }
 

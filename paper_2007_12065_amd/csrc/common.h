@@ -99,8 +99,9 @@ size_t batch_workspace(const pl_frame *frames, int n, pl_dtype ndt);
 pl_status batch_create(const pl_frame *frames, int n, pl_dtype ndt, void *ws, hipStream_t s,
                        pl_batch_s **out);
 pl_status batch_run(const pl_batch_s *b, const uint8_t *active, hipStream_t s);
-pl_status batch_capture(pl_batch_s *b, const uint8_t *active, hipStream_t s);
-pl_status batch_replay(const pl_batch_s *b, hipStream_t s);
+int batch_size(const pl_batch_s *b);
+pl_status batch_capture(pl_batch_s *b, const uint8_t *active, int bound, hipStream_t s);
+pl_status batch_replay(const pl_batch_s *b, int n_active, hipStream_t s);
 void batch_destroy(pl_batch_s *b);
 
 }  // namespace pl

@@ -280,7 +280,15 @@ class GpuBatchExecutor:
         self.mask_host = [torch.zeros(self.n, dtype=torch.uint8).pin_memory()
                           for _ in range(self.max_inflight + 1)]
         self.mask_np = [m.numpy() for m in self.mask_host]   # host views of the pinned masks
-        self.batch.capture(self.mask_dev)
+        # one graph per bound on the step size (1, 2, 4, ..., all slots): a
+        # step replays the smallest covering graph, whose launches are sized
+        # for that many frames
+        b = 1
+        while True:
+            self.batch.capture(self.mask_dev, max_active=min(b, self.n))
+            if b >= self.n:
+                break
+            b *= 2
 
     def start_clock(self) -> None:
         self.stream.synchronize()
@@ -311,7 +319,7 @@ class GpuBatchExecutor:
             copied.record(self.copy_stream)
         self.stream.wait_event(copied)
         self.mask_dev.copy_(buf, non_blocking=True)
-        self.batch.replay()
+        self.batch.replay(n_active=len(members))
         ev = self.torch.cuda.Event(enable_timing=True)
         ev.record(self.stream)
         return ev

@@ -181,6 +181,37 @@ def test_batch_active_subset(pl):
     b.close()
 
 
+def test_batch_bounded_graphs(pl):
+    # graphs sized for at most k active frames give the full run's bits for
+    # every subset of at most k frames; a replay needs a covering bound
+    import torch
+    specs = mixed_specs()
+    b = pl.Batch(specs, torch.float32)
+    b.run()
+    torch.cuda.synchronize()
+    want = [{k: (v.clone() if v is not None else None) for k, v in o.items()} for o in b.outputs]
+    mask = torch.zeros(len(specs), dtype=torch.uint8, device="cuda:0")
+    for k in (1, 3):
+        b.capture(mask, max_active=k)
+    with pytest.raises(pl.PLError):
+        b.replay(n_active=4)                      # no bound >= 4 captured
+    for subset in ([1], [4], [0, 2, 3], [1, 3, 8], [2, 7]):
+        print("[case] bounded replay, active", subset, flush=True)
+        for o in b.outputs:
+            o["normals_T"].fill_(-5)
+            o["points"].fill_(-5)
+        mask.zero_()
+        mask[subset] = 1
+        torch.cuda.synchronize()
+        b.replay(n_active=len(subset))
+        torch.cuda.synchronize()
+        for i in subset:
+            assert_frame_equal(b.outputs[i], want[i], f"bounded frame {i}")
+        for i in set(range(len(specs))) - set(subset):
+            assert bool((b.outputs[i]["points"] == -5).all())
+    b.close()
+
+
 def test_batch_runs_repeatedly(pl):
     import torch
     specs = mixed_specs()[5:]
