@@ -34,6 +34,16 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return start + idx;
 }
 
+// Division of a small non-negative index by a workgroup-uniform divisor d:
+// with m = ceil(2^32 / d), floor(i / d) = umulhi(i, m) for every i < 2^32 / d
+// (the error term i (m d - 2^32) / (d 2^32) stays below 1 / d).  Tile
+// indices are far below that bound.
+struct DivBy {
+    unsigned m;
+    __device__ __forceinline__ explicit DivBy(int d) : m(0xFFFFFFFFu / (unsigned)d + 1u) {}
+    __device__ __forceinline__ int div(int i) const { return (int)__umulhi((unsigned)i, m); }
+};
+
 // Inclusive prefix sum across one 64-wide wavefront.
 __device__ __forceinline__ int wave_inclusive_scan(int x) {
     const int lane = threadIdx.x & (kWave - 1);

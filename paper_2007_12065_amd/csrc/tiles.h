@@ -259,8 +259,11 @@ __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
 // Invalid pixels (any NaN coordinate) and pixels outside the image are staged
 // as (0, 0, 0, +inf): the pad makes the squared distance +inf, whose
 // reciprocal square root is exactly 0, so they drop out of both sums without
-// a branch.  Invalid pixels and the border band are never updated; invalid
-// pixels are written back from the input bits.  F = 0 copies the tile.
+// a branch.  Pixels of the border band are staged with pad -0.0, which adds
+// nothing to a distance: they are neighbours like any other, but only a +0.0
+// pad (bits all zero) marks a pixel that is updated.  Invalid pixels and the
+// border band are never updated; invalid pixels are written back from the
+// input bits.  F = 0 copies the tile.
 // LDS: 2 * (TH + 2RF) * (TW + 2RF) float4.
 // ---------------------------------------------------------------------------
 
@@ -279,14 +282,17 @@ __device__ __forceinline__ void lap_tile(const float *__restrict__ src, float *_
     const int oy = ty0 - halo, ox = tx0 - halo;
     const float inf = __builtin_inff();
 
+    const DivBy byW(W);
     for (int idx = threadIdx.x; idx < H * W; idx += kTileBlock) {
-        const int ly = idx / W, lx = idx - ly * W;
+        const int ly = byW.div(idx), lx = idx - ly * W;
         const int gy = oy + ly, gx = ox + lx;
         float4 p = make_float4(0.f, 0.f, 0.f, inf);
         if (gy >= 0 && gy < M && gx >= 0 && gx < N) {
             const float *q = src + 3 * ((size_t)gy * N + gx);
             const float x = q[0], y = q[1], z = q[2];
-            if (!(is_nan_bits(x) || is_nan_bits(y) || is_nan_bits(z))) p = make_float4(x, y, z, 0.f);
+            const bool inner = gy >= R && gy < M - R && gx >= R && gx < N - R;
+            if (!(is_nan_bits(x) || is_nan_bits(y) || is_nan_bits(z)))
+                p = make_float4(x, y, z, inner ? 0.f : -0.f);
         }
         A[idx] = p;
     }
@@ -295,13 +301,13 @@ __device__ __forceinline__ void lap_tile(const float *__restrict__ src, float *_
     for (int f = 1; f <= F; ++f) {
         const int lo = R * f;
         const int Hf = H - 2 * lo, Wf = W - 2 * lo;
+        const DivBy byWf(Wf);
         for (int idx = threadIdx.x; idx < Hf * Wf; idx += kTileBlock) {
-            const int ry = idx / Wf;
+            const int ry = byWf.div(idx);
             const int ly = lo + ry, lx = lo + (idx - ry * Wf);
-            const int gy = oy + ly, gx = ox + lx;
             const float4 c = A[ly * W + lx];
             float4 o = c;
-            const bool active = c.w == 0.f && gy >= R && gy < M - R && gx >= R && gx < N - R;
+            const bool active = __float_as_uint(c.w) == 0u;   // valid, not in the border band
             if (active) {
                 float ws = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
                 // 3x3: fully unrolled; larger windows: one row of the window
@@ -324,7 +330,7 @@ __device__ __forceinline__ void lap_tile(const float *__restrict__ src, float *_
                     }
                 }
                 if (ws > 0.f) {
-                    const float k = lam / ws;
+                    const float k = lam * __builtin_amdgcn_rcpf(ws);
                     o.x = fmaf(k, sx, c.x);
                     o.y = fmaf(k, sy, c.y);
                     o.z = fmaf(k, sz, c.z);
@@ -336,13 +342,14 @@ __device__ __forceinline__ void lap_tile(const float *__restrict__ src, float *_
         float4 *t = A; A = B; B = t;
     }
 
+    const DivBy byTW(TW);
     for (int idx = threadIdx.x; idx < TH * TW; idx += kTileBlock) {
-        const int ry = idx / TW, rx = idx - ry * TW;
+        const int ry = byTW.div(idx), rx = idx - ry * TW;
         const int gy = ty0 + ry, gx = tx0 + rx;
         if (gy >= M || gx >= N) continue;
         const size_t off = 3 * ((size_t)gy * N + gx);
         const float4 c = A[(ry + halo) * W + rx + halo];
-        if (c.w == 0.f) {
+        if (c.w == 0.f) {                   // +0 or -0: a valid pixel
             dst[off] = c.x; dst[off + 1] = c.y; dst[off + 2] = c.z;
         } else {
             dst[off] = src[off]; dst[off + 1] = src[off + 1]; dst[off + 2] = src[off + 2];
@@ -689,8 +696,9 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     const int oy = qy0 - halo, ox = qx0 - halo;
 
     if (F > 0) {
+        const DivBy byW(W);
         for (int idx = threadIdx.x; idx < S; idx += kTileBlock) {
-            const int ly = idx / W, lx = idx - ly * W;
+            const int ly = byW.div(idx), lx = idx - ly * W;
             const int qy = oy + ly, qx = ox + lx;
             float4 c0 = make_float4(inf, inf, inf, 0.f), c1 = c0;
             float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
@@ -729,8 +737,9 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     for (int f = 1; f < F; ++f) {
         const int lo = R * f;
         const int Hf = H - 2 * lo, Wf = W - 2 * lo;
+        const DivBy byWf(Wf);
         for (int idx = threadIdx.x; idx < Hf * Wf; idx += kTileBlock) {
-            const int ry = idx / Wf;
+            const int ry = byWf.div(idx);
             const int a = (lo + ry) * W + lo + (idx - ry * Wf);
             float4 r0, r1;
             bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r0, r1);
@@ -744,8 +753,9 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     }
 
     // last sweep (or the copy when F = 0): the tile itself, to global memory
+    const DivBy byTQW(TQW);
     for (int idx = threadIdx.x; idx < TQH * TQW; idx += kTileBlock) {
-        const int ty = idx / TQW, tx = idx - ty * TQW;
+        const int ty = byTQW.div(idx), tx = idx - ty * TQW;
         const int qy = qy0 + ty, qx = qx0 + tx;
         if (qy >= Mq || qx >= Nq) continue;
         const size_t q = (size_t)qy * Nq + qx;
