@@ -108,13 +108,14 @@ def measured_traffic(kernel, launches_per_call):
     return r.get("bytes_per_launch")
 
 
-def cpu_baseline(frames_np, k, seconds):
+def cpu_baseline(frames_np, k, seconds, threads=None):
     import oracle
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    threads = max(1, min(cores, int(os.environ.get("OMP_NUM_THREADS", cores))))
+    if threads is None:
+        threads = max(1, min(cores, int(os.environ.get("OMP_NUM_THREADS", cores))))
     oracle.build(force=False)
     T = 2 * (k.M - 1) * (k.N - 1)
     done = 0
@@ -337,6 +338,9 @@ def main():
 
     per_call = {c: np.array([evs[i][j].elapsed_time(evs[i][j + 1]) * 1e3 for i in range(K)])
                 for j, c in enumerate(calls)}
+    # the paper's rate: smoothing (Laplacian, normals, bilateral and gather)
+    # only, mesh creation timed and reported on its own
+    smooth_us = per_call["pl_laplacian"] + per_call["pl_tri_normals"] + per_call["pl_bilateral"]
     lat = np.array([evs[i][0].elapsed_time(evs[i][4]) * 1e3 for i in range(K)])
     n_tri = [int(p.n_tri.item()) for p in plans]
     T = 2 * (M - 1) * (N - 1)
@@ -365,6 +369,19 @@ def main():
                  "peak_note": "published fp32 vector peak (packed); this code is built without "
                               "packed FP32, whose ceiling is half (78.6 TFLOP/s)"})
 
+    # measured HBM ceiling: a 256 MiB device-to-device copy (read + write)
+    ca = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        cb.copy_(ca)
+    c1.record(stream)
+    torch.cuda.synchronize(dev)
+    copy_gbs = 2 * ca.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del ca, cb
+
     if args.copy_probe:
         # plain copy of known size for counter calibration: 256 MiB read and
         # 256 MiB written by one device-to-device copy kernel, larger than L2
@@ -385,6 +402,9 @@ def main():
                    "frame": [M, N], "triangles_per_frame": T, "valid_triangles_mean": float(np.mean(n_tri)),
                    "frame_sets": sets},
         "stage_us": {c: round(float(np.median(per_call[c])), 2) for c in calls},
+        "smoothing_triangles_per_s": round(T / (float(np.mean(smooth_us)) * 1e-6), 1),
+        "mesh_us": round(float(np.median(per_call["pl_mesh_opc"])), 2),
+        "hbm_copy_ceiling_gbs": round(copy_gbs, 1),
         "frame_latency_us": {"p50": round(float(np.median(lat)), 2),
                              "p99": round(float(np.percentile(lat, 99)), 2)},
         "hbm_effective_gbs": round(sum(specs[c]["bytes"] * specs[c]["launches"] for c in calls)
@@ -402,6 +422,7 @@ def main():
     if args.cpu_seconds > 0:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(frames_np, k, args.cpu_seconds)
+        out["cpu_baseline_1thread"] = cpu_baseline(frames_np, k, max(2.0, args.cpu_seconds / 2), threads=1)
     print(json.dumps(out), flush=True)
 
 

@@ -281,6 +281,16 @@ pl_status pl_batch_replay(pl_batch batch, hipStream_t stream);
 pl_status pl_batch_capture_bounded(pl_batch batch, const uint8_t *active, int32_t max_active,
                                    hipStream_t stream);
 pl_status pl_batch_replay_bounded(pl_batch batch, int32_t n_active, hipStream_t stream);
+
+/*
+ * One-shot form for callers that run a frame list once: pl_batch_create,
+ * pl_batch_run over all frames, pl_batch_destroy.  `ws` holds
+ * pl_batch_workspace(frames, n, ndt) bytes and must stay allocated and
+ * untouched until the enqueued run has completed on `stream`.  Synchronises
+ * `stream` once (the plan's table upload), like pl_batch_create.
+ */
+pl_status pl_smooth_batch(const pl_frame *frames, int32_t n, pl_dtype ndt, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
 void pl_batch_destroy(pl_batch batch);
 
 #ifdef __cplusplus

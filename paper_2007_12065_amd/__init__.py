@@ -78,6 +78,8 @@ _lib.pl_batch_capture_bounded.argtypes = [_vp, _vp, _i32, _vp]
 _lib.pl_batch_capture_bounded.restype = _i32
 _lib.pl_batch_replay_bounded.argtypes = [_vp, _i32, _vp]
 _lib.pl_batch_replay_bounded.restype = _i32
+_lib.pl_smooth_batch.argtypes = [_vp, _i32, _i32, _vp, _sz, _vp]
+_lib.pl_smooth_batch.restype = _i32
 _lib.pl_batch_destroy.argtypes = [_vp]
 _lib.pl_batch_destroy.restype = None
 
@@ -88,7 +90,7 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
            "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
            "pl_batch_replay", "pl_batch_capture_bounded", "pl_batch_replay_bounded",
-           "pl_batch_destroy"]
+           "pl_batch_destroy", "pl_smooth_batch"]
 
 
 class PLError(RuntimeError):
@@ -320,6 +322,62 @@ def pl_tune_set(stage: int, kernel: int, tile_rows: int, tile_cols: int, fuse: i
     _check(_lib.pl_tune_set(stage, kernel, tile_rows, tile_cols, fuse), "pl_tune_set")
 
 
+def _marshal_frames(frames: list, ndt: int, halfedges: bool = True, tri_valid: bool = True):
+    """PLFrame array over `frames` (dicts: pts [M, N, 3] float32 device tensor,
+    kernel_lap, lam, iters_lap, kernel_bil, sigma_length, sigma_angle,
+    iters_bil) with freshly allocated outputs; returns (array, outputs)."""
+    if not frames:
+        raise ValueError("a batch needs at least one frame")
+    nd = _tdtype(ndt)
+    device = frames[0]["pts"].device
+    outputs = []
+    arr = (PLFrame * len(frames))()
+    for i, f in enumerate(frames):
+        pts = f["pts"]
+        _dev_tensor(pts, torch.float32, f"frames[{i}].pts")
+        M, N = int(pts.shape[0]), int(pts.shape[1])
+        T = 2 * max(M - 1, 1) * max(N - 1, 1)
+        e = lambda shape, dt: torch.empty(shape, dtype=dt, device=device)
+        o = dict(points=e((M, N, 3), torch.float32),
+                 normals=e((M - 1, N - 1, 2, 3), nd),
+                 centroids=e((M - 1, N - 1, 2, 3), torch.float32),
+                 tri_valid=e(T, torch.uint8) if tri_valid else None,
+                 tri_map=e(T, torch.int32), triangles=e((T, 3), torch.int32),
+                 halfedges=e(3 * T, torch.int32) if halfedges else None,
+                 n_tri=e(1, torch.int32), normals_T=e((T, 3), nd))
+        outputs.append(o)
+        a = arr[i]
+        a.pts = pts.data_ptr()
+        a.M, a.N = M, N
+        a.kernel_lap, a.iters_lap, a.lambda_ = f["kernel_lap"], f["iters_lap"], f["lam"]
+        a.kernel_bil, a.iters_bil = f["kernel_bil"], f["iters_bil"]
+        a.sigma_length, a.sigma_angle = f["sigma_length"], f["sigma_angle"]
+        for key, field in (("points", "pts_out"), ("normals", "normals"),
+                           ("centroids", "centroids"), ("tri_valid", "tri_valid"),
+                           ("tri_map", "tri_map"), ("triangles", "triangles"),
+                           ("halfedges", "halfedges"), ("n_tri", "n_tri"),
+                           ("normals_T", "normals_T")):
+            setattr(a, field, o[key].data_ptr() if o[key] is not None else None)
+    return arr, outputs
+
+
+def pl_smooth_batch(frames: list, normal_dtype=torch.float32) -> list:
+    """One pass of the whole path over `frames` (as for Batch) through the
+    one-shot entry point; returns each frame's output dict."""
+    ndt = _ndt(normal_dtype)
+    device = frames[0]["pts"].device if frames else None
+    arr, outputs = _marshal_frames(frames, ndt)
+    ws_n = _lib.pl_batch_workspace(arr, len(frames), ndt)
+    if ws_n == 0:
+        raise PLError(-1, "pl_batch_workspace")
+    ws = torch.empty(ws_n, dtype=torch.uint8, device=device)
+    _check(_lib.pl_smooth_batch(arr, len(frames), ndt, _ptr(ws), ws_n, _stream(device)),
+           "pl_smooth_batch")
+    for o in outputs:                 # the caching allocator keeps ws until the stream is past
+        o["_ws"] = ws
+    return outputs
+
+
 class Batch:
     """A batch of frames through the whole path with one launch per stage (pl_batch_* in include/pl.h).
 
@@ -331,40 +389,10 @@ class Batch:
 
     def __init__(self, frames: list, normal_dtype=torch.float32, halfedges: bool = True,
                  tri_valid: bool = True):
-        if not frames:
-            raise ValueError("a batch needs at least one frame")
         self.ndt = _ndt(normal_dtype)
-        nd = _tdtype(self.ndt)
+        arr, self.outputs = _marshal_frames(frames, self.ndt, halfedges, tri_valid)
         self.device = frames[0]["pts"].device
-        self.inputs, self.outputs = [], []
-        arr = (PLFrame * len(frames))()
-        for i, f in enumerate(frames):
-            pts = f["pts"]
-            _dev_tensor(pts, torch.float32, f"frames[{i}].pts")
-            M, N = int(pts.shape[0]), int(pts.shape[1])
-            T = 2 * max(M - 1, 1) * max(N - 1, 1)
-            e = lambda shape, dt: torch.empty(shape, dtype=dt, device=self.device)
-            o = dict(points=e((M, N, 3), torch.float32),
-                     normals=e((M - 1, N - 1, 2, 3), nd),
-                     centroids=e((M - 1, N - 1, 2, 3), torch.float32),
-                     tri_valid=e(T, torch.uint8) if tri_valid else None,
-                     tri_map=e(T, torch.int32), triangles=e((T, 3), torch.int32),
-                     halfedges=e(3 * T, torch.int32) if halfedges else None,
-                     n_tri=e(1, torch.int32), normals_T=e((T, 3), nd))
-            self.inputs.append(pts)
-            self.outputs.append(o)
-            a = arr[i]
-            a.pts = pts.data_ptr()
-            a.M, a.N = M, N
-            a.kernel_lap, a.iters_lap, a.lambda_ = f["kernel_lap"], f["iters_lap"], f["lam"]
-            a.kernel_bil, a.iters_bil = f["kernel_bil"], f["iters_bil"]
-            a.sigma_length, a.sigma_angle = f["sigma_length"], f["sigma_angle"]
-            for key, field in (("points", "pts_out"), ("normals", "normals"),
-                               ("centroids", "centroids"), ("tri_valid", "tri_valid"),
-                               ("tri_map", "tri_map"), ("triangles", "triangles"),
-                               ("halfedges", "halfedges"), ("n_tri", "n_tri"),
-                               ("normals_T", "normals_T")):
-                setattr(a, field, o[key].data_ptr() if o[key] is not None else None)
+        self.inputs = [f["pts"] for f in frames]
         self._frames = arr
         n = len(frames)
         ws_n = _lib.pl_batch_workspace(arr, n, self.ndt)

@@ -491,4 +491,15 @@ __attribute__((visibility("default"))) void pl_batch_destroy(pl_batch batch) {
     batch_destroy(batch);
 }
 
+__attribute__((visibility("default"))) pl_status pl_smooth_batch(const pl_frame *frames, int32_t n,
+                                                                 pl_dtype ndt, void *ws,
+                                                                 size_t ws_bytes,
+                                                                 hipStream_t stream) {
+    pl_batch b = nullptr;
+    if (pl_status st = pl_batch_create(frames, n, ndt, ws, ws_bytes, stream, &b)) return st;
+    const pl_status st = pl_batch_run(b, nullptr, stream);
+    pl_batch_destroy(b);          // host-side plan only: the queued run reads `ws`
+    return st;
+}
+
 }  // extern "C"

@@ -126,6 +126,19 @@ def test_batch_of_full_size_frames_equals_single_frames(pl, dtype_name):
     b.close()
 
 
+@pytest.mark.parametrize("dtype_name", ["float32", "float16"])
+def test_smooth_batch_one_shot(pl, dtype_name):
+    # pl_smooth_batch (create, run, release) gives the single-frame results
+    import torch
+    dtype = getattr(torch, dtype_name)
+    specs = mixed_specs()[:7]
+    print("[case] one-shot batch,", dtype_name, flush=True)
+    outs = pl.pl_smooth_batch(specs, dtype)
+    torch.cuda.synchronize()
+    for i, sp in enumerate(specs):
+        assert_frame_equal(outs[i], single(pl, sp, dtype), f"one-shot frame {i}")
+
+
 def test_batch_graph_replay(pl):
     import torch
     specs = mixed_specs()[:6]
