@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 __all__ = ["build", "mesh", "halfedges", "laplacian", "tri_normals",
-           "bilateral", "gather", "pipeline"]
+           "bilateral", "gather", "pipeline", "group_assign"]
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +59,9 @@ def _load():
         lib.oracle_bilateral.restype = None
         lib.oracle_gather.argtypes = [vp, vp, i32, i32, vp]
         lib.oracle_gather.restype = None
+        lib.oracle_group_assign.argtypes = [vp, i64, vp, i64, vp, vp, i32,
+                                            ctypes.c_float, ctypes.c_float, vp]
+        lib.oracle_group_assign.restype = None
         _lib = lib
     return _lib
 
@@ -147,3 +150,22 @@ def pipeline(pts, kernel_lap: int, lam: float, iters_lap: int, kernel_bil: int,
     return dict(tri_map=tri_map, triangles=tris, halfedges=he, points=smooth,
                 normals=normals, centroids=centroids, filtered=filtered,
                 normals_T=normals_T)
+
+
+def group_assign(points, triangles, normals, dominant, l_max: float, ang_min: float):
+    """Alg. 4 (Sec. 7.1): group label uint8 [n] of every triangle of T.
+
+    `points` float32 [..., 3] (the smoothed vertices; flattened), `triangles`
+    int32 [n, 3] vertex indices, `normals` [n, 3] (the filtered normals of T,
+    converted to float32), `dominant` [l, 3] dominant plane normals.  The
+    decisions are taken in float32 (see oracle_group_assign)."""
+    p = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
+    t = np.ascontiguousarray(np.asarray(triangles, dtype=np.int32).reshape(-1, 3))
+    n = np.ascontiguousarray(np.asarray(normals, dtype=np.float32).reshape(-1, 3))
+    d = np.ascontiguousarray(np.asarray(dominant, dtype=np.float32).reshape(-1, 3))
+    if len(n) != len(t):
+        raise ValueError("one normal per triangle")
+    out = np.empty(max(len(t), 1), dtype=np.uint8)
+    _load().oracle_group_assign(_ptr(p), len(p), _ptr(t), len(t), _ptr(n), _ptr(d), len(d),
+                                float(l_max), float(ang_min), _ptr(out))
+    return out[:len(t)].copy()

@@ -8,7 +8,8 @@
  * constant with the HIP library, and the HIP library never calls it.
  *
  * Every floating-point step runs in double precision on double inputs (the
- * caller promotes the float32 frame).  Loops follow the paper's definitions
+ * caller promotes the float32 frame), except in group assignment, whose
+ * comparisons decide an integer label and are taken in float32 (see there).  Loops follow the paper's definitions
  * directly; the only parallelism is an OpenMP loop over independent outputs,
  * so results do not depend on the thread count.
  *
@@ -386,5 +387,63 @@ OR_EXPORT void oracle_gather(const double *normals, const int32_t *tri_map,
         normals_T[3LL * t + 0] = normals[3 * g + 0];
         normals_T[3LL * t + 1] = normals[3 * g + 1];
         normals_T[3LL * t + 2] = normals[3 * g + 2];
+    }
+}
+
+/*
+ * Group assignment (Sec. 7.1, Alg. 4): label every triangle t of T with the
+ * index j of the dominant plane normal most similar to its normal, or the
+ * sentinel 255 when one of its edges is longer than l_max or the best
+ * similarity falls short of ang_min.
+ *
+ * Reading: the points are the mesh vertices after smoothing and the normals
+ * the filtered normals of T (the half-edge mesh the planar segmentation
+ * receives).  Every label starts at 255; a triangle whose normal is NaN
+ * matches no dominant normal and keeps it; with no dominant normal every
+ * label is 255; among equal similarities the first wins (the strict
+ * comparison of Alg. 4).
+ * Reading (precision): these comparisons decide an integer, so they are taken
+ * in float32 on the float32 data, as the GPU takes them, with each sum of
+ * products written as fused multiply-adds in this order:
+ *     |a - b|^2 = fma(dx, dx, fma(dy, dy, dz * dz)),  d = a - b
+ *     n . n_j   = fma(nx, njx, fma(ny, njy, nz * njz))
+ * and the edge test keeps a triangle iff each squared edge is <= l_max * l_max
+ * (for exact reals, max |e| > l_max iff some |e|^2 > l_max^2); an edge with
+ * a NaN coordinate passes no such test, so a triangle with an invalid vertex
+ * gets 255, as does one with a vertex index outside [0, n_pts).
+ */
+static float sq_dist_f(const float *a, const float *b)
+{
+    const float dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+OR_EXPORT void oracle_group_assign(const float *pts, int64_t n_pts, const int32_t *tris,
+                                   int64_t n_tri, const float *normals,
+                                   const float *dominant, int l, float l_max,
+                                   float ang_min, uint8_t *groups)
+{
+    const float lmax2 = l_max * l_max;
+    for (int64_t t = 0; t < n_tri; ++t) {
+        groups[t] = 255;
+        const int32_t *v = tris + 3 * t;
+        if (v[0] < 0 || v[1] < 0 || v[2] < 0 || v[0] >= n_pts || v[1] >= n_pts || v[2] >= n_pts)
+            continue;
+        const float *a = pts + 3LL * v[0], *b = pts + 3LL * v[1], *c = pts + 3LL * v[2];
+        if (!(sq_dist_f(a, b) <= lmax2 && sq_dist_f(b, c) <= lmax2 && sq_dist_f(c, a) <= lmax2))
+            continue;                               /* an edge longer than l_max */
+        const float *n = normals + 3 * t;
+        float best = -1.0f;
+        int g = 255;
+        for (int j = 0; j < l; ++j) {
+            const float *d = dominant + 3 * j;
+            const float sim = fmaf(n[0], d[0], fmaf(n[1], d[1], n[2] * d[2]));
+            if (sim > best) {
+                g = j;
+                best = sim;
+            }
+        }
+        if (best < ang_min) g = 255;
+        groups[t] = (uint8_t)g;
     }
 }

@@ -44,7 +44,7 @@ import numpy as np
 
 __all__ = [
     "FrameKind", "KINDS", "make_frame", "config_frame", "random_grid",
-    "batch_mix", "poisson_arrivals",
+    "batch_mix", "poisson_arrivals", "scene_planes",
 ]
 
 
@@ -60,15 +60,20 @@ class FrameKind:
     lam: float = 1.0
     sigma_length: float = 0.1
     sigma_angle: float = 0.1
+    l_max: float = 0.05
+    ang_min: float = 0.96
 
 
 # Filter parameters per workload.  lambda = 1 and sigma_length = sigma_angle =
 # 0.1 follow the parameter tables the paper uses for its OPC runs (Tables 7, 9).
+# Group assignment takes l_max and ang_min from the paper's RealSense table
+# (Table 7: 0.05 m, 0.96) for the pinhole frames and from its KITTI table
+# (Table 4: 1.25 m, 0.97) for the LiDAR frames.
 KINDS = {
     "rgbd_small": FrameKind("rgbd_small", 120, 160, 3, 3, 3, 2),
     "rgbd": FrameKind("rgbd", 480, 640, 3, 4, 3, 2),
-    "lidar": FrameKind("lidar", 64, 1024, 5, 4, 5, 3),
-    "lidar128": FrameKind("lidar128", 128, 2048, 5, 4, 5, 3),
+    "lidar": FrameKind("lidar", 64, 1024, 5, 4, 5, 3, l_max=1.25, ang_min=0.97),
+    "lidar128": FrameKind("lidar128", 128, 2048, 5, 4, 5, 3, l_max=1.25, ang_min=0.97),
 }
 
 # Workload index -> frame kind (the seed of frame f of workload c is 1000 c + f).
@@ -124,6 +129,9 @@ def _nan_uniform(pts, count, rng):
     flat[idx] = np.nan
 
 
+_SMALL_TILT = math.radians(10.0)
+
+
 def _rgbd_small(seed: int) -> np.ndarray:
     k = KINDS["rgbd_small"]
     M, N = k.M, k.N
@@ -131,7 +139,7 @@ def _rgbd_small(seed: int) -> np.ndarray:
     fx = fy = 140.0
     cx, cy = (N - 1) / 2.0, (M - 1) / 2.0
     d = _pinhole_dirs(M, N, fx, fy, cx, cy)
-    tilt = math.radians(10.0)
+    tilt = _SMALL_TILT
     n_f = np.array([0.0, -math.sin(tilt), -math.cos(tilt)])  # floor normal toward camera
     dist = 1.5
     # floor: n_f . p = -dist
@@ -182,6 +190,19 @@ def _blob_holes(M, N, target, rng):
     return mask
 
 
+def _rgbd_pose(rng):
+    """Room corner and camera pose of the 480x640 scene (the first draws of its
+    generator): wall distances wx, wy, yaw and the camera axes r, dn, f in the
+    room frame (z up, floor at z = 0, walls x = wx and y = wy)."""
+    wx, wy = rng.uniform(2.2, 3.8, size=2)
+    yaw = math.atan2(wy, wx) + rng.uniform(-math.radians(5), math.radians(5))
+    pitch = math.radians(20.0)
+    f = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), -math.sin(pitch)])
+    r = np.array([math.sin(yaw), -math.cos(yaw), 0.0])
+    dn = np.cross(f, r)
+    return wx, wy, yaw, r, dn, f
+
+
 def _rgbd(seed: int) -> np.ndarray:
     k = KINDS["rgbd"]
     M, N = k.M, k.N
@@ -189,12 +210,7 @@ def _rgbd(seed: int) -> np.ndarray:
     fx = fy = 525.0
     cx, cy = 319.5, 239.5
     d_cam = _pinhole_dirs(M, N, fx, fy, cx, cy)
-    wx, wy = rng.uniform(2.2, 3.8, size=2)
-    yaw = math.atan2(wy, wx) + rng.uniform(-math.radians(5), math.radians(5))
-    pitch = math.radians(20.0)
-    f = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), -math.sin(pitch)])
-    r = np.array([math.sin(yaw), -math.cos(yaw), 0.0])
-    dn = np.cross(f, r)
+    wx, wy, yaw, r, dn, f = _rgbd_pose(rng)
     O = np.array([0.0, 0.0, 1.2])
     d = d_cam[:, :1] * r + d_cam[:, 1:2] * dn + d_cam[:, 2:3] * f
     inf = np.inf
@@ -273,6 +289,34 @@ def make_frame(kind: str, seed: int) -> np.ndarray:
     if kind == "lidar128":
         return _lidar(seed, 128, 2048)
     raise ValueError(f"unknown frame kind {kind!r}")
+
+
+def scene_planes(kind: str, seed: int) -> np.ndarray:
+    """Unit normals of the large planes of frame (kind, seed), float32 [l, 3],
+    in the frame's own coordinates: the dominant plane normals a plane
+    detector would report for it, given as known inputs.
+
+    120x160: the floor and the cube face turned toward the camera.  480x640:
+    the floor and the two walls.  LiDAR: the road (and sidewalk tops) and the
+    two curb faces.  Each normal is oriented the way the frame's triangles
+    wind: toward the sensor for the pinhole frames and away from it for the
+    LiDAR frames, whose azimuth runs to the left as seen from the sensor and
+    so mirrors the image grid."""
+    if kind == "rgbd_small":
+        t = _SMALL_TILT
+        n_f = np.array([0.0, -math.sin(t), -math.cos(t)])
+        e2 = np.cross(n_f, np.array([1.0, 0.0, 0.0]))
+        planes = np.stack([n_f, -e2])
+    elif kind == "rgbd":
+        _, _, _, r, dn, f = _rgbd_pose(np.random.default_rng(seed))
+        world = np.array([[0.0, 0.0, 1.0], [-1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])
+        planes = np.stack([world @ r, world @ dn, world @ f], axis=1)
+    elif kind in ("lidar", "lidar128"):
+        planes = -np.array([[0.0, 0.0, 1.0], [0.0, -1.0, 0.0], [0.0, 1.0, 0.0]])
+    else:
+        raise ValueError(f"unknown frame kind {kind!r}")
+    planes = planes / np.linalg.norm(planes, axis=1, keepdims=True)
+    return planes.astype(np.float32)
 
 
 def config_frame(config: int, frame: int = 0) -> tuple[np.ndarray, FrameKind]:
