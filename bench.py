@@ -132,6 +132,55 @@ def cpu_baseline(frames_np, k, seconds, threads=None):
                       f"{threads} OpenMP threads), {el:.1f} s"}
 
 
+def groups_bench(plans, k, stream, s, reps=300):
+    """Group assignment (Alg. 4) over the frame sets after the timed path:
+    per-launch time of k_group_assign on float32 normals with each frame's
+    three scene planes as dominant normals, its roofline (HBM bound: T, the
+    normals and the labels streamed once, every point read once), and the
+    oracle's time for the same labels on one frame."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from synth import scene_planes
+    sets = len(plans)
+    doms = [torch.from_numpy(scene_planes("rgbd", 1000 + i)).to(plans[0].device) for i in range(sets)]
+    for i in range(sets):
+        plans[i].run_groups(doms[i], k.l_max, k.ang_min, s)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for i in range(reps):
+        plans[i % sets].run_groups(doms[i % sets], k.l_max, k.ang_min, s)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    n_tri = float(np.mean([int(p.n_tri.item()) for p in plans]))
+    P = plans[0].M * plans[0].N
+    nbytes = 12 * n_tri + 12 * n_tri + n_tri + 12 * P
+    gbs = nbytes / (us * 1e-6) / 1e9
+    labels = plans[0].groups[: int(plans[0].n_tri.item())].cpu().numpy()
+    # the oracle on the same float32 inputs (the GPU frame's own T, points and
+    # normals: a timing of the CPU code, not a parity check)
+    p0 = plans[0]
+    n0 = int(p0.n_tri.item())
+    args = (p0.points.cpu().numpy(), p0.triangles[:n0].cpu().numpy(),
+            p0.normals_T[:n0].cpu().numpy(), doms[0].cpu().numpy(), k.l_max, k.ang_min)
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    r = 0
+    while time.perf_counter() - t0 < 1.0:
+        oracle.group_assign(*args)
+        r += 1
+    cpu_s = (time.perf_counter() - t0) / r
+    return {"kernel": "k_group_assign", "launch_us": round(us, 2),
+            "labels_per_s": round(n_tri / (us * 1e-6), 1),
+            "bytes_per_launch": int(nbytes), "achieved_gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "assigned_frac": round(float(np.mean(labels != 255)), 4),
+            "l_max": k.l_max, "ang_min": k.ang_min, "dominant_normals": 3,
+            "cpu_oracle_labels_per_s": round(n_tri / cpu_s, 1), "cpu_oracle_threads": 1}
+
+
 def angle_stats(got, ref):
     import numpy as np
     g = np.asarray(got, dtype=np.float64).reshape(-1, 3)
@@ -413,6 +462,8 @@ def main():
         "tuning": {name: {"tile": list(r["best"][:2]), "fuse": r["best"][2]}
                    for name, r in tuning.items()},
     }
+    print("[bench] group assignment", file=sys.stderr, flush=True)
+    out["groups"] = groups_bench(plans, k, stream, s)
     if args.batched:
         print("[bench] batched 64-frame mix", file=sys.stderr, flush=True)
         out["batched"] = batched_bench(tune_cache=args.tune_cache)

@@ -53,8 +53,10 @@ typedef enum {
     PL_OK = 0,
     PL_ERR_ARG = -1,       /* NULL required pointer, lambda outside [0, 1],
                               sigma <= 0 or not finite, iterations < 0,
-                              cap < 0, unknown dtype                        */
-    PL_ERR_SHAPE = -2,     /* M < 2 or N < 2, or 6 (M-1)(N-1) >= 2^31       */
+                              cap < 0, unknown dtype, more than 254
+                              dominant normals, l_max < 0 or NaN           */
+    PL_ERR_SHAPE = -2,     /* M < 2 or N < 2, or 6 (M-1)(N-1) >= 2^31;
+                              for group assignment 3 n_pts or 3 cap >= 2^31 */
     PL_ERR_KERNEL = -3,    /* kernel size even, < 3 or > 9                  */
     PL_ERR_ALIAS = -4,     /* an output overlaps an input (Jacobi semantics) */
     PL_ERR_WORKSPACE = -5, /* ws NULL or ws_bytes below the required size   */
@@ -172,6 +174,47 @@ pl_status pl_bilateral(const void *normals_in, const float *centroids, pl_dtype 
                        float sigma_length, float sigma_angle, int32_t iterations,
                        void *normals_out, const int32_t *tri_map, void *normals_T,
                        void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Group assignment, Sec. 7.1 Alg. 4: a label per triangle of T for the
+ * planar segmentation.  Triangle t gets the index j of the dominant normal
+ * n^d_j with the largest similarity n_t . n^d_j (the first such j among
+ * equals), or 255 ("no group") when one of its edges is longer than l_max,
+ * when that similarity is below ang_min, or when there is no dominant normal.
+ * The comparisons are taken in float32 on the float32 values (float16
+ * normals are widened exactly):
+ *     edge test   fma(dx,dx, fma(dy,dy, dz*dz)) <= l_max*l_max for all
+ *                 three edges, d = difference of the edge's endpoints;
+ *                 a NaN coordinate fails it,
+ *     similarity  fma(nx,djx, fma(ny,djy, nz*djz)), strict > against the
+ *                 running best (which starts at -1),
+ * so the labels are a function of the inputs alone.  A NaN normal gets 255;
+ * a triangle with a vertex index outside [0, n_pts) gets 255.
+ *
+ * pts        float32 [n_pts][3]: the vertices (for a frame, the smoothed
+ *            points [M][N][3], n_pts = M N).
+ * triangles  int32 [cap][3]: T (pl_mesh_opc's layout).
+ * normals_T  [cap][3] of type ndt: row t is the normal of triangle t
+ *            (pl_bilateral's gathered output).
+ * n_tri      int32 DEVICE scalar: |T|; rows t with
+ *            t < min(*n_tri, cap) are labelled, the rest of `groups` is
+ *            left untouched (read when the kernel runs, so the call can
+ *            follow pl_mesh_opc on the same stream without a host sync).
+ * cap        rows of triangles / normals_T / groups; 0 enqueues nothing.
+ * dominant   float32 [l][3] device array of dominant unit normals, used as
+ *            given; may be NULL when l = 0.
+ * l          0..254.
+ * l_max      >= 0 (may be +inf); ang_min any number but NaN.
+ * groups     uint8 [cap] output; must not overlap an input.
+ * All arrays are device memory owned by the caller; pts may be NULL when
+ * n_pts = 0, and triangles, normals_T and groups when cap = 0.  No workspace, no
+ * allocation; stream-ordered.  PL_ERR_ARG / PL_ERR_SHAPE / PL_ERR_ALIAS on
+ * invalid arguments (nothing enqueued).
+ */
+pl_status pl_group_assign(const float *pts, int32_t n_pts, const int32_t *triangles,
+                          const void *normals_T, pl_dtype ndt, const int32_t *n_tri,
+                          int32_t cap, const float *dominant, int32_t l, float l_max,
+                          float ang_min, uint8_t *groups, hipStream_t stream);
 
 /*
  * Tile shapes and sweep fusion ("tuning").  Every stage runs its kernel

@@ -82,6 +82,9 @@ _lib.pl_smooth_batch.argtypes = [_vp, _i32, _i32, _vp, _sz, _vp]
 _lib.pl_smooth_batch.restype = _i32
 _lib.pl_batch_destroy.argtypes = [_vp]
 _lib.pl_batch_destroy.restype = None
+_lib.pl_group_assign.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _f32, _f32,
+                                 _vp, _vp]
+_lib.pl_group_assign.restype = _i32
 
 PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL, PL_STAGE_BATCH_LAPLACIAN, PL_STAGE_BATCH_BILATERAL = 0, 1, 2, 3
 
@@ -90,7 +93,7 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
            "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
            "pl_batch_replay", "pl_batch_capture_bounded", "pl_batch_replay_bounded",
-           "pl_batch_destroy", "pl_smooth_batch"]
+           "pl_batch_destroy", "pl_smooth_batch", "pl_group_assign"]
 
 
 class PLError(RuntimeError):
@@ -246,6 +249,44 @@ def smooth_frame(pts: torch.Tensor, kernel_lap: int, lam: float, iters_lap: int,
                 filtered=filtered, normals_T=normals_T)
 
 
+def pl_group_assign(points: torch.Tensor, triangles: torch.Tensor, normals_T: torch.Tensor,
+                    n_tri: torch.Tensor, dominant: torch.Tensor | None, l_max: float,
+                    ang_min: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Alg. 4, Sec. 7.1: uint8 group label [cap] of each triangle of T.
+
+    points     float32 [M, N, 3] or [n, 3] device tensor (the smoothed vertices)
+    triangles  int32 [cap, 3] (T), normals_T [cap, 3] float32 or float16
+    n_tri      int32 [1] device tensor (|T|; rows at or past it are left as
+               they were, uninitialised when `out` is allocated here)
+    dominant   float32 [l, 3] device tensor of dominant normals, l <= 254
+               (None or empty: every label is 255)."""
+    _dev_tensor(points, torch.float32, "points")
+    _dev_tensor(triangles, torch.int32, "triangles")
+    ndt = _ndt(normals_T.dtype)
+    _dev_tensor(normals_T, _tdtype(ndt), "normals_T")
+    _dev_tensor(n_tri, torch.int32, "n_tri")
+    if points.shape[-1] != 3 or triangles.dim() != 2 or triangles.shape[1] != 3:
+        raise ValueError("points must be [..., 3] and triangles [cap, 3]")
+    cap = int(triangles.shape[0])
+    if tuple(normals_T.shape) != (cap, 3):
+        raise ValueError("normals_T must be [cap, 3] like triangles")
+    l = 0
+    if dominant is not None and dominant.numel():
+        _dev_tensor(dominant, torch.float32, "dominant")
+        if dominant.dim() != 2 or dominant.shape[1] != 3:
+            raise ValueError("dominant must be [l, 3]")
+        l = int(dominant.shape[0])
+    else:
+        dominant = None
+    dev = points.device
+    out = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev) if out is None else out
+    _dev_tensor(out, torch.uint8, "out")
+    _check(_lib.pl_group_assign(_ptr(points), points.numel() // 3, _ptr(triangles),
+                                _ptr(normals_T), ndt, _ptr(n_tri), cap, _ptr(dominant), l,
+                                l_max, ang_min, _ptr(out), _stream(dev)), "pl_group_assign")
+    return out[:cap]
+
+
 class FramePlan:
     """Device buffers for one frame shape, allocated once, and the four ABI
     calls of the whole path on them.  run() only enqueues work on the current
@@ -274,6 +315,7 @@ class FramePlan:
         self.centroids = e((M - 1, N - 1, 2, 3), torch.float32)
         self.filtered = e((M - 1, N - 1, 2, 3), nd)
         self.normals_T = e((T, 3), nd)
+        self.groups = e(T, torch.uint8)
         self._ws_mesh_n = _lib.pl_mesh_opc_workspace(M, N)
         self._ws_lap_n = _lib.pl_laplacian_workspace(M, N, iters_lap)
         self._ws_bil_n = _lib.pl_bilateral_workspace(M, N, self.ndt, iters_bil)
@@ -301,6 +343,16 @@ class FramePlan:
                                  self.kernel_bil, self.sigma_length, self.sigma_angle, self.iters_bil,
                                  _ptr(self.filtered), _ptr(self.tri_map), _ptr(self.normals_T),
                                  _ptr(self.ws_bil), self._ws_bil_n, s), "pl_bilateral")
+
+    def run_groups(self, dominant: torch.Tensor, l_max: float, ang_min: float, s=None):
+        """Alg. 4 on this frame's T, smoothed points and filtered normals_T
+        (after run()); labels land in self.groups[:n_tri]."""
+        s = _stream(self.device) if s is None else s
+        _dev_tensor(dominant, torch.float32, "dominant")
+        _check(_lib.pl_group_assign(_ptr(self.points), self.M * self.N, _ptr(self.triangles),
+                                    _ptr(self.normals_T), self.ndt, _ptr(self.n_tri), self.T,
+                                    _ptr(dominant), int(dominant.shape[0]), l_max, ang_min,
+                                    _ptr(self.groups), s), "pl_group_assign")
 
     def run(self, pts: torch.Tensor) -> None:
         s = _stream(self.device)

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpl.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["abi.hip", "mesh.hip", "laplacian.hip", "normals.hip", "bilateral.hip", "tuning.hip", "batch.hip"]
+SOURCES = ["abi.hip", "mesh.hip", "laplacian.hip", "normals.hip", "bilateral.hip", "tuning.hip", "batch.hip",
+           "groups.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

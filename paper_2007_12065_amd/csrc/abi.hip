@@ -107,7 +107,7 @@ static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
 
 extern "C" {
 
-__attribute__((visibility("default"))) int32_t pl_version(void) { return 100; }
+__attribute__((visibility("default"))) int32_t pl_version(void) { return 101; }
 
 __attribute__((visibility("default"))) const char *pl_last_error(void) { return g_err; }
 
@@ -489,6 +489,53 @@ __attribute__((visibility("default"))) pl_status pl_batch_replay_bounded(pl_batc
 
 __attribute__((visibility("default"))) void pl_batch_destroy(pl_batch batch) {
     batch_destroy(batch);
+}
+
+__attribute__((visibility("default"))) pl_status pl_group_assign(
+    const float *pts, int32_t n_pts, const int32_t *triangles, const void *normals_T,
+    pl_dtype ndt, const int32_t *n_tri, int32_t cap, const float *dominant, int32_t l,
+    float l_max, float ang_min, uint8_t *groups, hipStream_t stream) {
+    g_err[0] = 0;
+    if (ndt != PL_F32 && ndt != PL_F16) {
+        set_error("unknown normal dtype %d", (int)ndt);
+        return PL_ERR_ARG;
+    }
+    if (n_pts < 0 || cap < 0) {
+        set_error("n_pts %d, cap %d: must not be negative", n_pts, cap);
+        return PL_ERR_ARG;
+    }
+    if (3.0 * (double)cap >= 2147483648.0 || 3.0 * (double)n_pts >= 2147483648.0) {
+        set_error("n_pts %d, cap %d: 3 n_pts and 3 cap must stay below 2^31", n_pts, cap);
+        return PL_ERR_SHAPE;
+    }
+    if (l < 0 || l > 254) {
+        set_error("%d dominant normals: at most 254 (255 is the sentinel label)", l);
+        return PL_ERR_ARG;
+    }
+    if (!(l_max >= 0.0f) || isnan(ang_min)) {
+        set_error("l_max must be >= 0 and ang_min a number (got %g, %g)", (double)l_max,
+                  (double)ang_min);
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ptrs({{n_tri, "n_tri"}}));
+    if (n_pts > 0) PL_TRY(check_ptrs({{pts, "pts"}}));
+    if (cap > 0)
+        PL_TRY(check_ptrs({{triangles, "triangles"}, {normals_T, "normals_T"},
+                           {groups, "groups"}}));
+    if (l > 0) PL_TRY(check_ptrs({{dominant, "dominant"}}));
+    const Range gr{groups, (size_t)cap};
+    const Range ins[] = {{pts, 12 * (size_t)n_pts},
+                         {triangles, 12 * (size_t)cap},
+                         {normals_T, (size_t)cap * 3 * (ndt == PL_F32 ? 4 : 2)},
+                         {n_tri, 4},
+                         {dominant, 12 * (size_t)l}};
+    for (const Range &r : ins)
+        if (overlap(gr, r)) {
+            set_error("groups must not overlap an input");
+            return PL_ERR_ALIAS;
+        }
+    return launch_group_assign(pts, n_pts, triangles, normals_T, ndt, n_tri, cap, dominant, l,
+                               l_max, ang_min, groups, stream);
 }
 
 __attribute__((visibility("default"))) pl_status pl_smooth_batch(const pl_frame *frames, int32_t n,

@@ -103,6 +103,12 @@ pl_status launch_bilateral(const void *nin, const float *cen, pl_dtype ndt, int 
                            void *normals_T, void *ws, hipStream_t s);
 size_t bilateral_workspace(int M, int N, pl_dtype ndt, int iterations);
 
+pl_status launch_group_assign(const float *pts, int n_pts, const int32_t *tris,
+                              const void *normals, pl_dtype ndt, const int32_t *n_tri, int cap,
+                              const float *dom, int l, float l_max, float ang_min,
+                              uint8_t *groups, hipStream_t s);
+int group_assign_blocks(int cap);
+
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t batch_workspace(const pl_frame *frames, int n, pl_dtype ndt);

@@ -32,7 +32,7 @@ def test_header_symbols_exported(pl):
 
 
 def test_version(pl):
-    assert pl.pl_version() == 100
+    assert pl.pl_version() == 101
 
 
 def test_workspace_sizes(pl):
@@ -97,6 +97,31 @@ def test_normals_and_bilateral_argument_errors(pl):
     assert bil(tm=C + 65536) == -1            # gather without a destination
     assert bil(nout=A) == -4
     assert bil(it=2) == -5
+
+
+def test_group_assign_argument_errors(pl):
+    lib = pl._lib
+    D = 0x400000
+
+    def ga(pts=A, n_pts=100, tris=B, nT=C, ndt=0, n_tri=D, cap=50, dom=D + 256, l=3,
+           l_max=0.05, ang_min=0.96, groups=D + 4096):
+        return lib.pl_group_assign(pts, n_pts, tris, nT, ndt, n_tri, cap, dom, l, l_max,
+                                   ang_min, groups, None)
+    assert ga(ndt=2) == -1
+    assert ga(l=255) == -1 and "254" in err(pl)
+    assert ga(l=-1) == -1
+    assert ga(l_max=-0.5) == -1
+    assert ga(l_max=float("nan")) == -1
+    assert ga(ang_min=float("nan")) == -1
+    assert ga(cap=-1) == -1
+    assert ga(n_pts=-1) == -1
+    assert ga(cap=1 << 30) == -2
+    assert ga(n_tri=None) == -1 and "n_tri" in err(pl)
+    assert ga(dom=None) == -1 and "dominant" in err(pl)
+    assert ga(groups=B + 8) == -1 and "aligned" in err(pl)
+    assert ga(groups=B + 16) == -4          # labels written over the triangle list
+    assert ga(groups=A + 32) == -4          # ... or over the points
+    assert ga(groups=D) == -4               # ... or over the triangle count
 
 
 def test_tuning_table_stages(pl):
