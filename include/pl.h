@@ -255,6 +255,9 @@ pl_status pl_tune_set(pl_stage stage, int32_t kernel, int32_t tile_rows, int32_t
  *   pl_tri_normals(pts_out -> normals before filtering, centroids)
  *   pl_bilateral(-> normals, kernel_bil, sigma_length, sigma_angle,
  *                iters_bil, tri_map -> normals_T)
+ *   pl_group_assign(pts_out, M N, triangles, normals_T, n_tri,
+ *                   cap = 2(M-1)(N-1), dominant, n_dominant, l_max,
+ *                   ang_min -> groups)       (only if groups != NULL)
  * All pointers are device pointers owned by the caller, 16-byte aligned,
  * with the sizes of the single-frame calls (triangles [2(M-1)(N-1)][3],
  * halfedges [6(M-1)(N-1)], normals / normals_T in the batch's dtype);
@@ -311,6 +314,12 @@ typedef struct {
     int32_t *halfedges;        /* optional [6(M-1)(N-1)]                     */
     int32_t *n_tri;            /* device scalar                              */
     void *normals_T;           /* [2(M-1)(N-1)][3]                           */
+    /* Optional group assignment (pl_group_assign on this frame's smoothed
+       points, T and normals_T): groups NULL leaves it out.                 */
+    const float *dominant;     /* [n_dominant][3]; may be NULL if none        */
+    int32_t n_dominant;        /* 0..254                                     */
+    float l_max, ang_min;      /* l_max >= 0, ang_min not NaN                */
+    uint8_t *groups;           /* [2(M-1)(N-1)]: rows < |T| receive labels   */
 } pl_frame;
 
 typedef struct pl_batch_s *pl_batch;

@@ -55,7 +55,8 @@ class PLFrame(ctypes.Structure):
                 ("iters_bil", _i32), ("sigma_length", _f32), ("sigma_angle", _f32),
                 ("pts_out", _vp), ("normals", _vp), ("centroids", _vp), ("tri_valid", _vp),
                 ("tri_map", _vp), ("triangles", _vp), ("halfedges", _vp), ("n_tri", _vp),
-                ("normals_T", _vp)]
+                ("normals_T", _vp), ("dominant", _vp), ("n_dominant", _i32), ("l_max", _f32),
+                ("ang_min", _f32), ("groups", _vp)]
 
 
 _lib.pl_tune_get.argtypes = [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -377,7 +378,10 @@ def pl_tune_set(stage: int, kernel: int, tile_rows: int, tile_cols: int, fuse: i
 def _marshal_frames(frames: list, ndt: int, halfedges: bool = True, tri_valid: bool = True):
     """PLFrame array over `frames` (dicts: pts [M, N, 3] float32 device tensor,
     kernel_lap, lam, iters_lap, kernel_bil, sigma_length, sigma_angle,
-    iters_bil) with freshly allocated outputs; returns (array, outputs)."""
+    iters_bil; optionally dominant [l, 3] float32 device tensor, l_max and
+    ang_min for group assignment, Alg. 4) with freshly allocated outputs
+    (plus groups uint8 [2Q] for frames that give dominant normals); returns
+    (array, outputs)."""
     if not frames:
         raise ValueError("a batch needs at least one frame")
     nd = _tdtype(ndt)
@@ -397,6 +401,12 @@ def _marshal_frames(frames: list, ndt: int, halfedges: bool = True, tri_valid: b
                  tri_map=e(T, torch.int32), triangles=e((T, 3), torch.int32),
                  halfedges=e(3 * T, torch.int32) if halfedges else None,
                  n_tri=e(1, torch.int32), normals_T=e((T, 3), nd))
+        dom = f.get("dominant")
+        if dom is not None:
+            _dev_tensor(dom, torch.float32, f"frames[{i}].dominant")
+            if dom.dim() != 2 or dom.shape[1] != 3:
+                raise ValueError(f"frames[{i}].dominant must be [l, 3]")
+            o["groups"] = e(T, torch.uint8)
         outputs.append(o)
         a = arr[i]
         a.pts = pts.data_ptr()
@@ -410,6 +420,11 @@ def _marshal_frames(frames: list, ndt: int, halfedges: bool = True, tri_valid: b
                            ("halfedges", "halfedges"), ("n_tri", "n_tri"),
                            ("normals_T", "normals_T")):
             setattr(a, field, o[key].data_ptr() if o[key] is not None else None)
+        if dom is not None:
+            a.dominant = dom.data_ptr() if dom.numel() else None
+            a.n_dominant = int(dom.shape[0])
+            a.l_max, a.ang_min = float(f["l_max"]), float(f["ang_min"])
+            a.groups = o["groups"].data_ptr()
     return arr, outputs
 
 
@@ -425,8 +440,9 @@ def pl_smooth_batch(frames: list, normal_dtype=torch.float32) -> list:
     ws = torch.empty(ws_n, dtype=torch.uint8, device=device)
     _check(_lib.pl_smooth_batch(arr, len(frames), ndt, _ptr(ws), ws_n, _stream(device)),
            "pl_smooth_batch")
-    for o in outputs:                 # the caching allocator keeps ws until the stream is past
+    for o, f in zip(outputs, frames):  # the caching allocator keeps ws until the stream is past
         o["_ws"] = ws
+        o["_dominant"] = f.get("dominant")
     return outputs
 
 
@@ -435,9 +451,11 @@ class Batch:
 
     `frames` is a list of dicts with keys pts ([M, N, 3] float32 device
     tensor), kernel_lap, lam, iters_lap, kernel_bil, sigma_length,
-    sigma_angle, iters_bil.  Outputs are allocated here, once, and stay bound
-    to the plan: outputs[i] holds points, normals (filtered, T_FC layout),
-    centroids, tri_valid, tri_map, triangles, halfedges, n_tri, normals_T."""
+    sigma_angle, iters_bil, and optionally dominant ([l, 3] float32 device
+    tensor), l_max and ang_min for group assignment (Alg. 4).  Outputs are
+    allocated here, once, and stay bound to the plan: outputs[i] holds
+    points, normals (filtered, T_FC layout), centroids, tri_valid, tri_map,
+    triangles, halfedges, n_tri, normals_T (and groups)."""
 
     def __init__(self, frames: list, normal_dtype=torch.float32, halfedges: bool = True,
                  tri_valid: bool = True):
@@ -445,6 +463,7 @@ class Batch:
         arr, self.outputs = _marshal_frames(frames, self.ndt, halfedges, tri_valid)
         self.device = frames[0]["pts"].device
         self.inputs = [f["pts"] for f in frames]
+        self._dominant = [f.get("dominant") for f in frames]   # read by every run
         self._frames = arr
         n = len(frames)
         ws_n = _lib.pl_batch_workspace(arr, n, self.ndt)

@@ -107,7 +107,7 @@ static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
 
 extern "C" {
 
-__attribute__((visibility("default"))) int32_t pl_version(void) { return 101; }
+__attribute__((visibility("default"))) int32_t pl_version(void) { return 102; }
 
 __attribute__((visibility("default"))) const char *pl_last_error(void) { return g_err; }
 
@@ -354,6 +354,16 @@ pl_status check_batch(const pl_frame *frames, int32_t n, pl_dtype ndt) {
             set_error("frame %d: tri_valid / halfedges not 16-byte aligned", i);
             return PL_ERR_ARG;
         }
+        if (f.groups) {
+            if (!aligned16(f.groups) || f.n_dominant < 0 || f.n_dominant > 254 ||
+                (f.n_dominant > 0 && (!f.dominant || !aligned16(f.dominant))) ||
+                !(f.l_max >= 0.0f) || isnan(f.ang_min)) {
+                set_error("frame %d: group assignment needs 16-byte aligned groups (and "
+                          "dominant), 0..254 dominant normals, l_max >= 0 and ang_min a number",
+                          i);
+                return PL_ERR_ARG;
+            }
+        }
         const size_t P = (size_t)f.M * f.N, T = 2 * (size_t)(f.M - 1) * (f.N - 1);
         auto add = [&](const void *p, size_t bytes, bool out) {
             if (p && bytes) spans.push_back(Span{(uintptr_t)p, (uintptr_t)p + bytes, i, out});
@@ -368,6 +378,10 @@ pl_status check_batch(const pl_frame *frames, int32_t n, pl_dtype ndt) {
         add(f.halfedges, 12 * T, true);
         add(f.n_tri, 4, true);
         add(f.normals_T, 3 * T * nb, true);
+        if (f.groups) {
+            add(f.groups, T, true);
+            add(f.dominant, 12 * (size_t)f.n_dominant, false);
+        }
     }
     std::sort(spans.begin(), spans.end(), [](const Span &x, const Span &y) { return x.a < y.a; });
     uintptr_t reach = 0;

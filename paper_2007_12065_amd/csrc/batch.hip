@@ -20,6 +20,8 @@
 //                      from the smoothed points while staging its tiles (and
 //                      writes the centroids), so there is no normals stage;
 //                      the frame's last pass gathers onto T
+//   k_batch_groups     tiles = (frame, 1024 rows of T)  -> group labels
+//                      (frames that asked for them)
 // Every tile runs the same device body as the single-frame kernels
 // (tiles.h), so each frame's outputs equal its single-frame results.
 //
@@ -34,6 +36,7 @@
 // persistent grid popping tiles from per-XCD atomic counters was measured
 // slower: contended device-scope atomics put a floor of several hundred
 // microseconds under every stage of a 64-frame batch.)
+#include "groups.h"
 #include "tiles.h"
 #include "tuning.h"
 
@@ -62,6 +65,10 @@ struct BFrame {
     float lam, ka, kb;
     int lap_th, lap_tw, lap_tiles_x;
     int bil_th, bil_tw, bil_tiles_x;
+    const float *dom;              // group assignment (groups != nullptr)
+    uint8_t *groups;
+    int n_dom;
+    float lmax2, ang_min;
 };
 
 struct PassFrame {                 // one frame's part of one sweep pass
@@ -177,6 +184,19 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_batch_bilatera
                              static_cast<NT *>(f.normals_T), lds, f.pts_out, f.centroids);
 }
 
+static_assert(kGroupBlock == kTileBlock, "queue tiles are staged by kTileBlock threads");
+
+template <typename NT>
+__global__ __launch_bounds__(kGroupBlock) void k_batch_groups(const BFrame *__restrict__ fr,
+                                                              QueueDev Q, int n) {
+    PL_QUEUE_TILE(Q, n, t)
+    const BFrame &f = fr[t.x];
+    const int cap = 2 * f.Mq * f.Nq;
+    group_rows<NT>(f.pts_out, f.M * f.N, f.triangles, static_cast<const NT *>(f.normals_T),
+                   f.n_tri, cap, f.dom, f.n_dom, f.lmax2, f.ang_min, f.groups,
+                   (t.y * kGroupBlock + (int)threadIdx.x) * kGroupPer);
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
@@ -220,6 +240,7 @@ struct pl_batch_s {
     size_t off_frames = 0, off_queues = 0, off_ones = 0;
     int n_queues = 0;              // stage queues with any tile, in table order
     pl::HostQueue mc, me;          // mesh count, mesh emit
+    pl::HostQueue grp;             // group assignment (frames with groups)
     std::vector<pl::Pass> lap, bil;
     std::map<int, hipGraphExec_t> graphs;   // bound on active frames -> captured run
 };
@@ -230,11 +251,14 @@ namespace {
 
 std::vector<HostQueue *> all_queues(pl_batch_s &b) {
     std::vector<HostQueue *> qs = {&b.mc, &b.me};
+    auto any = [](const HostQueue &q) {
+        return std::any_of(q.count.begin(), q.count.end(), [](int c) { return c > 0; });
+    };
     for (auto *passes : {&b.lap, &b.bil})
         for (auto &p : *passes)
             for (HostQueue &q : p.q)
-                if (std::any_of(q.count.begin(), q.count.end(), [](int c) { return c > 0; }))
-                    qs.push_back(&q);
+                if (any(q)) qs.push_back(&q);
+    if (any(b.grp)) qs.push_back(&b.grp);
     return qs;
 }
 
@@ -261,7 +285,7 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
     b.bil.assign(maxbil, Pass());
     for (auto &p : b.lap) { p.tab.assign(n, PassFrame{}); p.off = L.take(sizeof(PassFrame) * n); }
     for (auto &p : b.bil) { p.tab.assign(n, PassFrame{}); p.off = L.take(sizeof(PassFrame) * n); }
-    for (HostQueue *q : {&b.mc, &b.me}) q->count.assign(n, 0);
+    for (HostQueue *q : {&b.mc, &b.me, &b.grp}) q->count.assign(n, 0);
     for (auto *passes : {&b.lap, &b.bil})
         for (auto &p : *passes)
             for (HostQueue &q : p.q) q.count.assign(n, 0);
@@ -277,6 +301,8 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         const int lp = passes_for(f.iters_lap, cl.fuse), bp = passes_for(f.iters_bil, cb.fuse);
         for (int p = 0; p < lp; ++p) b.lap[p].q[f.kernel_lap / 2 - 1].count[i] = ltiles;
         for (int p = 0; p < bp; ++p) b.bil[p].q[f.kernel_bil / 2 - 1].count[i] = btiles;
+        const long rows_per_tile = (long)kGroupBlock * kGroupPer;
+        if (f.groups) b.grp.count[i] = (int)((2L * Mq * Nq + rows_per_tile - 1) / rows_per_tile);
     }
     const std::vector<HostQueue *> qs = all_queues(b);
     for (HostQueue *q : qs) {
@@ -337,6 +363,11 @@ size_t batch_layout(const pl_frame *frames, int n, pl_dtype ndt, pl_batch_s *pla
         const TileCfg cl = tile_cfg(kStageBatchLaplacian, d.Rl), cb = tile_cfg(kStageBatchBilateral, d.Rb);
         d.lap_th = cl.th; d.lap_tw = cl.tw; d.lap_tiles_x = (f.N + cl.tw - 1) / cl.tw;
         d.bil_th = cb.th; d.bil_tw = cb.tw; d.bil_tiles_x = (f.N - 1 + cb.tw - 1) / cb.tw;
+        d.dom = f.groups ? f.dominant : nullptr;
+        d.groups = f.groups;
+        d.n_dom = f.groups ? f.n_dominant : 0;
+        d.lmax2 = f.groups ? f.l_max * f.l_max : 0.0f;
+        d.ang_min = f.groups ? f.ang_min : 0.0f;
         // sweep passes, the last of each stage landing in the caller's output
         const int lp = passes_for(f.iters_lap, cl.fuse);
         int left = f.iters_lap;
@@ -401,6 +432,8 @@ template <typename NT>
 pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
     if (pl_status st = size_grid(b.mc, (const void *)k_batch_mesh_count, 0)) return st;
     if (pl_status st = size_grid(b.me, (const void *)k_batch_mesh_emit, 0)) return st;
+    if (b.grp.max_tiles > 0)
+        if (pl_status st = size_grid(b.grp, (const void *)k_batch_groups<NT>, 0)) return st;
     static const void *const lap_k[kMaxRadius] = {
         (const void *)k_batch_laplacian<1>, (const void *)k_batch_laplacian<2>,
         (const void *)k_batch_laplacian<3>, (const void *)k_batch_laplacian<4>};
@@ -493,6 +526,10 @@ pl_status run_batch(const pl_batch_s &b, const uint8_t *active, hipStream_t s, i
             }
             if (pl_status st = hip_check(hipGetLastError(), "k_batch_bilateral")) return st;
         }
+    }
+    if (b.grp.max_tiles > 0) {
+        k_batch_groups<NT><<<bounded_grid(b.grp, bound), kGroupBlock, 0, s>>>(fr, dev_queue(b, b.grp), n);
+        if (pl_status st = hip_check(hipGetLastError(), "k_batch_groups")) return st;
     }
     return PL_OK;
 }

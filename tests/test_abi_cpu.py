@@ -32,7 +32,7 @@ def test_header_symbols_exported(pl):
 
 
 def test_version(pl):
-    assert pl.pl_version() == 101
+    assert pl.pl_version() == 102
 
 
 def test_workspace_sizes(pl):
@@ -122,6 +122,42 @@ def test_group_assign_argument_errors(pl):
     assert ga(groups=B + 16) == -4          # labels written over the triangle list
     assert ga(groups=A + 32) == -4          # ... or over the points
     assert ga(groups=D) == -4               # ... or over the triangle count
+
+
+def test_batch_group_fields_checked(pl):
+    """The optional group-assignment fields of pl_frame are validated with
+    the rest of the frame (host-only: no device memory is touched)."""
+    lib = pl._lib
+    M, N = 8, 9
+    T = 2 * (M - 1) * (N - 1)
+    base = 0x10000000
+    f = pl.PLFrame()
+    f.M, f.N, f.kernel_lap, f.iters_lap, f.lambda_ = M, N, 3, 1, 1.0
+    f.kernel_bil, f.iters_bil, f.sigma_length, f.sigma_angle = 3, 1, 0.1, 0.1
+    for j, name in enumerate(["pts", "pts_out", "normals", "centroids", "tri_map", "triangles",
+                              "n_tri", "normals_T"]):
+        setattr(f, name, base + j * 0x100000)
+    arr = (pl.PLFrame * 1)(f)
+    plain = lib.pl_batch_workspace(arr, 1, 0)
+    assert plain > 0
+    arr[0].groups = base + 0x1000000
+    arr[0].dominant, arr[0].n_dominant, arr[0].l_max, arr[0].ang_min = base + 0x1100000, 3, 0.05, 0.96
+    assert lib.pl_batch_workspace(arr, 1, 0) > plain        # one more queue
+    for field, bad in (("n_dominant", 255), ("l_max", -1.0), ("ang_min", float("nan")),
+                       ("dominant", None), ("groups", base + 0x1000008)):
+        g = pl.PLFrame.from_buffer_copy(arr[0])
+        setattr(g, field, bad)
+        assert lib.pl_batch_workspace((pl.PLFrame * 1)(g), 1, 0) == 0, field
+        assert "group" in err(pl), field
+    g = pl.PLFrame.from_buffer_copy(arr[0])
+    g.groups = g.triangles + 16 * 12                      # labels over the triangle list
+    assert lib.pl_batch_workspace((pl.PLFrame * 1)(g), 1, 0) == 0
+    assert "overlap" in err(pl)
+    # l = 0 needs no dominant array
+    g = pl.PLFrame.from_buffer_copy(arr[0])
+    g.n_dominant, g.dominant = 0, None
+    assert lib.pl_batch_workspace((pl.PLFrame * 1)(g), 1, 0) > plain
+    assert T > 0
 
 
 def test_tuning_table_stages(pl):

@@ -174,3 +174,92 @@ def test_whole_path_against_oracle_path(pl, orc):
                    & (np.abs(srt[:, -1] - amin) > m))
         assert decided.mean() > 0.98
         assert np.array_equal(got[decided], ref[decided]), np.count_nonzero(got[decided] != ref[decided])
+
+
+def _batch_specs(with_groups):
+    """Mixed frames; every other one asks for group assignment, with 3
+    scene planes, none, one or 254 dominant normals."""
+    from synth import KINDS, make_frame, random_grid, scene_planes
+    rng = np.random.default_rng(5)
+    specs = []
+    frames = [("rgbd_small", 1), ("rgbd", 2), ("lidar", 3), ("lidar128", 4), ("rgbd", 5)]
+    for j, (kind, seed) in enumerate(frames):
+        k = KINDS[kind]
+        s = dict(pts=to_dev(make_frame(kind, seed)), kernel_lap=k.kernel_lap, lam=k.lam,
+                 iters_lap=k.iters_lap, kernel_bil=k.kernel_bil, sigma_length=k.sigma_length,
+                 sigma_angle=k.sigma_angle, iters_bil=k.iters_bil)
+        if with_groups and j != 3:
+            s.update(dominant=to_dev(scene_planes(kind, seed)), l_max=k.l_max, ang_min=k.ang_min)
+        specs.append(s)
+    for j, (M, N, l) in enumerate([(2, 2, 1), (37, 150, 0), (50, 70, 254), (9, 600, 5)]):
+        s = dict(pts=to_dev(random_grid(M, N, 40 + j, nan_frac=0.1)), kernel_lap=3, lam=1.0,
+                 iters_lap=2, kernel_bil=5, sigma_length=0.1, sigma_angle=0.1, iters_bil=2)
+        if with_groups:
+            d = rng.normal(size=(l, 3))
+            if l:
+                d[0] = (0.0, 0.0, -1.0)
+            d = (d / np.maximum(np.linalg.norm(d, axis=1, keepdims=True), 1e-30)).astype(np.float32)
+            s.update(dominant=to_dev(d.reshape(l, 3)), l_max=0.1, ang_min=0.9)
+        specs.append(s)
+    return specs
+
+
+def _single_call_groups(pl, o, s):
+    return pl.pl_group_assign(o["points"], o["triangles"], o["normals_T"], o["n_tri"],
+                              s["dominant"], s["l_max"], s["ang_min"])
+
+
+@pytest.mark.parametrize("dtype_name", ["float32", "float16"])
+def test_batch_groups_equal_single_call(pl, dtype_name):
+    """The batch's group stage gives every frame the labels pl_group_assign
+    gives on that frame's (bitwise identical) outputs; frames without groups
+    are unaffected, and the plan runs repeatedly and from a bounded graph."""
+    import torch
+    dtype = getattr(torch, dtype_name)
+    specs = _batch_specs(True)
+    say("batch groups", len(specs), "frames", dtype_name)
+    b = pl.Batch(specs, dtype)
+    b.run()
+    torch.cuda.synchronize()
+    plain = pl.Batch(_batch_specs(False), dtype)
+    plain.run()
+    torch.cuda.synchronize()
+    for i, (o, s) in enumerate(zip(b.outputs, specs)):
+        n = int(o["n_tri"].item())
+        assert torch.equal(o["normals_T"][:n], plain.outputs[i]["normals_T"][:n]), i
+        if "dominant" not in s:
+            assert "groups" not in o
+            continue
+        want = _single_call_groups(pl, o, s)
+        torch.cuda.synchronize()
+        assert torch.equal(o["groups"][:n], want[:n]), i
+    # active subset from a bounded graph: inactive frames keep their labels
+    say("batch groups bounded graph")
+    for o in b.outputs:
+        if "groups" in o:
+            o["groups"].fill_(UNTOUCHED)
+    act = torch.zeros(len(specs), dtype=torch.uint8, device="cuda:0")
+    act[[0, 2, 6]] = 1
+    b.capture(act, max_active=3)
+    for _ in range(2):
+        b.replay(3)
+        torch.cuda.synchronize()
+    for i, (o, s) in enumerate(zip(b.outputs, specs)):
+        if "groups" not in o:
+            continue
+        n = int(o["n_tri"].item())
+        if i in (0, 2, 6):
+            assert torch.equal(o["groups"][:n], _single_call_groups(pl, o, s)[:n]), i
+        else:
+            assert bool((o["groups"] == UNTOUCHED).all()), i
+
+
+def test_one_shot_batch_groups(pl):
+    import torch
+    specs = _batch_specs(True)[:3]
+    say("one-shot batch groups")
+    outs = pl.pl_smooth_batch(specs)
+    torch.cuda.synchronize()
+    for o, s in zip(outs, specs):
+        n = int(o["n_tri"].item())
+        assert torch.equal(o["groups"][:n], _single_call_groups(pl, o, s)[:n])
