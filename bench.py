@@ -79,11 +79,17 @@ def kernel_specs(k, M, N, n_tri_mean):
     }
 
 
-def kernel_source_digest(files=("paper_2007_12065_amd/csrc/tiles.h", "paper_2007_12065_amd/csrc/common.h",
-                                "paper_2007_12065_amd/csrc/bilateral.hip",
-                                "paper_2007_12065_amd/csrc/laplacian.hip",
-                                "paper_2007_12065_amd/csrc/normals.hip")):
-    """SHA-256 over the sources the single-frame filter kernels are built from."""
+FILTER_SOURCES = ("paper_2007_12065_amd/csrc/tiles.h", "paper_2007_12065_amd/csrc/common.h",
+                  "paper_2007_12065_amd/csrc/bilateral.hip", "paper_2007_12065_amd/csrc/laplacian.hip",
+                  "paper_2007_12065_amd/csrc/normals.hip")
+GROUP_SOURCES = ("paper_2007_12065_amd/csrc/common.h", "paper_2007_12065_amd/csrc/groups.h",
+                 "paper_2007_12065_amd/csrc/groups.hip")
+KERNEL_SOURCES = {"k_bilateral": FILTER_SOURCES, "k_group_assign": GROUP_SOURCES}
+
+
+def kernel_source_digest(files=FILTER_SOURCES):
+    """SHA-256 over the sources a kernel is built from (default: the
+    single-frame filter kernels)."""
     import hashlib
     h = hashlib.sha256()
     for f in files:
@@ -103,7 +109,7 @@ def measured_traffic(kernel, launches_per_call):
     except (OSError, ValueError):
         return None
     r = rec.get(kernel)
-    if not r or r.get("source_digest") != kernel_source_digest():
+    if not r or r.get("source_digest") != kernel_source_digest(KERNEL_SOURCES.get(kernel, FILTER_SOURCES)):
         return None
     return r.get("bytes_per_launch")
 
@@ -176,6 +182,7 @@ def groups_bench(plans, k, stream, s, reps=300):
             "labels_per_s": round(n_tri / (us * 1e-6), 1),
             "bytes_per_launch": int(nbytes), "achieved_gbs": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("k_group_assign", 1),
             "assigned_frac": round(float(np.mean(labels != 255)), 4),
             "l_max": k.l_max, "ang_min": k.ang_min, "dominant_normals": 3,
             "cpu_oracle_labels_per_s": round(n_tri / cpu_s, 1), "cpu_oracle_threads": 1}
