@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 __all__ = ["build", "mesh", "halfedges", "laplacian", "tri_normals",
-           "bilateral", "gather", "pipeline", "group_assign"]
+           "bilateral", "gather", "pipeline", "group_assign", "ga_icosahedron", "ga_integrate"]
 
 
 def build(force: bool = True) -> str:
@@ -62,6 +62,12 @@ def _load():
         lib.oracle_group_assign.argtypes = [vp, i64, vp, i64, vp, vp, i32,
                                             ctypes.c_float, ctypes.c_float, vp]
         lib.oracle_group_assign.restype = None
+        lib.oracle_ga_sizes.argtypes = [i32, vp, vp]
+        lib.oracle_ga_sizes.restype = i32
+        lib.oracle_ga_icosahedron.argtypes = [i32, vp, vp, vp]
+        lib.oracle_ga_icosahedron.restype = i32
+        lib.oracle_ga_integrate.argtypes = [vp, i32, vp, i64, i32, vp, vp]
+        lib.oracle_ga_integrate.restype = None
         _lib = lib
     return _lib
 
@@ -169,3 +175,34 @@ def group_assign(points, triangles, normals, dominant, l_max: float, ang_min: fl
     _load().oracle_group_assign(_ptr(p), len(p), _ptr(t), len(t), _ptr(n), _ptr(d), len(d),
                                 float(l_max), float(ang_min), _ptr(out))
     return out[:len(t)].copy()
+
+
+def ga_icosahedron(level: int):
+    """Sec. 6.1.1: the refined icosahedron of `level` as (vertices float64
+    [V, 3], faces int32 [F, 3], cell normals float32 [F, 3])."""
+    lib = _load()
+    nv, nf = ctypes.c_int64(), ctypes.c_int64()
+    if lib.oracle_ga_sizes(int(level), ctypes.byref(nv), ctypes.byref(nf)) != 0:
+        raise ValueError("level must be in [0, 7]")
+    V = np.empty((nv.value, 3), dtype=np.float64)
+    F = np.empty((nf.value, 3), dtype=np.int32)
+    C = np.empty((nf.value, 3), dtype=np.float32)
+    if lib.oracle_ga_icosahedron(int(level), _ptr(V), _ptr(F), _ptr(C)) != 0:
+        raise RuntimeError("icosahedron refinement produced the wrong vertex count")
+    return V, F, C
+
+
+def ga_integrate(cells, normals, stride: int = 1):
+    """Alg. 3 by definition (Sec. 6.1.3): (cell index int32 per integrated
+    row, counts uint32 [n_cells]) for rows 0, stride, 2 stride, ... of the
+    float32 normals (decisions in float32, see oracle_ga_integrate)."""
+    c = np.ascontiguousarray(np.asarray(cells, dtype=np.float32).reshape(-1, 3))
+    n = np.ascontiguousarray(np.asarray(normals, dtype=np.float32).reshape(-1, 3))
+    if stride < 1:
+        raise ValueError("stride must be >= 1")
+    rows = (len(n) + stride - 1) // stride
+    idx = np.empty(max(rows, 1), dtype=np.int32)
+    counts = np.zeros(len(c), dtype=np.uint32)
+    _load().oracle_ga_integrate(_ptr(c), len(c), _ptr(n), len(n), int(stride), _ptr(idx),
+                                _ptr(counts))
+    return idx[:rows].copy(), counts

@@ -8,8 +8,9 @@
  * constant with the HIP library, and the HIP library never calls it.
  *
  * Every floating-point step runs in double precision on double inputs (the
- * caller promotes the float32 frame), except in group assignment, whose
- * comparisons decide an integer label and are taken in float32 (see there).  Loops follow the paper's definitions
+ * caller promotes the float32 frame), except in group assignment and in the
+ * Gaussian accumulator's integration, whose comparisons decide an integer
+ * label or cell and are taken in float32 (see there).  Loops follow the paper's definitions
  * directly; the only parallelism is an OpenMP loop over independent outputs,
  * so results do not depend on the thread count.
  *
@@ -445,5 +446,164 @@ OR_EXPORT void oracle_group_assign(const float *pts, int64_t n_pts, const int32_
         }
         if (best < ang_min) g = 255;
         groups[t] = (uint8_t)g;
+    }
+}
+
+/*
+ * Gaussian accumulator (Sec. 6.1): the refined icosahedron of Sec. 6.1.1 and
+ * the integration of unit normals into its cells (Alg. 3).
+ *
+ * Level 0 is the regular icosahedron with vertices on the unit sphere; each
+ * refinement splits every triangle into four through its edge midpoints and
+ * pushes the new vertices out onto the sphere.  Level L has 10 * 4^L + 2
+ * vertices and 20 * 4^L triangles (Table 1).  Each triangle is a cell of the
+ * histogram; its surface normal is the unit normal of the triangle's plane,
+ * pointing out of the sphere.
+ * Reading: the cell normal is the plane normal (b - a) x (c - a), normalised;
+ * the minimum angle between edge-adjacent cell normals reproduces Table 1's
+ * separations at every level (a test checks it).
+ *
+ * Integration: the paper's search (space-filling-curve index, windowed
+ * binary search, local neighbour search) is a fast way to find the cell
+ * whose surface normal is closest to the input normal; the oracle takes that
+ * definition directly, by brute force over all cells.
+ * Reading (precision): the choice of cell decides an integer, so it is made
+ * in float32 on float32 cell normals, with the squared distance written as
+ *     d = c - n,  |d|^2 = fma(dx, dx, fma(dy, dy, dz * dz))
+ * and the first cell with the smallest value winning (strict <).  A normal
+ * with a NaN or infinite coordinate lands in no cell (index -1, not counted).
+ * Sampling: rows 0, stride, 2 stride, ... of the normal list are integrated
+ * (the paper integrates a sample of the mesh normals).
+ */
+static const double ICO_T = 1.6180339887498948482; /* golden ratio */
+
+/* Base icosahedron: the 12 points (0, +-1, +-t) and their cyclic
+ * permutations, and its 20 faces wound counter-clockwise seen from outside. */
+static const double ico_base_v[12][3] = {
+    {-1, ICO_T, 0}, {1, ICO_T, 0}, {-1, -ICO_T, 0}, {1, -ICO_T, 0},
+    {0, -1, ICO_T}, {0, 1, ICO_T}, {0, -1, -ICO_T}, {0, 1, -ICO_T},
+    {ICO_T, 0, -1}, {ICO_T, 0, 1}, {-ICO_T, 0, -1}, {-ICO_T, 0, 1}};
+static const int ico_base_f[20][3] = {
+    {0, 11, 5}, {0, 5, 1}, {0, 1, 7}, {0, 7, 10}, {0, 10, 11},
+    {1, 5, 9}, {5, 11, 4}, {11, 10, 2}, {10, 7, 6}, {7, 1, 8},
+    {3, 9, 4}, {3, 4, 2}, {3, 2, 6}, {3, 6, 8}, {3, 8, 9},
+    {4, 9, 5}, {2, 4, 11}, {6, 2, 10}, {8, 6, 7}, {9, 8, 1}};
+
+static void unit3(double *v)
+{
+    const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= r; v[1] /= r; v[2] /= r;
+}
+
+OR_EXPORT int oracle_ga_sizes(int level, int64_t *n_vertices, int64_t *n_faces)
+{
+    if (level < 0 || level > 7) return -1;
+    int64_t f = 20;
+    for (int l = 0; l < level; ++l) f *= 4;
+    *n_faces = f;
+    *n_vertices = f / 2 + 2;
+    return 0;
+}
+
+/* Midpoint vertex of edge (a, b), created once per edge: an open-addressed
+ * table keyed by the ordered pair. */
+typedef struct {
+    int64_t *key;
+    int32_t *val;
+    int64_t cap;
+} edge_map;
+
+static int32_t edge_mid(edge_map *m, double *V, int32_t *nv, int32_t a, int32_t b)
+{
+    const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    const int64_t k = ((int64_t)lo << 32) | (uint32_t)hi;
+    uint64_t h = (uint64_t)k * 0x9E3779B97F4A7C15ull;
+    int64_t i = (int64_t)(h % (uint64_t)m->cap);
+    while (m->key[i] != -1 && m->key[i] != k) i = (i + 1) % m->cap;
+    if (m->key[i] == k) return m->val[i];
+    const int32_t id = (*nv)++;
+    for (int c = 0; c < 3; ++c) V[3 * id + c] = 0.5 * (V[3 * lo + c] + V[3 * hi + c]);
+    unit3(V + 3 * id);
+    m->key[i] = k;
+    m->val[i] = id;
+    return id;
+}
+
+/* Refined icosahedron of `level`: vertices [V][3] (double, unit length),
+ * faces [F][3] (counter-clockwise from outside) and cell normals [F][3]
+ * rounded to float32.  Returns 0, or -1 for a level outside [0, 7]. */
+OR_EXPORT int oracle_ga_icosahedron(int level, double *V, int32_t *F, float *cells)
+{
+    int64_t nv_all, nf_all;
+    if (oracle_ga_sizes(level, &nv_all, &nf_all)) return -1;
+    int32_t nv = 12;
+    int64_t nf = 20;
+    for (int i = 0; i < 12; ++i) {
+        for (int c = 0; c < 3; ++c) V[3 * i + c] = ico_base_v[i][c];
+        unit3(V + 3 * i);
+    }
+    for (int i = 0; i < 20; ++i)
+        for (int c = 0; c < 3; ++c) F[3 * i + c] = ico_base_f[i][c];
+    int32_t *G = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)nf_all);
+    for (int l = 0; l < level; ++l) {
+        edge_map m;
+        m.cap = 4 * nf + 7;
+        m.key = (int64_t *)malloc(sizeof(int64_t) * (size_t)m.cap);
+        m.val = (int32_t *)malloc(sizeof(int32_t) * (size_t)m.cap);
+        for (int64_t i = 0; i < m.cap; ++i) m.key[i] = -1;
+        for (int64_t f = 0; f < nf; ++f) {
+            const int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+            const int32_t ab = edge_mid(&m, V, &nv, a, b);
+            const int32_t bc = edge_mid(&m, V, &nv, b, c);
+            const int32_t ca = edge_mid(&m, V, &nv, c, a);
+            const int32_t sub[4][3] = {{a, ab, ca}, {b, bc, ab}, {c, ca, bc}, {ab, bc, ca}};
+            for (int s = 0; s < 4; ++s)
+                for (int k = 0; k < 3; ++k) G[3 * (4 * f + s) + k] = sub[s][k];
+        }
+        free(m.key);
+        free(m.val);
+        nf *= 4;
+        memcpy(F, G, sizeof(int32_t) * 3 * (size_t)nf);
+    }
+    free(G);
+    for (int64_t f = 0; f < nf; ++f) {
+        const double *a = V + 3 * F[3 * f], *b = V + 3 * F[3 * f + 1], *c = V + 3 * F[3 * f + 2];
+        double e1[3], e2[3], n[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = b[k] - a[k];
+            e2[k] = c[k] - a[k];
+        }
+        n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        unit3(n);
+        for (int k = 0; k < 3; ++k) cells[3 * f + k] = (float)n[k];
+    }
+    return nv == nv_all ? 0 : -2;
+}
+
+/* Alg. 3 by its definition: nearest cell normal (float32 squared distance,
+ * first minimum) for rows 0, stride, 2 stride, ... of `normals`; writes the
+ * cell of the j-th integrated row to cell_out[j] (or -1) and adds one to
+ * counts[cell] for each row that lands in a cell. */
+OR_EXPORT void oracle_ga_integrate(const float *cells, int n_cells, const float *normals,
+                                   int64_t n, int stride, int32_t *cell_out, uint32_t *counts)
+{
+    int64_t j = 0;
+    for (int64_t t = 0; t < n; t += stride, ++j) {
+        const float *p = normals + 3 * t;
+        float best = INFINITY;
+        int32_t arg = -1;
+        for (int c = 0; c < n_cells; ++c) {
+            const float dx = cells[3 * c] - p[0], dy = cells[3 * c + 1] - p[1],
+                        dz = cells[3 * c + 2] - p[2];
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (d2 < best) {
+                best = d2;
+                arg = c;
+            }
+        }
+        cell_out[j] = arg;
+        if (arg >= 0) counts[arg] += 1;
     }
 }
