@@ -217,6 +217,60 @@ pl_status pl_group_assign(const float *pts, int32_t n_pts, const int32_t *triang
                           float ang_min, uint8_t *groups, hipStream_t stream);
 
 /*
+ * Gaussian accumulator, Sec. 6.1: the cells of a refined icosahedron
+ * (Sec. 6.1.1, Table 1) and the integration of normals into them (Alg. 3).
+ *
+ * Level L (0..5) has 20 * 4^L triangular cells; each cell's surface normal is
+ * the outward unit normal of its plane.  Integration adds one to the count of
+ * the cell whose normal is nearest to each integrated normal: squared
+ * Euclidean distance in float32, d = c - n,
+ *     |d|^2 = fma(dx, dx, fma(dy, dy, dz * dz)),
+ * the lowest cell index among equals.  The result is exactly that of a
+ * brute-force search over all cells (the library finds the cell through a
+ * precomputed table of candidates per direction bin, or over all cells for
+ * normals whose length is outside [0.5, 2]).  A normal with a NaN or
+ * infinite coordinate lands in no cell.
+ *
+ * pl_ga_workspace(level)      bytes of device workspace for a level-L
+ *                             accumulator (0 if L is outside 0..5).  The
+ *                             first call for a level builds its tables on
+ *                             the host (tens of milliseconds at level 4);
+ *                             they are kept for the process.
+ * pl_ga_workspace_cells       the same for caller-given cell normals
+ *                             (host float32 [n_cells][3], 1 <= n_cells <=
+ *                             32768, each of unit length within 1e-5).
+ * pl_ga_create[_cells]        uploads the cells and tables into `ws` (which
+ *                             must stay allocated and untouched until
+ *                             pl_ga_destroy); synchronises `stream` once.
+ * pl_ga_cell_count, pl_ga_cells  the number of cells and a device pointer to
+ *                             their normals, float32 [n_cells][3] inside ws.
+ * pl_ga_integrate             integrates rows 0, stride, 2 stride, ... below
+ *                             min(*n_normals, cap) of `normals` ([cap][3],
+ *                             type ndt, device): counts (uint32 [n_cells],
+ *                             device) are ADDED to (clear them first for a
+ *                             fresh histogram); cell_out (optional, int32
+ *                             [ceil(cap / stride)]) receives row j's cell (or
+ *                             -1) at index j / stride for every integrated
+ *                             row.  n_normals is an int32 device scalar (e.g.
+ *                             pl_mesh_opc's |T| with normals_T).  No
+ *                             allocation; stream-ordered.
+ * pl_ga_destroy               releases the host-side handle.
+ * Integrations into the same counts may run concurrently (atomic adds).
+ */
+typedef struct pl_ga_s *pl_ga;
+size_t pl_ga_workspace(int32_t level);
+size_t pl_ga_workspace_cells(const float *cells, int32_t n_cells);
+pl_status pl_ga_create(int32_t level, void *ws, size_t ws_bytes, hipStream_t stream, pl_ga *out);
+pl_status pl_ga_create_cells(const float *cells, int32_t n_cells, void *ws, size_t ws_bytes,
+                             hipStream_t stream, pl_ga *out);
+int32_t pl_ga_cell_count(pl_ga ga);
+const float *pl_ga_cells(pl_ga ga);
+pl_status pl_ga_integrate(pl_ga ga, const void *normals, pl_dtype ndt, const int32_t *n_normals,
+                          int32_t cap, int32_t stride, uint32_t *counts, int32_t *cell_out,
+                          hipStream_t stream);
+void pl_ga_destroy(pl_ga ga);
+
+/*
  * Tile shapes and sweep fusion ("tuning").  Every stage runs its kernel
  * over tiles of tile_rows x tile_cols (points for the Laplacian, quads for
  * the bilateral) and fuses up to `fuse` sweeps per launch.  float32 results

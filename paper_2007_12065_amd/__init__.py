@@ -86,6 +86,22 @@ _lib.pl_batch_destroy.restype = None
 _lib.pl_group_assign.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _f32, _f32,
                                  _vp, _vp]
 _lib.pl_group_assign.restype = _i32
+_lib.pl_ga_workspace.argtypes = [_i32]
+_lib.pl_ga_workspace.restype = _sz
+_lib.pl_ga_workspace_cells.argtypes = [_vp, _i32]
+_lib.pl_ga_workspace_cells.restype = _sz
+_lib.pl_ga_create.argtypes = [_i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]
+_lib.pl_ga_create.restype = _i32
+_lib.pl_ga_create_cells.argtypes = [_vp, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]
+_lib.pl_ga_create_cells.restype = _i32
+_lib.pl_ga_cell_count.argtypes = [_vp]
+_lib.pl_ga_cell_count.restype = _i32
+_lib.pl_ga_cells.argtypes = [_vp]
+_lib.pl_ga_cells.restype = _vp
+_lib.pl_ga_integrate.argtypes = [_vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp]
+_lib.pl_ga_integrate.restype = _i32
+_lib.pl_ga_destroy.argtypes = [_vp]
+_lib.pl_ga_destroy.restype = None
 
 PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL, PL_STAGE_BATCH_LAPLACIAN, PL_STAGE_BATCH_BILATERAL = 0, 1, 2, 3
 
@@ -94,7 +110,9 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
            "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
            "pl_batch_replay", "pl_batch_capture_bounded", "pl_batch_replay_bounded",
-           "pl_batch_destroy", "pl_smooth_batch", "pl_group_assign"]
+           "pl_batch_destroy", "pl_smooth_batch", "pl_group_assign", "pl_ga_workspace",
+           "pl_ga_workspace_cells", "pl_ga_create", "pl_ga_create_cells", "pl_ga_cell_count",
+           "pl_ga_cells", "pl_ga_integrate", "pl_ga_destroy"]
 
 
 class PLError(RuntimeError):
@@ -286,6 +304,83 @@ def pl_group_assign(points: torch.Tensor, triangles: torch.Tensor, normals_T: to
                                 _ptr(normals_T), ndt, _ptr(n_tri), cap, _ptr(dominant), l,
                                 l_max, ang_min, _ptr(out), _stream(dev)), "pl_group_assign")
     return out[:cap]
+
+
+class GaussianAccumulator:
+    """Sec. 6.1: a refined icosahedron's cells (pl_ga_* in include/pl.h).
+
+    GaussianAccumulator(level) builds the library's level-`level` cells;
+    GaussianAccumulator(cells=host float32 [n, 3]) uses the given unit cell
+    normals.  The workspace is allocated here and kept with the handle."""
+
+    def __init__(self, level: int | None = None, cells=None, device=None):
+        import numpy as np
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        h = _vp()
+        if cells is None:
+            n = _lib.pl_ga_workspace(int(level))
+            if n == 0:
+                raise PLError(-1, "pl_ga_workspace")
+            self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+            _check(_lib.pl_ga_create(int(level), _ptr(self.ws), n, _stream(self.device),
+                                     ctypes.byref(h)), "pl_ga_create")
+        else:
+            c = np.ascontiguousarray(np.asarray(cells, dtype=np.float32).reshape(-1, 3))
+            cp = c.ctypes.data_as(ctypes.c_void_p)
+            n = _lib.pl_ga_workspace_cells(cp, len(c))
+            if n == 0:
+                raise PLError(-1, "pl_ga_workspace_cells")
+            self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+            _check(_lib.pl_ga_create_cells(cp, len(c), _ptr(self.ws), n, _stream(self.device),
+                                           ctypes.byref(h)), "pl_ga_create_cells")
+        self._h = h
+        self.n_cells = int(_lib.pl_ga_cell_count(h))
+
+    def cells(self) -> torch.Tensor:
+        """The cell normals, float32 [n_cells, 3] (a copy)."""
+        out = torch.empty((self.n_cells, 3), dtype=torch.float32, device=self.device)
+        base = _lib.pl_ga_cells(self._h)
+        off = base - self.ws.data_ptr()
+        out.copy_(self.ws[off:off + 12 * self.n_cells].view(torch.float32).view(self.n_cells, 3))
+        return out
+
+    def integrate(self, normals: torch.Tensor, n: torch.Tensor | None = None, stride: int = 1,
+                  counts: torch.Tensor | None = None, cell_out: bool | torch.Tensor = False):
+        """Alg. 3 over rows 0, stride, ... below n (int32 [1] device tensor;
+        None = all rows) of normals [cap, 3] (float32 or float16).  Returns
+        (counts uint32 [n_cells], added to when given; cell per integrated row
+        int32 or None)."""
+        ndt = _ndt(normals.dtype)
+        _dev_tensor(normals, _tdtype(ndt), "normals")
+        if normals.dim() != 2 or normals.shape[1] != 3:
+            raise ValueError("normals must be [cap, 3]")
+        cap = int(normals.shape[0])
+        if n is None:
+            n = torch.full((1,), cap, dtype=torch.int32, device=normals.device)
+        _dev_tensor(n, torch.int32, "n")
+        if counts is None:
+            counts = torch.zeros(self.n_cells, dtype=torch.uint32, device=normals.device)
+        _dev_tensor(counts, torch.uint32, "counts")
+        rows = 0 if cap == 0 else (cap - 1) // stride + 1
+        if cell_out is True:
+            cell_out = torch.empty(max(rows, 1), dtype=torch.int32, device=normals.device)
+        elif cell_out is False:
+            cell_out = None
+        _check(_lib.pl_ga_integrate(self._h, _ptr(normals), ndt, _ptr(n), cap, int(stride),
+                                    _ptr(counts), _ptr(cell_out), _stream(normals.device)),
+               "pl_ga_integrate")
+        return counts, (cell_out[:rows] if cell_out is not None else None)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.pl_ga_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FramePlan:

@@ -1,6 +1,7 @@
 // extern "C" entry points of libpl.so: argument validation, then dispatch to
 // the kernel launchers.  Nothing is enqueued when validation fails.
 #include "common.h"
+#include "ga.h"
 #include "tuning.h"
 
 #include <algorithm>
@@ -107,7 +108,7 @@ static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
 
 extern "C" {
 
-__attribute__((visibility("default"))) int32_t pl_version(void) { return 102; }
+__attribute__((visibility("default"))) int32_t pl_version(void) { return 103; }
 
 __attribute__((visibility("default"))) const char *pl_last_error(void) { return g_err; }
 
@@ -551,6 +552,127 @@ __attribute__((visibility("default"))) pl_status pl_group_assign(
     return launch_group_assign(pts, n_pts, triangles, normals_T, ndt, n_tri, cap, dominant, l,
                                l_max, ang_min, groups, stream);
 }
+
+__attribute__((visibility("default"))) size_t pl_ga_workspace(int32_t level) {
+    if (level < 0 || level > kGaMaxLevel) return 0;
+    return ga_level_workspace(level);
+}
+
+}  // extern "C"
+
+namespace {
+
+pl_status check_cells(const float *cells, int32_t n_cells) {
+    if (!cells || n_cells < 1 || n_cells > kGaMaxCells) {
+        set_error("cells: need 1..%d host cell normals", kGaMaxCells);
+        return PL_ERR_ARG;
+    }
+    for (int32_t i = 0; i < n_cells; ++i) {
+        const double x = cells[3 * i], y = cells[3 * i + 1], z = cells[3 * i + 2];
+        const double r = sqrt(x * x + y * y + z * z);
+        if (!(fabs(r - 1.0) <= 1e-5)) {
+            set_error("cell %d is not a unit vector", i);
+            return PL_ERR_ARG;
+        }
+    }
+    return PL_OK;
+}
+
+pl_status check_ga_ws(void *ws, size_t ws_bytes, size_t need, hipStream_t stream, pl_ga *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return PL_ERR_ARG;
+    }
+    *out = nullptr;
+    (void)stream;
+    return check_ws(ws, ws_bytes, need);
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) size_t pl_ga_workspace_cells(const float *cells,
+                                                                    int32_t n_cells) {
+    if (check_cells(cells, n_cells)) return 0;
+    return ga_cells_workspace(cells, n_cells);
+}
+
+__attribute__((visibility("default"))) pl_status pl_ga_create(int32_t level, void *ws,
+                                                              size_t ws_bytes,
+                                                              hipStream_t stream, pl_ga *out) {
+    g_err[0] = 0;
+    if (level < 0 || level > kGaMaxLevel) {
+        set_error("level %d: must be in [0, %d]", level, kGaMaxLevel);
+        if (out) *out = nullptr;
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ga_ws(ws, ws_bytes, ga_level_workspace(level), stream, out));
+    return ga_create_level(level, ws, stream, out);
+}
+
+__attribute__((visibility("default"))) pl_status pl_ga_create_cells(const float *cells,
+                                                                    int32_t n_cells, void *ws,
+                                                                    size_t ws_bytes,
+                                                                    hipStream_t stream,
+                                                                    pl_ga *out) {
+    g_err[0] = 0;
+    if (out) *out = nullptr;
+    PL_TRY(check_cells(cells, n_cells));
+    PL_TRY(check_ga_ws(ws, ws_bytes, ga_cells_workspace(cells, n_cells), stream, out));
+    return ga_create_cells(cells, n_cells, ws, stream, out);
+}
+
+__attribute__((visibility("default"))) int32_t pl_ga_cell_count(pl_ga ga) {
+    return ga ? ga_cell_count(ga) : 0;
+}
+
+__attribute__((visibility("default"))) const float *pl_ga_cells(pl_ga ga) {
+    return ga ? ga_cells(ga) : nullptr;
+}
+
+__attribute__((visibility("default"))) pl_status pl_ga_integrate(
+    pl_ga ga, const void *normals, pl_dtype ndt, const int32_t *n_normals, int32_t cap,
+    int32_t stride, uint32_t *counts, int32_t *cell_out, hipStream_t stream) {
+    g_err[0] = 0;
+    if (!ga) {
+        set_error("ga is NULL");
+        return PL_ERR_ARG;
+    }
+    if (ndt != PL_F32 && ndt != PL_F16) {
+        set_error("unknown normal dtype %d", (int)ndt);
+        return PL_ERR_ARG;
+    }
+    if (cap < 0 || stride < 1) {
+        set_error("cap %d, stride %d: need cap >= 0 and stride >= 1", cap, stride);
+        return PL_ERR_ARG;
+    }
+    if (3.0 * (double)cap >= 2147483648.0) {
+        set_error("cap %d: 3 cap must stay below 2^31", cap);
+        return PL_ERR_SHAPE;
+    }
+    PL_TRY(check_ptrs({{n_normals, "n_normals"}, {counts, "counts"}}));
+    if (cap > 0) PL_TRY(check_ptrs({{normals, "normals"}}));
+    if (cell_out) PL_TRY(check_ptrs({{cell_out, "cell_out"}}));
+    const size_t rows = cap == 0 ? 0 : (size_t)(cap - 1) / stride + 1;
+    const Range cr{counts, 4 * (size_t)ga_cell_count(ga)};
+    const Range orr{cell_out, 4 * rows};
+    const Range ins[] = {{normals, (size_t)cap * 3 * (ndt == PL_F32 ? 4 : 2)},
+                         {n_normals, 4},
+                         {ga_cells(ga), ga_bytes(ga)}};
+    for (const Range &r : ins)
+        if (overlap(cr, r) || overlap(orr, r)) {
+            set_error("counts and cell_out must not overlap an input or the accumulator");
+            return PL_ERR_ALIAS;
+        }
+    if (overlap(cr, orr)) {
+        set_error("counts and cell_out overlap");
+        return PL_ERR_ALIAS;
+    }
+    return ga_integrate(ga, normals, ndt, n_normals, cap, stride, counts, cell_out, stream);
+}
+
+__attribute__((visibility("default"))) void pl_ga_destroy(pl_ga ga) { ga_destroy(ga); }
 
 __attribute__((visibility("default"))) pl_status pl_smooth_batch(const pl_frame *frames, int32_t n,
                                                                  pl_dtype ndt, void *ws,

@@ -12,8 +12,11 @@ __global__ __launch_bounds__(kGroupBlock) void k_group_assign(
     const NT *__restrict__ normals, const int32_t *__restrict__ n_tri, int cap,
     const float *__restrict__ dom, int l, float lmax2, float ang_min,
     uint8_t *__restrict__ groups) {
+    // each XCD takes one contiguous eighth of T, so the vertex rows that
+    // neighbouring workgroups share meet in one L2
+    const int chunk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     group_rows<NT>(pts, n_pts, tris, normals, n_tri, cap, dom, l, lmax2, ang_min, groups,
-                   (blockIdx.x * kGroupBlock + threadIdx.x) * kGroupPer);
+                   (chunk * kGroupBlock + (int)threadIdx.x) * kGroupPer);
 }
 
 }  // namespace

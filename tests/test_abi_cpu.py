@@ -32,7 +32,7 @@ def test_header_symbols_exported(pl):
 
 
 def test_version(pl):
-    assert pl.pl_version() == 102
+    assert pl.pl_version() == 103
 
 
 def test_workspace_sizes(pl):
@@ -158,6 +158,28 @@ def test_batch_group_fields_checked(pl):
     g.n_dominant, g.dominant = 0, None
     assert lib.pl_batch_workspace((pl.PLFrame * 1)(g), 1, 0) > plain
     assert T > 0
+
+
+def test_ga_host_side(pl):
+    """Accumulator sizes and argument checks (host only)."""
+    import numpy as np
+    lib = pl._lib
+    sizes = [lib.pl_ga_workspace(L) for L in range(6)]
+    assert all(s > 0 for s in sizes) and sizes == sorted(sizes)
+    # cells, bin table and candidate lists: the cells alone take 12 B each
+    assert sizes[4] > 12 * 5120
+    assert lib.pl_ga_workspace(-1) == 0 and lib.pl_ga_workspace(6) == 0
+    cells = np.array([[0, 0, 1], [0, 1, 0], [1, 0, 0]], dtype=np.float32)
+    cp = cells.ctypes.data_as(ctypes.c_void_p)
+    assert lib.pl_ga_workspace_cells(cp, 3) > 0
+    bad = cells * 1.01
+    assert lib.pl_ga_workspace_cells(bad.ctypes.data_as(ctypes.c_void_p), 3) == 0
+    assert lib.pl_ga_workspace_cells(None, 3) == 0
+    h = ctypes.c_void_p()
+    assert lib.pl_ga_create(9, A, 1 << 20, None, ctypes.byref(h)) == -1 and not h.value
+    assert lib.pl_ga_create(2, A, 16, None, ctypes.byref(h)) == -5
+    assert lib.pl_ga_integrate(None, A, 0, B, 10, 1, C, None, None) == -1
+    assert lib.pl_ga_cell_count(None) == 0
 
 
 def test_tuning_table_stages(pl):
