@@ -188,6 +188,51 @@ def groups_bench(plans, k, stream, s, reps=300):
             "cpu_oracle_labels_per_s": round(n_tri / cpu_s, 1), "cpu_oracle_threads": 1}
 
 
+def ga_bench(plans, stream, reps=200, level=4, stride=1):
+    """Gaussian accumulator integration (Alg. 3) of each frame's filtered
+    normals (all |T| rows, float32) into a level-4 accumulator: per-launch
+    time of k_ga_integrate, normals per second, algorithmic HBM bytes (the
+    normals read once; cells, bin tables and counts stay in cache), and the
+    oracle's brute-force rate on one thread for the same normals."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2007_12065_amd as pl
+    sets = len(plans)
+    ga = pl.GaussianAccumulator(level, device=plans[0].device)
+    counts = torch.zeros(ga.n_cells, dtype=torch.uint32, device=plans[0].device)
+    for i in range(sets):
+        ga.integrate(plans[i].normals_T, n=plans[i].n_tri, stride=stride, counts=counts)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for i in range(reps):
+        ga.integrate(plans[i % sets].normals_T, n=plans[i % sets].n_tri, stride=stride, counts=counts)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    n_tri = float(np.mean([int(p.n_tri.item()) for p in plans]))
+    rows = n_tri / stride
+    nbytes = 12 * rows
+    p0 = plans[0]
+    n0 = int(p0.n_tri.item())
+    normals = p0.normals_T[:n0].cpu().numpy()
+    from oracle import ga_icosahedron
+    _, _, cells = ga_icosahedron(level)
+    sample = normals[: max(1, len(normals) // 50)]
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.ga_integrate(cells, sample)
+    cpu_s = time.perf_counter() - t0
+    ga.close()
+    return {"kernel": "k_ga_integrate", "level": level, "cells": 20 * 4 ** level, "stride": stride,
+            "launch_us": round(us, 2), "normals_per_s": round(rows / (us * 1e-6), 1),
+            "bytes_per_launch": int(nbytes), "achieved_gbs": round(nbytes / (us * 1e-6) / 1e9, 1),
+            "hbm_frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "cpu_oracle_normals_per_s": round(len(sample) / cpu_s, 1), "cpu_oracle_threads": 1,
+            "cpu_oracle_sample": f"{len(sample)} normals of one frame, brute force over all cells"}
+
+
 def angle_stats(got, ref):
     import numpy as np
     g = np.asarray(got, dtype=np.float64).reshape(-1, 3)
@@ -471,6 +516,10 @@ def main():
     }
     print("[bench] group assignment", file=sys.stderr, flush=True)
     out["groups"] = groups_bench(plans, k, stream, s)
+    print("[bench] gaussian accumulator", file=sys.stderr, flush=True)
+    out["gaussian_accumulator"] = ga_bench(plans, stream)
+    # the paper integrates a sample of about 12% of the normals (sample_pct)
+    out["gaussian_accumulator_sampled"] = ga_bench(plans, stream, stride=8)
     if args.batched:
         print("[bench] batched 64-frame mix", file=sys.stderr, flush=True)
         out["batched"] = batched_bench(tune_cache=args.tune_cache)

@@ -255,7 +255,9 @@ pl_status pl_group_assign(const float *pts, int32_t n_pts, const int32_t *triang
  *                             pl_mesh_opc's |T| with normals_T).  No
  *                             allocation; stream-ordered.
  * pl_ga_destroy               releases the host-side handle.
- * Integrations into the same counts may run concurrently (atomic adds).
+ * Integrations through one accumulator must not overlap in time (they share
+ * its scratch histograms in ws); different accumulators may add into the
+ * same counts concurrently (atomic adds).
  */
 typedef struct pl_ga_s *pl_ga;
 size_t pl_ga_workspace(int32_t level);

@@ -11,14 +11,21 @@
 // be nearest for some direction in the bin (a conservative angular bound,
 // padded for the float32 rounding of the bin index and of the distances).
 // A normal then costs one bin computation and the distances to its bin's
-// few candidates, and the chosen cell is exactly the brute-force one.
+// few candidates (stored with their cell normals, so a search is two
+// dependent table loads), and the chosen cell is exactly the brute-force
+// one.
 // Normals whose length is outside [0.5, 2] (zero, NaN, infinite or badly
 // scaled) are searched over all cells, which keeps the result the
 // brute-force one for every input.
 //
 // Counts accumulate in an LDS histogram per workgroup (every cell's count,
-// 4 bytes each) and are flushed with one global atomic add per non-zero
-// cell; sums of integers do not depend on the order of the adds.
+// 4 bytes each).  A scene's normals crowd into a few cells, and atomic adds
+// to one address serialise (about 30 ns each), so workgroups flush their
+// non-zero cells into one of kGaReplicas copies of the histogram in the
+// accumulator's workspace (copy = workgroup index mod kGaReplicas, which
+// also keeps each copy on one XCD), and a second launch folds the copies
+// into the caller's counts and clears them.  Sums of integers do not depend
+// on the order of the adds.
 #include "ga.h"
 #include "tuning.h"
 
@@ -38,7 +45,15 @@ namespace pl {
 namespace {
 
 constexpr int kGaBlock = 256;
-constexpr int kGaMaxGrid = 2048;           // workgroups of one integration launch
+#ifndef PL_GA_PER
+#define PL_GA_PER 4
+#endif
+constexpr int kGaPer = PL_GA_PER;          // integrated rows per thread and pass
+#ifndef PL_GA_MAX_GRID
+#define PL_GA_MAX_GRID 1024
+#endif
+constexpr int kGaMaxGrid = PL_GA_MAX_GRID;  // workgroups of one integration launch
+constexpr int kGaReplicas = 16;             // histogram copies the workgroups flush into
 
 // Bin of a direction with |n|^2 in [0.25, 4]: the cube face of its largest
 // component (+x, -x, +y, -y, +z, -z), then the two other components over
@@ -65,62 +80,109 @@ __device__ __forceinline__ float ga_d2(const float *__restrict__ c, float x, flo
     return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
 }
 
-__device__ __forceinline__ int ga_nearest(float x, float y, float z,
-                                          const float *__restrict__ cells, int n_cells,
-                                          const int *__restrict__ bin_start,
-                                          const uint16_t *__restrict__ bin_cells, int G) {
+// Brute force over all cells (normals whose length is outside [0.5, 2]).
+__device__ __noinline__ int ga_nearest_all(float x, float y, float z,
+                                           const float *__restrict__ cells, int n_cells) {
     float best = __builtin_inff();
     int arg = -1;
-    const float s2 = fmaf(x, x, fmaf(y, y, z * z));
-    if (s2 >= 0.25f && s2 <= 4.0f) {
-        const int b = ga_bin(x, y, z, G);
-        const int k0 = bin_start[b], k1 = bin_start[b + 1];
-        for (int k = k0; k < k1; ++k) {
-            const int c = bin_cells[k];
-            const float d2 = ga_d2(cells + 3 * c, x, y, z);
-            if (d2 < best) {
-                best = d2;
-                arg = c;
-            }
-        }
-    } else {
-        for (int c = 0; c < n_cells; ++c) {
-            const float d2 = ga_d2(cells + 3 * c, x, y, z);
-            if (d2 < best) {
-                best = d2;
-                arg = c;
-            }
+    for (int c = 0; c < n_cells; ++c) {
+        const float d2 = ga_d2(cells + 3 * c, x, y, z);
+        if (d2 < best) {
+            best = d2;
+            arg = c;
         }
     }
     return arg;
 }
 
+// Each thread takes kGaPer consecutive integrated rows and runs their
+// searches side by side (loads of all rows, then of all bins, then the
+// candidates in lockstep), so several dependent load chains are in flight
+// per thread.
 template <typename NT>
 __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
     const NT *__restrict__ normals, const int32_t *__restrict__ n_dev, int cap, int stride,
     const float *__restrict__ cells, int n_cells, const int *__restrict__ bin_start,
-    const uint16_t *__restrict__ bin_cells, int G, uint32_t *__restrict__ counts,
+    const float4 *__restrict__ bin_cells, int G, uint32_t *__restrict__ replicas,
     int32_t *__restrict__ cell_out) {
     extern __shared__ uint32_t hist[];
     const int n = min(max(*n_dev, 0), cap);
     const int rows = n == 0 ? 0 : (n - 1) / stride + 1;
-    const int first = (int)blockIdx.x * kGaBlock;
+    const int span = (int)gridDim.x * kGaBlock * kGaPer;
+    const int first = (int)blockIdx.x * kGaBlock * kGaPer;
     if (first >= rows) return;                       // the whole workgroup has no row
     for (int i = threadIdx.x; i < n_cells; i += kGaBlock) hist[i] = 0u;
     __syncthreads();
-    for (int j = first + (int)threadIdx.x; j < rows; j += (int)gridDim.x * kGaBlock) {
-        const size_t t = (size_t)j * (size_t)stride;
-        const float x = ld_f(normals + 3 * t), y = ld_f(normals + 3 * t + 1),
-                    z = ld_f(normals + 3 * t + 2);
-        const int c = ga_nearest(x, y, z, cells, n_cells, bin_start, bin_cells, G);
-        if (cell_out) cell_out[j] = c;
-        if (c >= 0) atomicAdd(&hist[c], 1u);
+    for (int base = first + (int)threadIdx.x * kGaPer; base < rows; base += span) {
+        float x[kGaPer], y[kGaPer], z[kGaPer];
+#pragma unroll
+        for (int q = 0; q < kGaPer; ++q) {
+            const int j = min(base + q, rows - 1);   // rows past the end repeat the last one
+            const size_t t = (size_t)j * (size_t)stride;
+            x[q] = ld_f(normals + 3 * t);
+            y[q] = ld_f(normals + 3 * t + 1);
+            z[q] = ld_f(normals + 3 * t + 2);
+        }
+        int lo[kGaPer], len[kGaPer], arg[kGaPer];
+        bool all[kGaPer];
+        int longest = 0;
+#pragma unroll
+        for (int q = 0; q < kGaPer; ++q) {
+            const float s2 = fmaf(x[q], x[q], fmaf(y[q], y[q], z[q] * z[q]));
+            all[q] = !(s2 >= 0.25f && s2 <= 4.0f);
+            const int b = all[q] ? 0 : ga_bin(x[q], y[q], z[q], G);
+            lo[q] = bin_start[b];
+            len[q] = all[q] ? 0 : bin_start[b + 1] - lo[q];
+            longest = max(longest, len[q]);
+            arg[q] = -1;
+        }
+        float best[kGaPer];
+#pragma unroll
+        for (int q = 0; q < kGaPer; ++q) best[q] = __builtin_inff();
+        for (int k = 0; k < longest; ++k) {
+#pragma unroll
+            for (int q = 0; q < kGaPer; ++q) {
+                if (k < len[q]) {
+                    // a candidate is its cell's normal with the cell index in w
+                    const float4 e = bin_cells[lo[q] + k];
+                    const float dx = e.x - x[q], dy = e.y - y[q], dz = e.z - z[q];
+                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    if (d2 < best[q]) {
+                        best[q] = d2;
+                        arg[q] = (int)__float_as_uint(e.w);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kGaPer; ++q) {
+            if (base + q >= rows) break;
+            const int c = all[q] ? ga_nearest_all(x[q], y[q], z[q], cells, n_cells) : arg[q];
+            if (cell_out) cell_out[base + q] = c;
+            if (c >= 0) atomicAdd(&hist[c], 1u);
+        }
     }
     __syncthreads();
+    uint32_t *copy = replicas + (size_t)(blockIdx.x % kGaReplicas) * n_cells;
     for (int i = threadIdx.x; i < n_cells; i += kGaBlock) {
         const uint32_t v = hist[i];
-        if (v) atomicAdd(&counts[i], v);
+        if (v) atomicAdd(&copy[i], v);
     }
+}
+
+// counts[i] += sum of the copies' cell i; the copies return to zero.
+__global__ __launch_bounds__(kGaBlock) void k_ga_fold(uint32_t *__restrict__ replicas,
+                                                      int n_cells, uint32_t *__restrict__ counts) {
+    const int i = (int)blockIdx.x * kGaBlock + (int)threadIdx.x;
+    if (i >= n_cells) return;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kGaReplicas; ++r) {
+        uint32_t *p = replicas + (size_t)r * n_cells + i;
+        sum += *p;
+        *p = 0u;
+    }
+    if (sum) atomicAdd(&counts[i], sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -249,8 +311,8 @@ struct GaTables {
     int n_cells = 0, G = 0;
     std::vector<float> cells;
     std::vector<int32_t> bin_start;
-    std::vector<uint16_t> bin_cells;
-    size_t off_cells = 0, off_start = 0, off_list = 0, bytes = 0;
+    std::vector<float> bin_cells;     // per candidate: x, y, z, cell index (bits)
+    size_t off_cells = 0, off_start = 0, off_list = 0, off_replicas = 0, bytes = 0;
 };
 
 constexpr double kPad = 1e-5;      // (u, v) padding: float32 rounding of the bin index
@@ -307,12 +369,19 @@ std::unique_ptr<GaTables> build_tables(const float *cells, int n_cells, int G) {
         total += lists[b].size();
     }
     T->bin_start[lists.size()] = (int32_t)total;
-    T->bin_cells.reserve(total);
-    for (auto &L : lists) T->bin_cells.insert(T->bin_cells.end(), L.begin(), L.end());
+    T->bin_cells.reserve(4 * total);
+    for (auto &L : lists)
+        for (uint16_t c : L) {
+            uint32_t bits = c;
+            float w;
+            std::memcpy(&w, &bits, 4);
+            T->bin_cells.insert(T->bin_cells.end(), {cells[3 * c], cells[3 * c + 1], cells[3 * c + 2], w});
+        }
     T->off_cells = 0;
     T->off_start = align_up(12 * (size_t)n_cells, 256);
     T->off_list = T->off_start + align_up(4 * T->bin_start.size(), 256);
-    T->bytes = T->off_list + align_up(2 * std::max<size_t>(total, 1), 256);
+    T->off_replicas = T->off_list + align_up(16 * std::max<size_t>(total, 1), 256);
+    T->bytes = T->off_replicas + align_up(4 * (size_t)kGaReplicas * n_cells, 256);
     return T;
 }
 
@@ -355,10 +424,10 @@ namespace {
 
 pl_status ga_upload(pl_ga_s *g, hipStream_t s) {
     const GaTables &T = *g->tab;
-    std::vector<uint8_t> img(T.bytes, 0);
+    std::vector<uint8_t> img(T.bytes, 0);      // the histogram copies start at zero
     std::memcpy(img.data() + T.off_cells, T.cells.data(), 4 * T.cells.size());
     std::memcpy(img.data() + T.off_start, T.bin_start.data(), 4 * T.bin_start.size());
-    std::memcpy(img.data() + T.off_list, T.bin_cells.data(), 2 * T.bin_cells.size());
+    std::memcpy(img.data() + T.off_list, T.bin_cells.data(), 4 * T.bin_cells.size());
     if (pl_status st = hip_check(hipMemcpyAsync(g->ws, img.data(), T.bytes, hipMemcpyHostToDevice, s),
                                  "hipMemcpyAsync"))
         return st;
@@ -408,19 +477,23 @@ pl_status ga_integrate(const pl_ga_s *g, const void *normals, pl_dtype ndt, cons
     if (cap == 0) return PL_OK;
     const GaTables &T = *g->tab;
     const long rows = ((long)cap + stride - 1) / stride;
-    const int grid = (int)std::min<long>(kGaMaxGrid, (rows + kGaBlock - 1) / kGaBlock);
+    const long per_wg = (long)kGaBlock * kGaPer;
+    const int grid = (int)std::min<long>(kGaMaxGrid, (rows + per_wg - 1) / per_wg);
     const float *cells = reinterpret_cast<const float *>(g->ws + T.off_cells);
     const int *start = reinterpret_cast<const int *>(g->ws + T.off_start);
-    const uint16_t *list = reinterpret_cast<const uint16_t *>(g->ws + T.off_list);
+    const float4 *list = reinterpret_cast<const float4 *>(g->ws + T.off_list);
+    uint32_t *reps = reinterpret_cast<uint32_t *>(g->ws + T.off_replicas);
     if (ndt == PL_F32)
         k_ga_integrate<float><<<grid, kGaBlock, g->lds, s>>>(
             static_cast<const float *>(normals), n_dev, cap, stride, cells, T.n_cells, start, list,
-            T.G, counts, cell_out);
+            T.G, reps, cell_out);
     else
         k_ga_integrate<__half><<<grid, kGaBlock, g->lds, s>>>(
             static_cast<const __half *>(normals), n_dev, cap, stride, cells, T.n_cells, start,
-            list, T.G, counts, cell_out);
-    return hip_check(hipGetLastError(), "k_ga_integrate");
+            list, T.G, reps, cell_out);
+    if (pl_status st = hip_check(hipGetLastError(), "k_ga_integrate")) return st;
+    k_ga_fold<<<(T.n_cells + kGaBlock - 1) / kGaBlock, kGaBlock, 0, s>>>(reps, T.n_cells, counts);
+    return hip_check(hipGetLastError(), "k_ga_fold");
 }
 
 void ga_destroy(pl_ga_s *g) { delete g; }
