@@ -24,7 +24,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 __all__ = ["build", "mesh", "halfedges", "laplacian", "tri_normals",
-           "bilateral", "gather", "pipeline", "group_assign", "ga_icosahedron", "ga_integrate"]
+           "bilateral", "gather", "pipeline", "group_assign", "ga_icosahedron", "ga_integrate",
+           "user_halfedges"]
 
 
 def build(force: bool = True) -> str:
@@ -68,6 +69,8 @@ def _load():
         lib.oracle_ga_icosahedron.restype = i32
         lib.oracle_ga_integrate.argtypes = [vp, i32, vp, i64, i32, vp, vp]
         lib.oracle_ga_integrate.restype = None
+        lib.oracle_user_halfedges.argtypes = [vp, i64, vp]
+        lib.oracle_user_halfedges.restype = None
         _lib = lib
     return _lib
 
@@ -206,3 +209,13 @@ def ga_integrate(cells, normals, stride: int = 1):
     _load().oracle_ga_integrate(_ptr(c), len(c), _ptr(n), len(n), int(stride), _ptr(idx),
                                 _ptr(counts))
     return idx[:rows].copy(), counts
+
+
+def user_halfedges(triangles):
+    """Sec. 4.3: twin of every half-edge of a user mesh (int32 [3 n]); edges
+    shared by more than two triangles keep the first pair (option 1, see
+    oracle_user_halfedges)."""
+    t = np.ascontiguousarray(np.asarray(triangles, dtype=np.int32).reshape(-1, 3))
+    out = np.empty(max(3 * len(t), 1), dtype=np.int32)
+    _load().oracle_user_halfedges(_ptr(t), len(t), _ptr(out))
+    return out[:3 * len(t)].copy()

@@ -607,3 +607,70 @@ OR_EXPORT void oracle_ga_integrate(const float *cells, int n_cells, const float 
         if (arg >= 0) counts[arg] += 1;
     }
 }
+
+/*
+ * Half-edges of a user-provided mesh (Sec. 4.3): every half-edge is keyed by
+ * its ordered point pair (a, b) and its twin is the half-edge keyed (b, a).
+ * Half-edge 3t + j of triangle t runs from vertex j to vertex (j+1) mod 3.
+ *
+ * Edges shared by more than two triangles (the second manifold condition
+ * of Sec. 4.3) take the paper's option 1, keep the first pair found:
+ * Reading: "first" is the lowest half-edge index.  A half-edge gets a twin
+ * only if it is the first with its key (a, b); its twin is then the first
+ * half-edge keyed (b, a), if any.  Every other half-edge, and every
+ * half-edge with a == b, gets -1.  The twins are then a symmetric pairing.
+ *
+ * Written as a sort of (key, index) pairs followed by binary searches: the
+ * first half-edge of a key is the head of its run.
+ */
+typedef struct {
+    uint64_t key;
+    int64_t id;
+} he_rec;
+
+static int he_cmp(const void *x, const void *y)
+{
+    const he_rec *a = (const he_rec *)x, *b = (const he_rec *)y;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id);
+}
+
+static uint64_t he_key(int32_t a, int32_t b)
+{
+    return ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+}
+
+/* head of the run with `key` in the sorted records (its lowest id), or -1 */
+static int64_t he_first(const he_rec *r, int64_t n, uint64_t key)
+{
+    int64_t lo = 0, hi = n;                     /* first record with r.key >= key */
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (r[mid].key < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && r[lo].key == key) ? r[lo].id : -1;
+}
+
+OR_EXPORT void oracle_user_halfedges(const int32_t *tris, int64_t n_tri, int32_t *he)
+{
+    he_rec *r = (he_rec *)malloc(sizeof(he_rec) * (size_t)(3 * n_tri + 1));
+    int64_t n = 0;
+    for (int64_t t = 0; t < n_tri; ++t)
+        for (int j = 0; j < 3; ++j) {
+            const int32_t a = tris[3 * t + j], b = tris[3 * t + (j + 1) % 3];
+            if (a != b) {
+                r[n].key = he_key(a, b);
+                r[n].id = 3 * t + j;
+                ++n;
+            }
+        }
+    qsort(r, (size_t)n, sizeof(he_rec), he_cmp);
+    for (int64_t h = 0; h < 3 * n_tri; ++h) he[h] = -1;
+    for (int64_t k = 0; k < n; ++k) {
+        if (k > 0 && r[k - 1].key == r[k].key) continue;     /* not the first of its key */
+        const int32_t a = (int32_t)(r[k].key >> 32), b = (int32_t)(r[k].key & 0xffffffffu);
+        const int64_t g = he_first(r, n, he_key(b, a));
+        he[r[k].id] = (int32_t)g;
+    }
+    free(r);
+}
