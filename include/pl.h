@@ -217,6 +217,35 @@ pl_status pl_group_assign(const float *pts, int32_t n_pts, const int32_t *triang
                           float ang_min, uint8_t *groups, hipStream_t stream);
 
 /*
+ * Half-edges of a user-provided mesh, Sec. 4.3: the twin of every half-edge
+ * of T found through a hash table keyed by ordered point pairs.
+ *
+ * Half-edge 3t + j of triangle t runs from vertex j to vertex (j+1) mod 3;
+ * its twin is a half-edge running the other way between the same two
+ * points.  Edges shared by more than two triangles (meshes that violate the
+ * second manifold condition) take the paper's option 1, keep the first pair:
+ * half-edge h = (a, b) is paired only if no lower-indexed half-edge is also
+ * (a, b), and then with the lowest-indexed half-edge (b, a) if there is one.
+ * Half-edges from a point to itself are never paired.  The pairing is
+ * symmetric, and on a two-manifold mesh it is the usual twin map (on
+ * pl_mesh_opc's T it equals that call's HE).  The output is deterministic.
+ *
+ * triangles  int32 [cap][3] point indices (any int32 values; no point array
+ *            is needed).
+ * n_tri      int32 DEVICE scalar: |T|; triangles t < min(*n_tri, cap) are
+ *            processed (e.g. pl_mesh_opc's count).
+ * halfedges  int32 [3 cap] output; entries at or past 3 min(*n_tri, cap) are
+ *            left untouched.
+ * Workspace: pl_user_halfedges_workspace(cap) bytes (a table of at least
+ * 6 cap slots of 12 bytes; 0 when cap = 0).  PL_ERR_ARG / PL_ERR_SHAPE /
+ * PL_ERR_WORKSPACE / PL_ERR_ALIAS on invalid arguments (nothing enqueued).
+ * Three launches on `stream`, no allocation, graph-capturable.
+ */
+size_t pl_user_halfedges_workspace(int32_t cap);
+pl_status pl_user_halfedges(const int32_t *triangles, const int32_t *n_tri, int32_t cap,
+                            int32_t *halfedges, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Gaussian accumulator, Sec. 6.1: the cells of a refined icosahedron
  * (Sec. 6.1.1, Table 1) and the integration of normals into them (Alg. 3).
  *

@@ -102,6 +102,10 @@ _lib.pl_ga_integrate.argtypes = [_vp, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp]
 _lib.pl_ga_integrate.restype = _i32
 _lib.pl_ga_destroy.argtypes = [_vp]
 _lib.pl_ga_destroy.restype = None
+_lib.pl_user_halfedges_workspace.argtypes = [_i32]
+_lib.pl_user_halfedges_workspace.restype = _sz
+_lib.pl_user_halfedges.argtypes = [_vp, _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.pl_user_halfedges.restype = _i32
 
 PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL, PL_STAGE_BATCH_LAPLACIAN, PL_STAGE_BATCH_BILATERAL = 0, 1, 2, 3
 
@@ -112,7 +116,8 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_batch_replay", "pl_batch_capture_bounded", "pl_batch_replay_bounded",
            "pl_batch_destroy", "pl_smooth_batch", "pl_group_assign", "pl_ga_workspace",
            "pl_ga_workspace_cells", "pl_ga_create", "pl_ga_create_cells", "pl_ga_cell_count",
-           "pl_ga_cells", "pl_ga_integrate", "pl_ga_destroy"]
+           "pl_ga_cells", "pl_ga_integrate", "pl_ga_destroy", "pl_user_halfedges_workspace",
+           "pl_user_halfedges"]
 
 
 class PLError(RuntimeError):
@@ -304,6 +309,30 @@ def pl_group_assign(points: torch.Tensor, triangles: torch.Tensor, normals_T: to
                                 _ptr(normals_T), ndt, _ptr(n_tri), cap, _ptr(dominant), l,
                                 l_max, ang_min, _ptr(out), _stream(dev)), "pl_group_assign")
     return out[:cap]
+
+
+def pl_user_halfedges(triangles: torch.Tensor, n_tri: torch.Tensor | None = None,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """Sec. 4.3: twin of every half-edge of a user mesh, int32 [3 cap]
+    (option 1 for edges shared by more than two triangles).  `triangles` is
+    int32 [cap, 3] on the device; n_tri an int32 [1] device tensor (None =
+    cap).  Entries past 3 n_tri are left as they were (uninitialised when
+    `out` is allocated here)."""
+    _dev_tensor(triangles, torch.int32, "triangles")
+    if triangles.dim() != 2 or triangles.shape[1] != 3:
+        raise ValueError("triangles must be [cap, 3]")
+    cap = int(triangles.shape[0])
+    dev = triangles.device
+    if n_tri is None:
+        n_tri = torch.full((1,), cap, dtype=torch.int32, device=dev)
+    _dev_tensor(n_tri, torch.int32, "n_tri")
+    out = torch.empty(max(3 * cap, 1), dtype=torch.int32, device=dev) if out is None else out
+    _dev_tensor(out, torch.int32, "out")
+    ws_n = _lib.pl_user_halfedges_workspace(cap)
+    ws = _ws(ws_n, dev)
+    _check(_lib.pl_user_halfedges(_ptr(triangles), _ptr(n_tri), cap, _ptr(out), _ptr(ws), ws_n,
+                                  _stream(dev)), "pl_user_halfedges")
+    return out[:3 * cap]
 
 
 class GaussianAccumulator:

@@ -2,6 +2,7 @@
 // the kernel launchers.  Nothing is enqueued when validation fails.
 #include "common.h"
 #include "ga.h"
+#include "he.h"
 #include "tuning.h"
 
 #include <algorithm>
@@ -108,7 +109,7 @@ static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
 
 extern "C" {
 
-__attribute__((visibility("default"))) int32_t pl_version(void) { return 103; }
+__attribute__((visibility("default"))) int32_t pl_version(void) { return 104; }
 
 __attribute__((visibility("default"))) const char *pl_last_error(void) { return g_err; }
 
@@ -673,6 +674,37 @@ __attribute__((visibility("default"))) pl_status pl_ga_integrate(
 }
 
 __attribute__((visibility("default"))) void pl_ga_destroy(pl_ga ga) { ga_destroy(ga); }
+
+__attribute__((visibility("default"))) size_t pl_user_halfedges_workspace(int32_t cap) {
+    if (cap < 0 || 3.0 * (double)cap >= 2147483648.0) return 0;
+    return cap == 0 ? 0 : user_halfedges_workspace(cap);
+}
+
+__attribute__((visibility("default"))) pl_status pl_user_halfedges(
+    const int32_t *triangles, const int32_t *n_tri, int32_t cap, int32_t *halfedges, void *ws,
+    size_t ws_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    if (cap < 0) {
+        set_error("cap %d must not be negative", cap);
+        return PL_ERR_ARG;
+    }
+    if (3.0 * (double)cap >= 2147483648.0) {
+        set_error("cap %d: 3 cap must stay below 2^31", cap);
+        return PL_ERR_SHAPE;
+    }
+    PL_TRY(check_ptrs({{n_tri, "n_tri"}}));
+    if (cap > 0) PL_TRY(check_ptrs({{triangles, "triangles"}, {halfedges, "halfedges"}}));
+    const size_t need = cap == 0 ? 0 : user_halfedges_workspace(cap);
+    PL_TRY(check_ws(ws, ws_bytes, need));
+    const Range tr{triangles, 12 * (size_t)cap}, nr{n_tri, 4}, hr{halfedges, 12 * (size_t)cap},
+        wr{ws, need};
+    if (overlap(hr, tr) || overlap(hr, nr) || overlap(hr, wr) || overlap(wr, tr) ||
+        overlap(wr, nr)) {
+        set_error("halfedges, the workspace and the inputs must not overlap");
+        return PL_ERR_ALIAS;
+    }
+    return launch_user_halfedges(triangles, n_tri, cap, halfedges, ws, stream);
+}
 
 __attribute__((visibility("default"))) pl_status pl_smooth_batch(const pl_frame *frames, int32_t n,
                                                                  pl_dtype ndt, void *ws,

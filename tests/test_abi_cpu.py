@@ -32,7 +32,7 @@ def test_header_symbols_exported(pl):
 
 
 def test_version(pl):
-    assert pl.pl_version() == 103
+    assert pl.pl_version() == 104
 
 
 def test_workspace_sizes(pl):
@@ -180,6 +180,21 @@ def test_ga_host_side(pl):
     assert lib.pl_ga_create(2, A, 16, None, ctypes.byref(h)) == -5
     assert lib.pl_ga_integrate(None, A, 0, B, 10, 1, C, None, None) == -1
     assert lib.pl_ga_cell_count(None) == 0
+
+
+def test_user_halfedges_host_side(pl):
+    lib = pl._lib
+    assert lib.pl_user_halfedges_workspace(0) == 0
+    assert lib.pl_user_halfedges_workspace(-1) == 0
+    assert lib.pl_user_halfedges_workspace(1000) >= 6 * 1000 * 12
+    assert lib.pl_user_halfedges_workspace(1 << 30) == 0
+    ws = lib.pl_user_halfedges_workspace(100)
+    D = 0x400000
+    assert lib.pl_user_halfedges(A, B, -1, C, D, ws, None) == -1
+    assert lib.pl_user_halfedges(A, None, 100, C, D, ws, None) == -1
+    assert lib.pl_user_halfedges(A, B, 100, C, D, ws - 16, None) == -5
+    assert lib.pl_user_halfedges(A, B, 100, A + 256, D, ws, None) == -4   # output over T
+    assert lib.pl_user_halfedges(A, B, 100, C, C + 256, ws, None) == -4   # workspace over output
 
 
 def test_tuning_table_stages(pl):

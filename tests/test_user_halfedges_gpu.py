@@ -1,0 +1,111 @@
+"""GPU parity of user-mesh half-edges (Sec. 4.3, option 1) through the C
+ABI: bit-exact against the oracle on organized meshes at their real sizes
+(where it is also Alg. 2's HE from pl_mesh_opc), on shuffled and relabelled
+meshes with fins, repeated and reversed triangles and degenerate edges, on
+random soups over few points, and for ragged triangle counts."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+UNTOUCHED = -77
+
+
+@pytest.fixture(scope="module")
+def pl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2007_12065_amd as pl
+    return pl
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def gpu_he(pl, tris, n=None):
+    import torch
+    cap = len(tris)
+    out = torch.full((max(3 * cap, 1),), UNTOUCHED, dtype=torch.int32, device="cuda:0")
+    nd = None if n is None else torch.tensor([n], dtype=torch.int32, device="cuda:0")
+    he = pl.pl_user_halfedges(to_dev(np.asarray(tris, dtype=np.int32).reshape(-1, 3)), nd, out=out)
+    torch.cuda.synchronize()
+    return he.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["rgbd", "lidar", "lidar128"])
+def test_organized_meshes(pl, orc, kind):
+    import torch
+    p = synth.make_frame(kind, 31)
+    tri_map, T = orc.mesh(p)
+    M, N = p.shape[:2]
+    want = orc.halfedges(tri_map, M, N, len(T))
+    say("user halfedges", kind, len(T))
+    got = gpu_he(pl, T)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got, oracle.user_halfedges(T))
+    m = pl.pl_mesh_opc(to_dev(p))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, m["halfedges"][:3 * len(T)].cpu().numpy())
+
+
+def _messy_mesh(orc, rng):
+    """An organized mesh shuffled and relabelled, with fins (third
+    triangles on existing edges), repeated and reversed triangles and
+    degenerate ones."""
+    p = synth.random_grid(60, 90, 5, nan_frac=0.1)
+    _, T = orc.mesh(p)
+    relabel = rng.permutation(60 * 90).astype(np.int32)
+    T = relabel[T]
+    extra = []
+    pick = rng.choice(len(T), 400, replace=False)
+    for k, t in enumerate(pick):
+        a, b, c = T[t]
+        if k % 4 == 0:
+            extra.append([b, a, 60 * 90 + k])         # a fin on edge a-b
+        elif k % 4 == 1:
+            extra.append([a, b, c])                   # repeated triangle
+        elif k % 4 == 2:
+            extra.append([a, c, b])                   # reversed triangle
+        else:
+            extra.append([a, a, b])                   # degenerate
+    T = np.concatenate([T, np.array(extra, dtype=np.int32)])
+    return T[rng.permutation(len(T))]
+
+
+def test_non_manifold_and_shuffled(pl, orc):
+    rng = np.random.default_rng(11)
+    T = _messy_mesh(orc, rng)
+    say("user halfedges messy", len(T))
+    got = gpu_he(pl, T)
+    want = oracle.user_halfedges(T)
+    assert np.array_equal(got, want), np.count_nonzero(got != want)
+    assert (want == -1).sum() > 1000
+
+
+@pytest.mark.parametrize("seed,n,span", [(1, 5000, 40), (2, 100000, 300), (3, 3000, 6)])
+def test_random_soups(pl, seed, n, span):
+    rng = np.random.default_rng(seed)
+    T = rng.integers(-span // 4, span, size=(n, 3)).astype(np.int32)
+    say("user halfedges soup", n, span)
+    got = gpu_he(pl, T)
+    assert np.array_equal(got, oracle.user_halfedges(T))
+
+
+def test_ragged_counts(pl, orc):
+    p = synth.random_grid(20, 30, 9, nan_frac=0.2)
+    _, T = orc.mesh(p)
+    cap = len(T)
+    for n in (cap, cap - 1, 1, 0, cap + 5, -2):
+        say("user halfedges n", n, "cap", cap)
+        got = gpu_he(pl, T, n)
+        m = min(max(n, 0), cap)
+        assert np.array_equal(got[:3 * m], oracle.user_halfedges(T[:m]))
+        assert np.all(got[3 * m:3 * cap] == UNTOUCHED)
