@@ -233,6 +233,51 @@ def ga_bench(plans, stream, reps=200, level=4, stride=1):
             "cpu_oracle_sample": f"{len(sample)} normals of one frame, brute force over all cells"}
 
 
+def user_halfedges_bench(plans, stream, reps=100):
+    """Half-edges of a user mesh (Sec. 4.3) on each frame's T taken as a
+    user-provided triangle list: per-call time of the three launches (table
+    clear, insert, lookup), half-edges per second, and the oracle's rate
+    (sort and binary searches, one thread) on the same triangles."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2007_12065_amd as pl
+    sets = len(plans)
+    outs = [torch.empty(3 * p.T, dtype=torch.int32, device=p.device) for p in plans]
+    cap = plans[0].T
+    ws_n = pl._lib.pl_user_halfedges_workspace(cap)
+    ws = torch.empty(ws_n, dtype=torch.uint8, device=plans[0].device)
+    s = pl._stream(plans[0].device)
+
+    def call(i):
+        p = plans[i % sets]
+        pl._check(pl._lib.pl_user_halfedges(pl._ptr(p.triangles), pl._ptr(p.n_tri), p.T,
+                                            pl._ptr(outs[i % sets]), pl._ptr(ws), ws_n, s),
+                  "pl_user_halfedges")
+    for i in range(sets):
+        call(i)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for i in range(reps):
+        call(i)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    n_tri = float(np.mean([int(p.n_tri.item()) for p in plans]))
+    n0 = int(plans[0].n_tri.item())
+    same = bool(torch.equal(outs[0][:3 * n0], plans[0].halfedges[:3 * n0]))
+    T = plans[0].triangles[:n0].cpu().numpy()
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.user_halfedges(T)
+    cpu_s = time.perf_counter() - t0
+    return {"kernels": ["k_he_clear", "k_he_insert", "k_he_lookup"], "call_us": round(us, 2),
+            "halfedges_per_s": round(3 * n_tri / (us * 1e-6), 1), "table_bytes": int(ws_n),
+            "equals_alg2_he": same,
+            "cpu_oracle_halfedges_per_s": round(3 * n0 / cpu_s, 1), "cpu_oracle_threads": 1}
+
+
 def angle_stats(got, ref):
     import numpy as np
     g = np.asarray(got, dtype=np.float64).reshape(-1, 3)
@@ -520,6 +565,8 @@ def main():
     out["gaussian_accumulator"] = ga_bench(plans, stream)
     # the paper integrates a sample of about 12% of the normals (sample_pct)
     out["gaussian_accumulator_sampled"] = ga_bench(plans, stream, stride=8)
+    print("[bench] user-mesh half-edges", file=sys.stderr, flush=True)
+    out["user_halfedges"] = user_halfedges_bench(plans, stream)
     if args.batched:
         print("[bench] batched 64-frame mix", file=sys.stderr, flush=True)
         out["batched"] = batched_bench(tune_cache=args.tune_cache)
