@@ -237,7 +237,7 @@ pl_status pl_group_assign(const float *pts, int32_t n_pts, const int32_t *triang
  * halfedges  int32 [3 cap] output; entries at or past 3 min(*n_tri, cap) are
  *            left untouched.
  * Workspace: pl_user_halfedges_workspace(cap) bytes (a table of at least
- * 6 cap slots of 12 bytes; 0 when cap = 0).  PL_ERR_ARG / PL_ERR_SHAPE /
+ * 6 cap slots of 16 bytes; 0 when cap = 0).  PL_ERR_ARG / PL_ERR_SHAPE /
  * PL_ERR_WORKSPACE / PL_ERR_ALIAS on invalid arguments (nothing enqueued).
  * Three launches on `stream`, no allocation, graph-capturable.
  */
