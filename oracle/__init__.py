@@ -25,7 +25,7 @@ _lib = None
 
 __all__ = ["build", "mesh", "halfedges", "laplacian", "tri_normals",
            "bilateral", "gather", "pipeline", "group_assign", "ga_icosahedron", "ga_integrate",
-           "user_halfedges"]
+           "user_halfedges", "vertex_update"]
 
 
 def build(force: bool = True) -> str:
@@ -71,6 +71,8 @@ def _load():
         lib.oracle_ga_integrate.restype = None
         lib.oracle_user_halfedges.argtypes = [vp, i64, vp]
         lib.oracle_user_halfedges.restype = None
+        lib.oracle_vertex_update.argtypes = [vp, i32, i32, vp, i32, vp, i32]
+        lib.oracle_vertex_update.restype = None
         _lib = lib
     return _lib
 
@@ -219,3 +221,17 @@ def user_halfedges(triangles):
     out = np.empty(max(3 * len(t), 1), dtype=np.int32)
     _load().oracle_user_halfedges(_ptr(t), len(t), _ptr(out))
     return out[:3 * len(t)].copy()
+
+
+def vertex_update(pts, normals, iterations: int, threads: int = 1):
+    """Vertex update from filtered normals (the second stage of bilateral
+    mesh denoising, Sun et al. 2007, restated; see oracle_vertex_update):
+    float64 [M, N, 3]."""
+    p = _f64(pts)
+    M, N = p.shape[:2]
+    n = _f64(normals)
+    if n.shape != (M - 1, N - 1, 2, 3):
+        raise ValueError("normals must be [M-1, N-1, 2, 3]")
+    out = np.empty_like(p)
+    _load().oracle_vertex_update(_ptr(p), M, N, _ptr(n), int(iterations), _ptr(out), threads)
+    return out

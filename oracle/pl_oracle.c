@@ -674,3 +674,65 @@ OR_EXPORT void oracle_user_halfedges(const int32_t *tris, int64_t n_tri, int32_t
     }
     free(r);
 }
+
+/*
+ * Vertex update after normal filtering: the second stage of the bilateral
+ * mesh denoising the paper cites for Eqs. (3)-(6) (Sun et al., 2007), which
+ * Polylidar3D itself skips (Sec. 5.2).  The paper does not print it; this is
+ * the published update restated: each sweep moves every vertex x_i by the
+ * mean, over the triangles f incident to it, of the correction that puts x_i
+ * on the plane through f's centroid c_f with f's filtered normal n_f:
+ *     x_i <- x_i + (1 / |F_i|) sum_{f in F_i} n_f (n_f . (c_f - x_i)).
+ * Reading: F_i are the triangles of T_FC that contain vertex i, whose three
+ * vertices are valid and whose filtered normal has no NaN; centroids are
+ * recomputed from the current vertices every sweep and every vertex is
+ * updated from the previous sweep's positions (Jacobi); a vertex with no
+ * such triangle, and an invalid (NaN) point, is copied unchanged.
+ * Parity unpinned against the paper itself (it gives no formula): the tests
+ * pin this restatement by closed forms and invariants.
+ */
+OR_EXPORT void oracle_vertex_update(const double *pts, int M, int N, const double *normals,
+                                    int iterations, double *out, int nthreads)
+{
+    const size_t P = (size_t)M * N;
+    double *cur = (double *)malloc(sizeof(double) * 3 * P);
+    memcpy(cur, pts, sizeof(double) * 3 * P);
+    memcpy(out, pts, sizeof(double) * 3 * P);
+    for (int it = 0; it < iterations; ++it) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int r = 0; r < M; ++r) {
+            for (int c = 0; c < N; ++c) {
+                const int64_t i = (int64_t)r * N + c;
+                const double *x = cur + 3 * i;
+                double *o = out + 3 * i;
+                o[0] = x[0]; o[1] = x[1]; o[2] = x[2];
+                if (!point_valid(x)) continue;
+                double acc[3] = {0.0, 0.0, 0.0};
+                int count = 0;
+                for (int u = r - 1; u <= r; ++u)
+                    for (int v = c - 1; v <= c; ++v) {
+                        if (u < 0 || v < 0 || u >= M - 1 || v >= N - 1) continue;
+                        for (int k = 0; k < 2; ++k) {
+                            int64_t idx[3];
+                            tri_vertices(u, v, k, N, idx);
+                            if (idx[0] != i && idx[1] != i && idx[2] != i) continue;
+                            const double *a = cur + 3 * idx[0], *b = cur + 3 * idx[1],
+                                         *d = cur + 3 * idx[2];
+                            const double *n = normals + 3 * (2LL * ((int64_t)u * (N - 1) + v) + k);
+                            if (!point_valid(a) || !point_valid(b) || !point_valid(d) || !vec_ok(n))
+                                continue;
+                            double proj = 0.0;
+                            for (int q = 0; q < 3; ++q)
+                                proj += n[q] * ((a[q] + b[q] + d[q]) / 3.0 - x[q]);
+                            for (int q = 0; q < 3; ++q) acc[q] += n[q] * proj;
+                            ++count;
+                        }
+                    }
+                if (count)
+                    for (int q = 0; q < 3; ++q) o[q] = x[q] + acc[q] / count;
+            }
+        }
+        memcpy(cur, out, sizeof(double) * 3 * P);
+    }
+    free(cur);
+}
