@@ -278,6 +278,40 @@ def user_halfedges_bench(plans, stream, reps=100):
             "cpu_oracle_halfedges_per_s": round(3 * n0 / cpu_s, 1), "cpu_oracle_threads": 1}
 
 
+def vertex_update_bench(plans, stream, reps=100, iterations=1):
+    """Vertex update from the filtered normals (one sweep per call) on each
+    frame: per-launch time of k_vertex_update, its algorithmic bytes (points
+    read and written once, the T_FC normals read once) and HBM fraction."""
+    import numpy as np
+    import torch
+
+    import paper_2007_12065_amd as pl
+    sets = len(plans)
+    outs = [torch.empty_like(p.points) for p in plans]
+    s = pl._stream(plans[0].device)
+    M, N = plans[0].M, plans[0].N
+
+    def call(i):
+        p = plans[i % sets]
+        pl._check(pl._lib.pl_vertex_update(pl._ptr(p.points), pl._ptr(outs[i % sets]), M, N,
+                                           pl._ptr(p.filtered), p.ndt, iterations, None, 0, s),
+                  "pl_vertex_update")
+    for i in range(sets):
+        call(i)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for i in range(reps):
+        call(i)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    nbytes = 24 * M * N + 12 * 2 * (M - 1) * (N - 1)
+    return {"kernel": "k_vertex_update", "sweeps": iterations, "launch_us": round(us, 2),
+            "points_per_s": round(M * N / (us * 1e-6), 1), "bytes_per_launch": int(nbytes),
+            "achieved_gbs": round(nbytes / (us * 1e-6) / 1e9, 1),
+            "hbm_frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def angle_stats(got, ref):
     import numpy as np
     g = np.asarray(got, dtype=np.float64).reshape(-1, 3)
@@ -567,6 +601,8 @@ def main():
     out["gaussian_accumulator_sampled"] = ga_bench(plans, stream, stride=8)
     print("[bench] user-mesh half-edges", file=sys.stderr, flush=True)
     out["user_halfedges"] = user_halfedges_bench(plans, stream)
+    print("[bench] vertex update", file=sys.stderr, flush=True)
+    out["vertex_update"] = vertex_update_bench(plans, stream)
     if args.batched:
         print("[bench] batched 64-frame mix", file=sys.stderr, flush=True)
         out["batched"] = batched_bench(tune_cache=args.tune_cache)

@@ -217,6 +217,28 @@ pl_status pl_group_assign(const float *pts, int32_t n_pts, const int32_t *triang
                           float ang_min, uint8_t *groups, hipStream_t stream);
 
 /*
+ * Vertex update from filtered normals: the second stage of the bilateral
+ * mesh denoising the paper cites with Eqs. (3)-(6) (Sun et al., 2007); the
+ * paper itself skips it (Sec. 5.2) and prints no formula.  `iterations`
+ * Jacobi sweeps of
+ *     x_i <- x_i + (1 / |F_i|) sum_{f in F_i} n_f (n_f . (c_f - x_i)),
+ * F_i the triangles of T_FC containing vertex i whose three vertices are
+ * valid and whose normal n_f (from `normals`, fixed) has no NaN, c_f their
+ * centroids from the current vertices.  An invalid point, or a vertex with
+ * no such triangle, keeps its value (bitwise).
+ *
+ * pts_in/pts_out  [M][N][3] float32; must not overlap.
+ * normals         T_FC layout of type ndt (e.g. pl_bilateral's output).
+ * iterations      >= 0; 0 copies pts_in to pts_out.
+ * Workspace: pl_vertex_update_workspace(M, N, iterations) bytes (one point
+ * buffer when iterations > 1).
+ */
+size_t pl_vertex_update_workspace(int32_t M, int32_t N, int32_t iterations);
+pl_status pl_vertex_update(const float *pts_in, float *pts_out, int32_t M, int32_t N,
+                           const void *normals, pl_dtype ndt, int32_t iterations, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/*
  * Half-edges of a user-provided mesh, Sec. 4.3: the twin of every half-edge
  * of T found through a hash table keyed by ordered point pairs.
  *

@@ -106,6 +106,10 @@ _lib.pl_user_halfedges_workspace.argtypes = [_i32]
 _lib.pl_user_halfedges_workspace.restype = _sz
 _lib.pl_user_halfedges.argtypes = [_vp, _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.pl_user_halfedges.restype = _i32
+_lib.pl_vertex_update_workspace.argtypes = [_i32, _i32, _i32]
+_lib.pl_vertex_update_workspace.restype = _sz
+_lib.pl_vertex_update.argtypes = [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _sz, _vp]
+_lib.pl_vertex_update.restype = _i32
 
 PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL, PL_STAGE_BATCH_LAPLACIAN, PL_STAGE_BATCH_BILATERAL = 0, 1, 2, 3
 
@@ -117,7 +121,7 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_batch_destroy", "pl_smooth_batch", "pl_group_assign", "pl_ga_workspace",
            "pl_ga_workspace_cells", "pl_ga_create", "pl_ga_create_cells", "pl_ga_cell_count",
            "pl_ga_cells", "pl_ga_integrate", "pl_ga_destroy", "pl_user_halfedges_workspace",
-           "pl_user_halfedges"]
+           "pl_user_halfedges", "pl_vertex_update_workspace", "pl_vertex_update"]
 
 
 class PLError(RuntimeError):
@@ -309,6 +313,27 @@ def pl_group_assign(points: torch.Tensor, triangles: torch.Tensor, normals_T: to
                                 _ptr(normals_T), ndt, _ptr(n_tri), cap, _ptr(dominant), l,
                                 l_max, ang_min, _ptr(out), _stream(dev)), "pl_group_assign")
     return out[:cap]
+
+
+def pl_vertex_update(pts: torch.Tensor, normals: torch.Tensor, iterations: int,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """Vertex update from filtered normals (the cited second stage of
+    bilateral denoising): [M, N, 3] float32 points moved toward the planes of
+    their triangles; normals in T_FC layout [M-1, N-1, 2, 3] (float32 or
+    float16)."""
+    _dev_tensor(pts, torch.float32, "pts")
+    ndt = _ndt(normals.dtype)
+    _dev_tensor(normals, _tdtype(ndt), "normals")
+    M, N = int(pts.shape[0]), int(pts.shape[1])
+    if tuple(normals.shape) != (M - 1, N - 1, 2, 3):
+        raise ValueError("normals must be [M-1, N-1, 2, 3]")
+    out = torch.empty_like(pts) if out is None else out
+    _dev_tensor(out, torch.float32, "out")
+    ws_n = _lib.pl_vertex_update_workspace(M, N, iterations)
+    ws = _ws(ws_n, pts.device)
+    _check(_lib.pl_vertex_update(_ptr(pts), _ptr(out), M, N, _ptr(normals), ndt, int(iterations),
+                                 _ptr(ws), ws_n, _stream(pts.device)), "pl_vertex_update")
+    return out
 
 
 def pl_user_halfedges(triangles: torch.Tensor, n_tri: torch.Tensor | None = None,

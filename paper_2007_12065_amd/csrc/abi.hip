@@ -3,6 +3,7 @@
 #include "common.h"
 #include "ga.h"
 #include "he.h"
+#include "vu.h"
 #include "tuning.h"
 
 #include <algorithm>
@@ -109,7 +110,7 @@ static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
 
 extern "C" {
 
-__attribute__((visibility("default"))) int32_t pl_version(void) { return 104; }
+__attribute__((visibility("default"))) int32_t pl_version(void) { return 105; }
 
 __attribute__((visibility("default"))) const char *pl_last_error(void) { return g_err; }
 
@@ -704,6 +705,39 @@ __attribute__((visibility("default"))) pl_status pl_user_halfedges(
         return PL_ERR_ALIAS;
     }
     return launch_user_halfedges(triangles, n_tri, cap, halfedges, ws, stream);
+}
+
+__attribute__((visibility("default"))) size_t pl_vertex_update_workspace(int32_t M, int32_t N,
+                                                                         int32_t iterations) {
+    if (M < 2 || N < 2 || iterations < 0) return 0;
+    return vertex_update_workspace(M, N, iterations);
+}
+
+__attribute__((visibility("default"))) pl_status pl_vertex_update(
+    const float *pts_in, float *pts_out, int32_t M, int32_t N, const void *normals, pl_dtype ndt,
+    int32_t iterations, void *ws, size_t ws_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    PL_TRY(check_shape(M, N));
+    if (ndt != PL_F32 && ndt != PL_F16) {
+        set_error("unknown normal dtype %d", (int)ndt);
+        return PL_ERR_ARG;
+    }
+    if (iterations < 0) {
+        set_error("iterations %d must not be negative", iterations);
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ptrs({{pts_in, "pts_in"}, {pts_out, "pts_out"}, {normals, "normals"}}));
+    const size_t need = vertex_update_workspace(M, N, iterations);
+    PL_TRY(check_ws(ws, ws_bytes, need));
+    const size_t P = (size_t)M * N, T = 2 * (size_t)(M - 1) * (N - 1);
+    const Range in{pts_in, 12 * P}, out{pts_out, 12 * P}, nr{normals, T * 3 * (ndt == PL_F32 ? 4 : 2)},
+        wr{ws, need};
+    if (overlap(in, out) || overlap(out, nr) || overlap(wr, in) || overlap(wr, out) ||
+        overlap(wr, nr)) {
+        set_error("pts_out and the workspace must not overlap the inputs or each other");
+        return PL_ERR_ALIAS;
+    }
+    return launch_vertex_update(pts_in, pts_out, M, N, normals, ndt, iterations, ws, stream);
 }
 
 __attribute__((visibility("default"))) pl_status pl_smooth_batch(const pl_frame *frames, int32_t n,

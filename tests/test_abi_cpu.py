@@ -32,7 +32,7 @@ def test_header_symbols_exported(pl):
 
 
 def test_version(pl):
-    assert pl.pl_version() == 104
+    assert pl.pl_version() == 105
 
 
 def test_workspace_sizes(pl):
