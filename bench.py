@@ -138,9 +138,34 @@ def cpu_baseline(frames_np, k, seconds, threads=None):
                       f"{threads} OpenMP threads), {el:.1f} s"}
 
 
+def graph_us(calls, replays=20):
+    """Average device time of one call: the calls (one per frame set) are
+    captured into a HIP graph on a side stream, and the graph is replayed
+    `replays` times between two events, so host issue cost does not enter.
+    Every call writes preallocated buffers only."""
+    import torch
+    for c in calls:
+        c()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for c in calls:
+            c()
+    g.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(replays):
+        g.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) * 1e3 / (replays * len(calls))
+
+
 def groups_bench(plans, k, stream, s, reps=300):
     """Group assignment (Alg. 4) over the frame sets after the timed path:
-    per-launch time of k_group_assign on float32 normals with each frame's
+    per-launch device time of k_group_assign (graph replays) on float32 normals with each frame's
     three scene planes as dominant normals, its roofline (HBM bound: T, the
     normals and the labels streamed once, every point read once), and the
     oracle's time for the same labels on one frame."""
@@ -151,15 +176,7 @@ def groups_bench(plans, k, stream, s, reps=300):
     from synth import scene_planes
     sets = len(plans)
     doms = [torch.from_numpy(scene_planes("rgbd", 1000 + i)).to(plans[0].device) for i in range(sets)]
-    for i in range(sets):
-        plans[i].run_groups(doms[i], k.l_max, k.ang_min, s)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record(stream)
-    for i in range(reps):
-        plans[i % sets].run_groups(doms[i % sets], k.l_max, k.ang_min, s)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    us = graph_us([lambda i=i: plans[i].run_groups(doms[i], k.l_max, k.ang_min) for i in range(sets)])
     n_tri = float(np.mean([int(p.n_tri.item()) for p in plans]))
     P = plans[0].M * plans[0].N
     nbytes = 12 * n_tri + 12 * n_tri + n_tri + 12 * P
@@ -202,15 +219,8 @@ def ga_bench(plans, stream, reps=200, level=4, stride=1):
     sets = len(plans)
     ga = pl.GaussianAccumulator(level, device=plans[0].device)
     counts = torch.zeros(ga.n_cells, dtype=torch.uint32, device=plans[0].device)
-    for i in range(sets):
-        ga.integrate(plans[i].normals_T, n=plans[i].n_tri, stride=stride, counts=counts)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record(stream)
-    for i in range(reps):
-        ga.integrate(plans[i % sets].normals_T, n=plans[i % sets].n_tri, stride=stride, counts=counts)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    us = graph_us([lambda i=i: ga.integrate(plans[i].normals_T, n=plans[i].n_tri, stride=stride,
+                                            counts=counts) for i in range(sets)])
     n_tri = float(np.mean([int(p.n_tri.item()) for p in plans]))
     rows = n_tri / stride
     nbytes = 12 * rows
@@ -235,7 +245,7 @@ def ga_bench(plans, stream, reps=200, level=4, stride=1):
 
 def user_halfedges_bench(plans, stream, reps=100):
     """Half-edges of a user mesh (Sec. 4.3) on each frame's T taken as a
-    user-provided triangle list: per-call time of the three launches (table
+    user-provided triangle list: per-call device time (graph replays) of the three launches (table
     clear, insert, lookup), half-edges per second, and the oracle's rate
     (sort and binary searches, one thread) on the same triangles."""
     import numpy as np
@@ -248,22 +258,12 @@ def user_halfedges_bench(plans, stream, reps=100):
     cap = plans[0].T
     ws_n = pl._lib.pl_user_halfedges_workspace(cap)
     ws = torch.empty(ws_n, dtype=torch.uint8, device=plans[0].device)
-    s = pl._stream(plans[0].device)
-
     def call(i):
         p = plans[i % sets]
         pl._check(pl._lib.pl_user_halfedges(pl._ptr(p.triangles), pl._ptr(p.n_tri), p.T,
-                                            pl._ptr(outs[i % sets]), pl._ptr(ws), ws_n, s),
-                  "pl_user_halfedges")
-    for i in range(sets):
-        call(i)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record(stream)
-    for i in range(reps):
-        call(i)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+                                            pl._ptr(outs[i % sets]), pl._ptr(ws), ws_n,
+                                            pl._stream(p.device)), "pl_user_halfedges")
+    us = graph_us([lambda i=i: call(i) for i in range(sets)], replays=5)
     n_tri = float(np.mean([int(p.n_tri.item()) for p in plans]))
     n0 = int(plans[0].n_tri.item())
     same = bool(torch.equal(outs[0][:3 * n0], plans[0].halfedges[:3 * n0]))
@@ -280,7 +280,7 @@ def user_halfedges_bench(plans, stream, reps=100):
 
 def vertex_update_bench(plans, stream, reps=100, iterations=1):
     """Vertex update from the filtered normals (one sweep per call) on each
-    frame: per-launch time of k_vertex_update, its algorithmic bytes (points
+    frame: per-launch device time (graph replays) of k_vertex_update, its algorithmic bytes (points
     read and written once, the T_FC normals read once) and HBM fraction."""
     import numpy as np
     import torch
@@ -288,23 +288,14 @@ def vertex_update_bench(plans, stream, reps=100, iterations=1):
     import paper_2007_12065_amd as pl
     sets = len(plans)
     outs = [torch.empty_like(p.points) for p in plans]
-    s = pl._stream(plans[0].device)
     M, N = plans[0].M, plans[0].N
 
     def call(i):
         p = plans[i % sets]
         pl._check(pl._lib.pl_vertex_update(pl._ptr(p.points), pl._ptr(outs[i % sets]), M, N,
-                                           pl._ptr(p.filtered), p.ndt, iterations, None, 0, s),
-                  "pl_vertex_update")
-    for i in range(sets):
-        call(i)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record(stream)
-    for i in range(reps):
-        call(i)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+                                           pl._ptr(p.filtered), p.ndt, iterations, None, 0,
+                                           pl._stream(p.device)), "pl_vertex_update")
+    us = graph_us([lambda i=i: call(i) for i in range(sets)])
     nbytes = 24 * M * N + 12 * 2 * (M - 1) * (N - 1)
     return {"kernel": "k_vertex_update", "sweeps": iterations, "launch_us": round(us, 2),
             "points_per_s": round(M * N / (us * 1e-6), 1), "bytes_per_launch": int(nbytes),

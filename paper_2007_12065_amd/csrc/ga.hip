@@ -14,9 +14,10 @@
 // few candidates (stored with their cell normals, so a search is two
 // dependent table loads), and the chosen cell is exactly the brute-force
 // one.
-// Normals whose length is outside [0.5, 2] (zero, NaN, infinite or badly
-// scaled) are searched over all cells, which keeps the result the
-// brute-force one for every input.
+// A normal with a NaN or infinite coordinate lands in no cell (so does the
+// brute force: every distance is NaN or infinite); finite normals whose
+// length is outside [0.5, 2] are searched over all cells, which keeps the
+// result the brute-force one for every input.
 //
 // Counts accumulate in an LDS histogram per workgroup (every cell's count,
 // 4 bytes each).  A scene's normals crowd into a few cells, and atomic adds
@@ -30,6 +31,7 @@
 #include "tuning.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -124,15 +126,18 @@ __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
             z[q] = ld_f(normals + 3 * t + 2);
         }
         int lo[kGaPer], len[kGaPer], arg[kGaPer];
-        bool all[kGaPer];
+        bool all[kGaPer], none[kGaPer];
         int longest = 0;
 #pragma unroll
         for (int q = 0; q < kGaPer; ++q) {
             const float s2 = fmaf(x[q], x[q], fmaf(y[q], y[q], z[q] * z[q]));
-            all[q] = !(s2 >= 0.25f && s2 <= 4.0f);
-            const int b = all[q] ? 0 : ga_bin(x[q], y[q], z[q], G);
+            // a NaN or infinite coordinate lands in no cell (every distance is
+            // NaN or infinite); only finite normals of odd length search all
+            none[q] = !(fabsf(x[q]) <= FLT_MAX && fabsf(y[q]) <= FLT_MAX && fabsf(z[q]) <= FLT_MAX);
+            all[q] = !none[q] && !(s2 >= 0.25f && s2 <= 4.0f);
+            const int b = (all[q] || none[q]) ? 0 : ga_bin(x[q], y[q], z[q], G);
             lo[q] = bin_start[b];
-            len[q] = all[q] ? 0 : bin_start[b + 1] - lo[q];
+            len[q] = (all[q] || none[q]) ? 0 : bin_start[b + 1] - lo[q];
             longest = max(longest, len[q]);
             arg[q] = -1;
         }
