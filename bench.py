@@ -8,6 +8,11 @@ and the gather onto T, all in float32.  Inputs are resident in HBM before the
 timed region; 16 frames with separate input and output buffers rotate so the
 working set (~1.1 GB) exceeds the 256 MB last-level cache.
 
+The timed steps run the path alone on the stream; a separate pass with HIP
+events between the calls gives the per-call breakdown and the dominant
+kernel's launch time (events cost the stream a few microseconds each, so
+that pass is slower than the timed one).
+
 Prints one JSON line (the contract fields plus the dominant kernel's
 roofline and the FP64 oracle's CPU throughput).
 """
@@ -499,19 +504,37 @@ def main():
     torch.cuda.synchronize(dev)
 
     K = args.steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+    # the timed steps: the whole path, nothing else on the stream
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     for i in range(K):
-        step(i, evs[i])
+        step(i)
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - t0
 
+    # the paper's rate: smoothing only (Laplacian, normals, bilateral with the
+    # gather onto T from the mesh of the steps above), again uninstrumented
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for i in range(K):
+        p, x = plans[i % sets], frames[i % sets]
+        p.run_laplacian(x, s)
+        p.run_normals(s)
+        p.run_bilateral(s)
+    torch.cuda.synchronize(dev)
+    smooth_elapsed = time.perf_counter() - t0
+
+    # a separate instrumented pass for the per-call breakdown and the roofline:
+    # an event between calls costs the stream about 4 us per boundary, so these
+    # durations are upper bounds and are not used for `value`
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+    torch.cuda.synchronize(dev)
+    for i in range(K):
+        step(i, evs[i])
+    torch.cuda.synchronize(dev)
+
     per_call = {c: np.array([evs[i][j].elapsed_time(evs[i][j + 1]) * 1e3 for i in range(K)])
                 for j, c in enumerate(calls)}
-    # the paper's rate: smoothing (Laplacian, normals, bilateral and gather)
-    # only, mesh creation timed and reported on its own
-    smooth_us = per_call["pl_laplacian"] + per_call["pl_tri_normals"] + per_call["pl_bilateral"]
     lat = np.array([evs[i][0].elapsed_time(evs[i][4]) * 1e3 for i in range(K)])
     n_tri = [int(p.n_tri.item()) for p in plans]
     T = 2 * (M - 1) * (N - 1)
@@ -573,10 +596,13 @@ def main():
                    "frame": [M, N], "triangles_per_frame": T, "valid_triangles_mean": float(np.mean(n_tri)),
                    "frame_sets": sets},
         "stage_us": {c: round(float(np.median(per_call[c])), 2) for c in calls},
-        "smoothing_triangles_per_s": round(T / (float(np.mean(smooth_us)) * 1e-6), 1),
+        "stage_note": "medians per call from a separate event-instrumented pass (each event "
+                      "boundary adds about 4 us to the stream); value, ms_per_step and the "
+                      "smoothing rate come from uninstrumented passes",
+        "smoothing_triangles_per_s": round(T / (smooth_elapsed / K), 1),
         "mesh_us": round(float(np.median(per_call["pl_mesh_opc"])), 2),
         "hbm_copy_ceiling_gbs": round(copy_gbs, 1),
-        "frame_latency_us": {"p50": round(float(np.median(lat)), 2),
+        "instrumented_frame_us": {"p50": round(float(np.median(lat)), 2),
                              "p99": round(float(np.percentile(lat, 99)), 2)},
         "hbm_effective_gbs": round(sum(specs[c]["bytes"] * specs[c]["launches"] for c in calls)
                                    / (elapsed / K) / 1e9, 1),
