@@ -47,10 +47,7 @@ namespace pl {
 namespace {
 
 constexpr int kGaBlock = 256;
-#ifndef PL_GA_PER
-#define PL_GA_PER 4
-#endif
-constexpr int kGaPer = PL_GA_PER;          // integrated rows per thread and pass
+constexpr int kGaPer = 4;                  // integrated rows per thread and pass (large inputs)
 #ifndef PL_GA_MAX_GRID
 #define PL_GA_MAX_GRID 1024
 #endif
@@ -97,11 +94,12 @@ __device__ __noinline__ int ga_nearest_all(float x, float y, float z,
     return arg;
 }
 
-// Each thread takes kGaPer consecutive integrated rows and runs their
-// searches side by side (loads of all rows, then of all bins, then the
-// candidates in lockstep), so several dependent load chains are in flight
-// per thread.
-template <typename NT>
+// Each thread takes PER consecutive integrated rows and runs their searches
+// side by side (loads of all rows, then of all bins, then the candidates in
+// lockstep), so several dependent load chains are in flight per thread.
+// Inputs too small to give every CU a workgroup at four rows per thread run
+// with one (a sampled frame's normals).
+template <typename NT, int PER>
 __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
     const NT *__restrict__ normals, const int32_t *__restrict__ n_dev, int cap, int stride,
     const float *__restrict__ cells, int n_cells, const int *__restrict__ bin_start,
@@ -110,26 +108,26 @@ __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
     extern __shared__ uint32_t hist[];
     const int n = min(max(*n_dev, 0), cap);
     const int rows = n == 0 ? 0 : (n - 1) / stride + 1;
-    const int span = (int)gridDim.x * kGaBlock * kGaPer;
-    const int first = (int)blockIdx.x * kGaBlock * kGaPer;
+    const int span = (int)gridDim.x * kGaBlock * PER;
+    const int first = (int)blockIdx.x * kGaBlock * PER;
     if (first >= rows) return;                       // the whole workgroup has no row
     for (int i = threadIdx.x; i < n_cells; i += kGaBlock) hist[i] = 0u;
     __syncthreads();
-    for (int base = first + (int)threadIdx.x * kGaPer; base < rows; base += span) {
-        float x[kGaPer], y[kGaPer], z[kGaPer];
+    for (int base = first + (int)threadIdx.x * PER; base < rows; base += span) {
+        float x[PER], y[PER], z[PER];
 #pragma unroll
-        for (int q = 0; q < kGaPer; ++q) {
+        for (int q = 0; q < PER; ++q) {
             const int j = min(base + q, rows - 1);   // rows past the end repeat the last one
             const size_t t = (size_t)j * (size_t)stride;
             x[q] = ld_f(normals + 3 * t);
             y[q] = ld_f(normals + 3 * t + 1);
             z[q] = ld_f(normals + 3 * t + 2);
         }
-        int lo[kGaPer], len[kGaPer], arg[kGaPer];
-        bool all[kGaPer], none[kGaPer];
+        int lo[PER], len[PER], arg[PER];
+        bool all[PER], none[PER];
         int longest = 0;
 #pragma unroll
-        for (int q = 0; q < kGaPer; ++q) {
+        for (int q = 0; q < PER; ++q) {
             const float s2 = fmaf(x[q], x[q], fmaf(y[q], y[q], z[q] * z[q]));
             // a NaN or infinite coordinate lands in no cell (every distance is
             // NaN or infinite); only finite normals of odd length search all
@@ -141,12 +139,12 @@ __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
             longest = max(longest, len[q]);
             arg[q] = -1;
         }
-        float best[kGaPer];
+        float best[PER];
 #pragma unroll
-        for (int q = 0; q < kGaPer; ++q) best[q] = __builtin_inff();
+        for (int q = 0; q < PER; ++q) best[q] = __builtin_inff();
         for (int k = 0; k < longest; ++k) {
 #pragma unroll
-            for (int q = 0; q < kGaPer; ++q) {
+            for (int q = 0; q < PER; ++q) {
                 if (k < len[q]) {
                     // a candidate is its cell's normal with the cell index in w
                     const float4 e = bin_cells[lo[q] + k];
@@ -160,7 +158,7 @@ __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
             }
         }
 #pragma unroll
-        for (int q = 0; q < kGaPer; ++q) {
+        for (int q = 0; q < PER; ++q) {
             if (base + q >= rows) break;
             const int c = all[q] ? ga_nearest_all(x[q], y[q], z[q], cells, n_cells) : arg[q];
             if (cell_out) cell_out[base + q] = c;
@@ -438,8 +436,12 @@ pl_status ga_upload(pl_ga_s *g, hipStream_t s) {
         return st;
     if (pl_status st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")) return st;
     g->lds = 4 * (size_t)T.n_cells;
-    if (pl_status st = allow_lds((const void *)k_ga_integrate<float>, g->lds)) return st;
-    return allow_lds((const void *)k_ga_integrate<__half>, g->lds);
+    for (const void *k : {(const void *)k_ga_integrate<float, kGaPer>,
+                          (const void *)k_ga_integrate<__half, kGaPer>,
+                          (const void *)k_ga_integrate<float, 1>,
+                          (const void *)k_ga_integrate<__half, 1>})
+        if (pl_status st = allow_lds(k, g->lds)) return st;
+    return PL_OK;
 }
 
 }  // namespace
@@ -482,20 +484,32 @@ pl_status ga_integrate(const pl_ga_s *g, const void *normals, pl_dtype ndt, cons
     if (cap == 0) return PL_OK;
     const GaTables &T = *g->tab;
     const long rows = ((long)cap + stride - 1) / stride;
-    const long per_wg = (long)kGaBlock * kGaPer;
-    const int grid = (int)std::min<long>(kGaMaxGrid, (rows + per_wg - 1) / per_wg);
     const float *cells = reinterpret_cast<const float *>(g->ws + T.off_cells);
     const int *start = reinterpret_cast<const int *>(g->ws + T.off_start);
     const float4 *list = reinterpret_cast<const float4 *>(g->ws + T.off_list);
     uint32_t *reps = reinterpret_cast<uint32_t *>(g->ws + T.off_replicas);
-    if (ndt == PL_F32)
-        k_ga_integrate<float><<<grid, kGaBlock, g->lds, s>>>(
-            static_cast<const float *>(normals), n_dev, cap, stride, cells, T.n_cells, start, list,
-            T.G, reps, cell_out);
-    else
-        k_ga_integrate<__half><<<grid, kGaBlock, g->lds, s>>>(
-            static_cast<const __half *>(normals), n_dev, cap, stride, cells, T.n_cells, start,
-            list, T.G, reps, cell_out);
+    // four rows per thread once that still gives every CU a workgroup
+    const bool wide = rows >= (long)kGaBlock * kGaPer * 256;
+    const long per_wg = (long)kGaBlock * (wide ? kGaPer : 1);
+    const int grid = (int)std::min<long>(kGaMaxGrid, (rows + per_wg - 1) / per_wg);
+    const size_t lds = g->lds;
+    if (ndt == PL_F32) {
+        const float *nv = static_cast<const float *>(normals);
+        if (wide)
+            k_ga_integrate<float, kGaPer><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
+                                                                   T.n_cells, start, list, T.G, reps, cell_out);
+        else
+            k_ga_integrate<float, 1><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
+                                                              T.n_cells, start, list, T.G, reps, cell_out);
+    } else {
+        const __half *nv = static_cast<const __half *>(normals);
+        if (wide)
+            k_ga_integrate<__half, kGaPer><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
+                                                                    T.n_cells, start, list, T.G, reps, cell_out);
+        else
+            k_ga_integrate<__half, 1><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
+                                                               T.n_cells, start, list, T.G, reps, cell_out);
+    }
     if (pl_status st = hip_check(hipGetLastError(), "k_ga_integrate")) return st;
     k_ga_fold<<<(T.n_cells + kGaBlock - 1) / kGaBlock, kGaBlock, 0, s>>>(reps, T.n_cells, counts);
     return hip_check(hipGetLastError(), "k_ga_fold");

@@ -178,3 +178,23 @@ def test_library_level_matches_oracle_counts(pl):
     assert clear.mean() > 0.99
     assert np.array_equal(got[clear], want[clear])
     ga.close()
+
+
+def test_integrate_large_input(pl):
+    """An input large enough for four rows per thread (the launch shape of a
+    full frame's normals), level 3, float32 and float16: identical to the
+    oracle."""
+    import torch
+    _, _, C = oracle.ga_icosahedron(3)
+    rng = np.random.default_rng(123)
+    N = np.concatenate([hard_normals(C, rng, n_random=300000)])
+    ga = pl.GaussianAccumulator(cells=C)
+    for nd in (np.float32, np.float16):
+        x = N.astype(nd)
+        say("ga large input", len(x), nd.__name__)
+        counts, cells = ga.integrate(to_dev(x), cell_out=True)
+        torch.cuda.synchronize()
+        want_idx, want_counts = oracle.ga_integrate(C, x.astype(np.float32))
+        assert np.array_equal(cells.cpu().numpy(), want_idx)
+        assert np.array_equal(counts.cpu().numpy(), want_counts)
+    ga.close()
