@@ -8,7 +8,11 @@ continuous batching on one GPU.
   possible, and rejects requests that could never fit.
 * Execution.  One batch plan (pl_batch_*) spans all slots; each step writes a
   device activity mask selecting the slots admitted since the previous step
-  and replays a HIP graph of the whole pipeline captured with that mask.
+  and replays a HIP graph of the whole pipeline captured with that mask.  A
+  step of a single frame (a lightly loaded stream) instead runs the four
+  single-frame calls on that slot's buffers: fewer, smaller launches, and
+  the same output bits (the batched and single-frame paths agree bit for
+  bit).
 * Continuous batching.  The next step is enqueued as soon as requests are
   waiting, while earlier steps may still be on the GPU: frames that arrive
   during a step join the next one instead of waiting for the queue to drain.
@@ -256,6 +260,53 @@ class GpuBatchExecutor:
         self.stream = torch.cuda.current_stream(device)
         self.copy_stream = torch.cuda.Stream(device)      # default priority
         self.ref = None
+        self.single = {}                      # per class: scratch of the single-frame calls
+
+    @staticmethod
+    def single_bytes(pl, c, normal_bytes: int) -> int:
+        """Device bytes of one class's scratch for single-frame steps: the raw
+        normals and the three calls' workspaces."""
+        T = 2 * (c.M - 1) * (c.N - 1)
+        ndt = pl.PL_F32 if normal_bytes == 4 else pl.PL_F16
+        return (3 * T * normal_bytes + pl._lib.pl_mesh_opc_workspace(c.M, c.N)
+                + pl._lib.pl_laplacian_workspace(c.M, c.N, c.iters_lap)
+                + pl._lib.pl_bilateral_workspace(c.M, c.N, ndt, c.iters_bil) + 4 * 256)
+
+    def _single_scratch(self, cls: str):
+        torch, pl = self.torch, self.pl
+        if cls not in self.single:
+            c = self.classes[cls]
+            ndt = pl._ndt(self.ndtype)
+            e = lambda n: torch.empty(max(n, 1), dtype=torch.uint8, device=self.dev)
+            sizes = (pl._lib.pl_mesh_opc_workspace(c.M, c.N),
+                     pl._lib.pl_laplacian_workspace(c.M, c.N, c.iters_lap),
+                     pl._lib.pl_bilateral_workspace(c.M, c.N, ndt, c.iters_bil))
+            raw = torch.empty((c.M - 1, c.N - 1, 2, 3), dtype=self.ndtype, device=self.dev)
+            self.single[cls] = (raw, [e(n) for n in sizes], sizes, ndt)
+        return self.single[cls]
+
+    def run_single(self, index: int) -> None:
+        """The four single-frame calls for slot `index`, into its outputs."""
+        pl = self.pl
+        c = self.classes[self.slot_cls[index]]
+        raw, ws, sizes, ndt = self._single_scratch(self.slot_cls[index])
+        o = self.batch.outputs[index]
+        x = self.inputs[index]
+        st = pl._stream(self.dev)
+        P = lambda t: pl._ptr(t)
+        T = 2 * (c.M - 1) * (c.N - 1)
+        pl._check(pl._lib.pl_mesh_opc(P(x), c.M, c.N, P(o["tri_valid"]), P(o["tri_map"]),
+                                      P(o["triangles"]), P(o["halfedges"]), T, P(o["n_tri"]),
+                                      P(ws[0]) if sizes[0] else None, sizes[0], st), "pl_mesh_opc")
+        pl._check(pl._lib.pl_laplacian(P(x), P(o["points"]), c.M, c.N, c.kernel_lap, c.lam,
+                                       c.iters_lap, P(ws[1]) if sizes[1] else None, sizes[1], st),
+                  "pl_laplacian")
+        pl._check(pl._lib.pl_tri_normals(P(o["points"]), c.M, c.N, P(raw), ndt, P(o["centroids"]), st),
+                  "pl_tri_normals")
+        pl._check(pl._lib.pl_bilateral(P(raw), P(o["centroids"]), ndt, c.M, c.N, c.kernel_bil,
+                                       c.sigma_length, c.sigma_angle, c.iters_bil, P(o["normals"]),
+                                       P(o["tri_map"]), P(o["normals_T"]),
+                                       P(ws[2]) if sizes[2] else None, sizes[2], st), "pl_bilateral")
 
     def alloc(self, cls: str) -> None:
         c = self.classes[cls]
@@ -274,6 +325,8 @@ class GpuBatchExecutor:
                               sigma_angle=c.sigma_angle, iters_bil=c.iters_bil))
         self.batch = self.pl.Batch(specs, self.ndtype)
         self.n = len(specs)
+        for cls in set(self.slot_cls):        # scratch for one-frame steps, allocated up front
+            self._single_scratch(cls)
         self.mask_dev = torch.zeros(self.n, dtype=torch.uint8, device=self.dev)
         # the pinned mask of a step is reused max_inflight + 1 steps later,
         # when that step has been retired
@@ -318,8 +371,11 @@ class GpuBatchExecutor:
             copied = self.torch.cuda.Event()
             copied.record(self.copy_stream)
         self.stream.wait_event(copied)
-        self.mask_dev.copy_(buf, non_blocking=True)
-        self.batch.replay(n_active=len(members))
+        if len(members) == 1:
+            self.run_single(members[0][0].index)
+        else:
+            self.mask_dev.copy_(buf, non_blocking=True)
+            self.batch.replay(n_active=len(members))
         ev = self.torch.cuda.Event(enable_timing=True)
         ev.record(self.stream)
         return ev
@@ -348,7 +404,9 @@ class Server:
                              pl.pl_tune_get(pl.PL_STAGE_BILATERAL, c.kernel_bil)[2])
                for k, c in classes.items()}
         self.exe = GpuBatchExecutor(classes, host_frames, ndtype, max_inflight, dev)
-        self.pool = SlotPool(budget_bytes, per, allocate=self.exe.alloc)
+        # the single-frame steps' scratch (one set per class) comes out of the budget
+        reserve = sum(GpuBatchExecutor.single_bytes(pl, c, nb) for c in classes.values())
+        self.pool = SlotPool(max(budget_bytes - reserve, 0), per, allocate=self.exe.alloc)
         self.max_inflight = max_inflight
 
     def presize(self, counts: dict, freeze: bool = False) -> None:
