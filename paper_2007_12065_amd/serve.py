@@ -327,6 +327,15 @@ class GpuBatchExecutor:
         self.n = len(specs)
         for cls in set(self.slot_cls):        # scratch for one-frame steps, allocated up front
             self._single_scratch(cls)
+        # each slot's single-frame calls as a graph of their own (one launch
+        # from the host per one-frame step)
+        self.single_graphs = []
+        side = torch.cuda.Stream(self.dev)
+        for i in range(self.n):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                self.run_single(i)
+            self.single_graphs.append(g)
         self.mask_dev = torch.zeros(self.n, dtype=torch.uint8, device=self.dev)
         # the pinned mask of a step is reused max_inflight + 1 steps later,
         # when that step has been retired
@@ -357,23 +366,27 @@ class GpuBatchExecutor:
         # a slot is refilled only after the step that last used it retired,
         # so these copies may overlap the steps still on the GPU; device-side
         # sources go in one fused copy, host sources one DMA each
-        dsts, srcs = [], []
-        with self.torch.cuda.stream(self.copy_stream):
-            for s, r in members:
-                src = self.host[r.cls][r.frame]
-                if src.is_cuda:
-                    dsts.append(self.inputs[s.index])
-                    srcs.append(src)
-                else:
-                    self.inputs[s.index].copy_(src, non_blocking=True)
-            if dsts:
-                self.torch._foreach_copy_(dsts, srcs, non_blocking=True)
-            copied = self.torch.cuda.Event()
-            copied.record(self.copy_stream)
-        self.stream.wait_event(copied)
         if len(members) == 1:
-            self.run_single(members[0][0].index)
+            # a lone frame: its copy and its calls back to back on the compute
+            # stream (no cross-stream wait), as the plain path does
+            s, r = members[0]
+            self.inputs[s.index].copy_(self.host[r.cls][r.frame], non_blocking=True)
+            self.single_graphs[s.index].replay()
         else:
+            dsts, srcs = [], []
+            with self.torch.cuda.stream(self.copy_stream):
+                for s, r in members:
+                    src = self.host[r.cls][r.frame]
+                    if src.is_cuda:
+                        dsts.append(self.inputs[s.index])
+                        srcs.append(src)
+                    else:
+                        self.inputs[s.index].copy_(src, non_blocking=True)
+                if dsts:
+                    self.torch._foreach_copy_(dsts, srcs, non_blocking=True)
+                copied = self.torch.cuda.Event()
+                copied.record(self.copy_stream)
+            self.stream.wait_event(copied)
             self.mask_dev.copy_(buf, non_blocking=True)
             self.batch.replay(n_active=len(members))
         ev = self.torch.cuda.Event(enable_timing=True)
