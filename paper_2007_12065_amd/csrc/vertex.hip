@@ -55,9 +55,10 @@ template <typename NT>
 __global__ __launch_bounds__(kVuBlock) void k_vertex_update(const float *__restrict__ in,
                                                             float *__restrict__ out, int M, int N,
                                                             const NT *__restrict__ normals) {
-    const int c = (int)blockIdx.x * kVuBlock + (int)threadIdx.x;
-    const int r = (int)blockIdx.y;
-    if (c >= N) return;
+    // one thread per point, row-major over the frame (a 1-D grid: any M)
+    const long long idx = (long long)blockIdx.x * kVuBlock + threadIdx.x;
+    if (idx >= (long long)M * N) return;
+    const int r = (int)(idx / N), c = (int)(idx - (long long)r * N);
     const P3 x = ld_p(in, N, r, c);
     float *o = out + 3 * ((size_t)r * N + c);
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
@@ -111,7 +112,7 @@ pl_status launch_vertex_update(const float *in, float *out, int M, int N, const 
     const size_t bytes = 12 * (size_t)M * N;
     if (iterations == 0)
         return hip_check(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
-    const dim3 grid((N + kVuBlock - 1) / kVuBlock, M);
+    const unsigned grid = (unsigned)(((size_t)M * N + kVuBlock - 1) / kVuBlock);
     const float *src = in;
     for (int it = 0; it < iterations; ++it) {
         // the last sweep lands in `out`; earlier ones alternate with the workspace

@@ -197,6 +197,21 @@ def test_user_halfedges_host_side(pl):
     assert lib.pl_user_halfedges(A, B, 100, C, C + 256, ws, None) == -4   # workspace over output
 
 
+def test_vertex_update_argument_errors(pl):
+    lib = pl._lib
+    assert lib.pl_vertex_update_workspace(10, 10, 1) == 0
+    assert lib.pl_vertex_update_workspace(10, 10, 2) >= 12 * 100
+    assert lib.pl_vertex_update_workspace(1, 10, 2) == 0
+    ws = lib.pl_vertex_update_workspace(10, 10, 3)
+    assert lib.pl_vertex_update(A, B, 1, 10, C, 0, 1, None, 0, None) == -2
+    assert lib.pl_vertex_update(A, B, 10, 10, C, 5, 1, None, 0, None) == -1
+    assert lib.pl_vertex_update(A, B, 10, 10, C, 0, -1, None, 0, None) == -1
+    assert lib.pl_vertex_update(None, B, 10, 10, C, 0, 1, None, 0, None) == -1
+    assert lib.pl_vertex_update(A, A + 64, 10, 10, C, 0, 1, None, 0, None) == -4
+    assert lib.pl_vertex_update(A, B, 10, 10, C, 0, 3, None, 0, None) == -5
+    assert lib.pl_vertex_update(A, B, 10, 10, C, 0, 3, B + 16, ws, None) == -4
+
+
 def test_tuning_table_stages(pl):
     # four independent tables: single-frame and batched, Laplacian and bilateral
     saved = {(s, k): pl.pl_tune_get(s, k) for s in range(4) for k in (3, 5)}

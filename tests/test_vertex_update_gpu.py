@@ -46,7 +46,8 @@ def check(pl, pts, normals, iters):
     return got
 
 
-@pytest.mark.parametrize("M,N,seed", [(2, 2, 1), (3, 300, 2), (37, 520, 3), (64, 257, 4), (9, 1000, 5)])
+@pytest.mark.parametrize("M,N,seed", [(2, 2, 1), (3, 300, 2), (37, 520, 3), (64, 257, 4), (9, 1000, 5),
+                                      (70000, 3, 6)])
 def test_random_grids(pl, orc, M, N, seed):
     g = synth.random_grid(M, N, seed, nan_frac=0.1, noise=0.02)
     n, _ = orc.tri_normals(g)
