@@ -41,9 +41,12 @@ __device__ __forceinline__ void vu_add(P3 x, P3 a, P3 b, P3 d, const NT *__restr
     const float nx = ld_f(n), ny = ld_f(n + 1), nz = ld_f(n + 2);
     if (!(p_ok(a) && p_ok(b) && p_ok(d)) || is_nan_bits(nx) || is_nan_bits(ny) || is_nan_bits(nz))
         return;
-    const float cx = (a.x + b.x + d.x) / 3.0f - x.x;
-    const float cy = (a.y + b.y + d.y) / 3.0f - x.y;
-    const float cz = (a.z + b.z + d.z) / 3.0f - x.z;
+    // the centroid through a multiply by the rounded 1/3 (within an ulp of
+    // the quotient; an IEEE division would cost ten instructions a component)
+    constexpr float kThird = 1.0f / 3.0f;
+    const float cx = fmaf(a.x + b.x + d.x, kThird, -x.x);
+    const float cy = fmaf(a.y + b.y + d.y, kThird, -x.y);
+    const float cz = fmaf(a.z + b.z + d.z, kThird, -x.z);
     const float proj = fmaf(nx, cx, fmaf(ny, cy, nz * cz));
     sx = fmaf(nx, proj, sx);
     sy = fmaf(ny, proj, sy);
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(kVuBlock) void k_vertex_update(const float *__restr
             vu_add(x, pu, x, pr, nrm(r - 1, c, 1), sx, sy, sz, count);
     }
     if (count) {
-        const float inv = 1.0f / (float)count;
+        const float inv = __builtin_amdgcn_rcpf((float)count);   // count in 1..6
         o[0] = fmaf(sx, inv, x.x);
         o[1] = fmaf(sy, inv, x.y);
         o[2] = fmaf(sz, inv, x.z);
