@@ -68,9 +68,11 @@ __device__ __forceinline__ int ga_bin(float x, float y, float z, int G) {
     } else {
         f = z >= 0.0f ? 4 : 5; m = az; u = x; v = y;
     }
-    const float hg = 0.5f * (float)G;
-    const int iu = min(max((int)floorf(fmaf(u / m, hg, hg)), 0), G - 1);
-    const int iv = min(max((int)floorf(fmaf(v / m, hg, hg)), 0), G - 1);
+    // the hardware reciprocal (1 ulp) instead of two IEEE divisions: the bins
+    // are padded by far more than the rounding of the coordinates
+    const float hg = 0.5f * (float)G, im = __builtin_amdgcn_rcpf(m);
+    const int iu = min(max((int)floorf(fmaf(u * im, hg, hg)), 0), G - 1);
+    const int iv = min(max((int)floorf(fmaf(v * im, hg, hg)), 0), G - 1);
     return (f * G + iv) * G + iu;
 }
 
