@@ -198,3 +198,25 @@ def test_integrate_large_input(pl):
         assert np.array_equal(cells.cpu().numpy(), want_idx)
         assert np.array_equal(counts.cpu().numpy(), want_counts)
     ga.close()
+
+
+@pytest.mark.parametrize("n_cells,seed", [(700, 1), (37, 2), (5000, 3)])
+def test_arbitrary_cell_sets(pl, n_cells, seed):
+    """The candidate tables hold for any unit cell set, not only icosahedra:
+    random directions (uneven spacing), with near-duplicates and exact
+    duplicates, against the oracle's brute force."""
+    import torch
+    rng = np.random.default_rng(seed)
+    C = unit_rows(rng.normal(size=(n_cells, 3)))
+    C[-3] = C[0]                                           # an exact duplicate
+    C[-2] = unit_rows((C[1] + 1e-6 * rng.normal(size=3))[None])[0]   # a near-duplicate
+    C = C.astype(np.float32)
+    N = hard_normals(C, rng, n_random=30000)
+    ga = pl.GaussianAccumulator(cells=C)
+    say("ga arbitrary cells", n_cells)
+    counts, cells = ga.integrate(to_dev(N), cell_out=True)
+    torch.cuda.synchronize()
+    want_idx, want_counts = oracle.ga_integrate(C, N)
+    assert np.array_equal(cells.cpu().numpy(), want_idx)
+    assert np.array_equal(counts.cpu().numpy(), want_counts)
+    ga.close()
