@@ -138,7 +138,14 @@ def cpu_baseline(frames_np, k, seconds, threads=None):
         el = time.perf_counter() - t0
         if el >= seconds or done >= 1000:
             break
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": T * done / el, "unit": "triangles/s", "cores": threads, "kind": "oracle",
+            "host_cpus": cores, "cpu_model": model,
             "sample": f"{done} frames of the 480x640 workload (whole path, FP64 C oracle, "
                       f"{threads} OpenMP threads), {el:.1f} s"}
 
