@@ -147,6 +147,21 @@ class Request:
     status: str = ""
 
 
+def arrival_wait(dt: float) -> None:
+    """Wait toward an event `dt` seconds ahead without oversleeping it: the
+    OS sleep overshoots by tens of microseconds, so a long gap (over 200 us)
+    is only half slept, for the caller to wait again, and a short one is
+    spun out on the clock.  The spin touches no GPU state: querying events
+    in a tight loop slowed the stream's own copies and launches.  Both
+    servers wait for arrivals this way."""
+    if dt > 2e-4:
+        time.sleep(dt * 0.5)
+        return
+    end = time.perf_counter() + dt
+    while time.perf_counter() < end:
+        pass
+
+
 def run_stream(reqs: list, pool: SlotPool, executor, clock, sleep, max_inflight: int = 2,
                on_done=None) -> dict:
     """Continuous batching over an arrival-ordered request list.
@@ -156,9 +171,10 @@ def run_stream(reqs: list, pool: SlotPool, executor, clock, sleep, max_inflight:
     ready(handle) -> bool, wait(handle) -> completion time (same clock as
     arrivals), and rebuild() (re-plan after the pool grew; called with no
     step in flight).  `clock()` gives seconds since the stream started and
-    `sleep(dt)` waits.  `on_done(request, slot)`, if given, runs when a
-    request's step has completed and before its slot is released (its
-    outputs are still in the slot).  Every request ends ADMITTED with a
+    `sleep(dt)` waits at most `dt` (returning early only costs another
+    poll).  `on_done(request, slot)`, if given, runs when a request's step
+    has completed and before its slot is released (its outputs are still in
+    the slot).  Every request ends ADMITTED with a
     completion time or REJECTED; the loop always terminates."""
     waiting = collections.OrderedDict()       # class -> FIFO of waiting requests
     nwait = 0
@@ -453,7 +469,7 @@ class Server:
         if on_done is not None:
             cb = lambda r, s: on_done(r, self.exe.batch.outputs[s.index])
         stats = run_stream(reqs, self.pool, self.exe, lambda: time.perf_counter() - t0,
-                           time.sleep, self.max_inflight, cb)
+                           arrival_wait, self.max_inflight, cb)
         stats.update(slots=len(self.pool.slots), slot_bytes=self.pool.used)
         return summarize(reqs, warmup_s, self.classes, extra=stats)
 
@@ -496,9 +512,7 @@ class PlainServer:
                 now = time.perf_counter() - t0
                 if now >= r.arrival:
                     break
-                gap = r.arrival - now
-                if gap > 2e-4:
-                    time.sleep(gap * 0.5)
+                arrival_wait(r.arrival - now)
             while len(inflight) >= max_inflight:
                 ev, rr = inflight.popleft()
                 ev.synchronize()
