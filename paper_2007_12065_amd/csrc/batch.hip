@@ -28,11 +28,13 @@
 // Tile queue.  A stage's tiles are numbered frame by frame over the active
 // frames only; the launch has one workgroup per tile of the whole batch and
 // the hardware dispatcher hands them out as CUs free up.  Workgroup b takes
-// tile number xcd_remap(b): the dispatcher deals workgroups round-robin over
-// the eight XCDs, so each XCD receives one contiguous eighth of the numbers
-// and neighbouring tiles, which share halo lines, meet in the same L2.  The
-// number is mapped back to (frame, tile) by binary search over the prefix
-// sums staged in LDS; numbers past the active total exit at once.  (A
+// a tile number by XCD: the dispatcher deals workgroups round-robin over the
+// eight XCDs, and each XCD takes one contiguous eighth of the ACTIVE total
+// (not of the grid, which is sized for a bound on the active frames), so
+// neighbouring tiles, which share halo lines, meet in the same L2 and all
+// eight XCDs share the work however few frames are active.  Workgroups past
+// their XCD's share exit at once.  The number is mapped back to (frame,
+// tile) by binary search over the prefix sums staged in LDS.  (A
 // persistent grid popping tiles from per-XCD atomic counters was measured
 // slower: contended device-scope atomics put a floor of several hundred
 // microseconds under every stage of a 64-frame batch.)
@@ -120,11 +122,13 @@ constexpr int kLdsFrames = 256;    // prefix sums staged in LDS up to this many 
 // This workgroup's tile: false when its number is past the active total
 // (the whole workgroup then exits).
 __device__ __forceinline__ bool queue_tile(const QueueDev &Q, int n, int *s_start, int2 &t) {
+    // the number depends only on blockIdx and the active total, so a
+    // workgroup without a tile leaves before touching LDS or a barrier
+    const int g = xcd_remap_active((int)blockIdx.x, Q.start[n]);
+    if (g < 0) return false;
     for (int i = threadIdx.x; i <= n && i <= kLdsFrames; i += kTileBlock) s_start[i] = Q.start[i];
     __syncthreads();
     const int *start = n <= kLdsFrames ? s_start : Q.start;
-    const int g = xcd_remap(blockIdx.x, gridDim.x);
-    if (g >= start[n]) return false;
     int lo = 0, hi = n;                       // last frame with start <= g
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;

@@ -34,6 +34,22 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return start + idx;
 }
 
+// The same dealing when only the first `total` numbers of a larger grid carry
+// work: each XCD takes a contiguous eighth of [0, total), so all eight share
+// the work however small `total` is; workgroups past their XCD's range get
+// -1.  With grid >= total each XCD is dealt ceil((grid - x) / 8) >=
+// ceil((total - x) / 8) workgroups, enough for its range: every number in
+// [0, total) is taken exactly once.
+__device__ __forceinline__ int xcd_remap_active(int b, int total) {
+    const int xcd = b % kNumXcd;
+    const int idx = b / kNumXcd;
+    const int q = total / kNumXcd;
+    const int rem = total % kNumXcd;
+    if (idx >= q + (xcd < rem ? 1 : 0)) return -1;
+    const int start = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+    return start + idx;
+}
+
 // Division of a small non-negative index by a workgroup-uniform divisor d:
 // with m = ceil(2^32 / d), floor(i / d) = umulhi(i, m) for every i < 2^32 / d
 // (the error term i (m d - 2^32) / (d 2^32) stays below 1 / d).  Tile
