@@ -9,6 +9,11 @@ Every function promotes its float32 input to float64 and calls the C routines
 in ``pl_oracle.c`` (each cites the passage of the paper it follows).  Array
 layouts match the GPU library: points ``[M, N, 3]``; per-triangle arrays in GID
 order ``[M-1, N-1, 2, 3]`` with GID = 2 (u (N-1) + v) + k (Sec. 4.2).
+
+Parity unpinned: ``vertex_update`` (the paper gives no formula for the vertex
+update; its pins check a restatement of the cited method's update).  Every
+other function is pinned by the tests to what the paper and the mathematics
+fix.
 """
 from __future__ import annotations
 

@@ -16,6 +16,12 @@
  *
  * Readings of points the paper leaves open are marked "Reading:" below.
  *
+ * Parity unpinned: oracle_vertex_update.  The paper names the vertex update
+ * of the method it cites but gives no formula for it; the routine restates
+ * that published update, and its pins (closed forms, invariants) check the
+ * restatement, not a result printed in the paper.  Every other routine is
+ * pinned to values or properties the paper and the mathematics fix.
+ *
  * Grid conventions (Sec. 3, Sec. 4.2): points p[u][v], u = row in [0, M),
  * v = column in [0, N), flat index i = u*N + v, 3 doubles per point.  Quad
  * (u, v) with u < M-1, v < N-1 holds the corners
