@@ -16,7 +16,10 @@ __global__ __launch_bounds__(kTileBlock) void k_mesh_count(const float *__restri
                                                            uint8_t *__restrict__ codes,
                                                            uint8_t *__restrict__ tri_valid,
                                                            int *__restrict__ row_count) {
-    mesh_count_row(pts, N, blockIdx.x, codes, tri_valid, row_count);
+    // each XCD takes a contiguous run of quad rows: the point row that two
+    // neighbouring quad rows share is then fetched once into one L2
+    mesh_count_row(pts, N, xcd_remap((int)blockIdx.x, (int)gridDim.x), codes, tri_valid,
+                   row_count);
 }
 
 __global__ __launch_bounds__(kTileBlock) void k_mesh_emit(const uint8_t *__restrict__ codes,
@@ -26,7 +29,10 @@ __global__ __launch_bounds__(kTileBlock) void k_mesh_emit(const uint8_t *__restr
                                                           int32_t *__restrict__ tris,
                                                           int32_t *__restrict__ he, int cap,
                                                           int32_t *__restrict__ n_tri) {
-    mesh_emit_row(codes, row_count, Mq, N, blockIdx.x, tri_map, tris, he, cap, n_tri);
+    // contiguous rows per XCD, as for the count (the twins read the
+    // neighbouring rows' codes)
+    mesh_emit_row(codes, row_count, Mq, N, xcd_remap((int)blockIdx.x, (int)gridDim.x), tri_map,
+                  tris, he, cap, n_tri);
 }
 
 }  // namespace

@@ -14,7 +14,9 @@ __global__ __launch_bounds__(kTileBlock) void k_tri_normals(const float *__restr
                                                             NT *__restrict__ normals,
                                                             float *__restrict__ centroids) {
     __shared__ NormalsStage st;
-    const size_t q0 = (size_t)blockIdx.x * kTileBlock;
+    // contiguous quad runs per XCD: the point row shared by two quad rows is
+    // fetched once into one L2
+    const size_t q0 = (size_t)xcd_remap((int)blockIdx.x, (int)gridDim.x) * kTileBlock;
     const int nq = (int)(Q - q0 < (size_t)kTileBlock ? Q - q0 : (size_t)kTileBlock);
     normals_block<NT>(pts, N, Nq, q0, nq, normals, centroids, st);
 }

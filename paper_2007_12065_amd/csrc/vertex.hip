@@ -58,8 +58,11 @@ template <typename NT>
 __global__ __launch_bounds__(kVuBlock) void k_vertex_update(const float *__restrict__ in,
                                                             float *__restrict__ out, int M, int N,
                                                             const NT *__restrict__ normals) {
-    // one thread per point, row-major over the frame (a 1-D grid: any M)
-    const long long idx = (long long)blockIdx.x * kVuBlock + threadIdx.x;
+    // one thread per point, row-major over the frame (a 1-D grid: any M);
+    // contiguous runs of points per XCD, so the normals of the quad rows
+    // that neighbouring point rows share are fetched once into one L2
+    const long long idx =
+        (long long)xcd_remap((int)blockIdx.x, (int)gridDim.x) * kVuBlock + threadIdx.x;
     if (idx >= (long long)M * N) return;
     const int r = (int)(idx / N), c = (int)(idx - (long long)r * N);
     const P3 x = ld_p(in, N, r, c);
