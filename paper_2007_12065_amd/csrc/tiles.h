@@ -250,6 +250,169 @@ __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
 }
 
 // ---------------------------------------------------------------------------
+// The same mesh over row segments of kMeshSeg quads, one quad per thread (the
+// single-frame kernels): a 480x640 frame is then 1,437 workgroups instead of
+// 479 rows, enough waves to cover the memory latency of these two short
+// stages.  Segment s of quad row u covers columns [s kMeshSeg, (s+1) kMeshSeg)
+// of every row alike, so with segments numbered row-major (k = u S + s, S
+// segments per row) the first triangle of segment k is the sum of the counts
+// of segments 0 .. k-1, and the twins in rows u-1 and u+1 start at the same
+// sums for k - S and k + S.  The outputs equal the whole-row bodies' above.
+// ---------------------------------------------------------------------------
+
+constexpr int kMeshSeg = kTileBlock;
+constexpr int kMeshSegMax = 8192;    // segments per frame up to which the segment bodies are used
+
+__host__ __device__ constexpr int mesh_segments(int Nq) { return (Nq + kMeshSeg - 1) / kMeshSeg; }
+
+// Validity codes of segment s of quad row u and its triangle count
+// seg_count[u S + s].
+__device__ __forceinline__ void mesh_count_seg(const float *__restrict__ pts, int N, int u, int s,
+                                               int S, uint8_t *__restrict__ codes,
+                                               uint8_t *__restrict__ tri_valid,
+                                               int *__restrict__ seg_count) {
+    __shared__ uint8_t ok[2][kMeshSeg + 1];
+    __shared__ int red[kTileBlock / kWave];
+    const int Nq = N - 1;
+    const int v0 = s * kMeshSeg;
+    const float *r0 = pts + (size_t)u * N * 3;
+    const float *r1 = r0 + (size_t)N * 3;
+    // points v0 .. v0 + kMeshSeg of both rows (the last one by thread 0),
+    // all loads issued before any is used
+    float x[2][2], y[2][2], z[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int v = v0 + (int)threadIdx.x + j * kMeshSeg;
+        const bool in = (j == 0 || threadIdx.x == 0) && v < N;
+        x[0][j] = in ? r0[3 * v] : 0.f; y[0][j] = in ? r0[3 * v + 1] : 0.f; z[0][j] = in ? r0[3 * v + 2] : 0.f;
+        x[1][j] = in ? r1[3 * v] : 0.f; y[1][j] = in ? r1[3 * v + 1] : 0.f; z[1][j] = in ? r1[3 * v + 2] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        if (j == 0 || threadIdx.x == 0) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                ok[r][threadIdx.x + j * kMeshSeg] =
+                    !(is_nan_bits(x[r][j]) || is_nan_bits(y[r][j]) || is_nan_bits(z[r][j]));
+        }
+    }
+    __syncthreads();
+    const int v = v0 + (int)threadIdx.x;
+    int cnt = 0;
+    if (v < Nq) {
+        const int l = threadIdx.x;
+        const int p1 = ok[0][l], p2 = ok[0][l + 1], p3 = ok[1][l + 1], p4 = ok[1][l];
+        const int f = p1 & p2 & p3;          // first triangle (p3, p2, p1)
+        const int g = p1 & p3 & p4;          // second triangle (p1, p4, p3)
+        const size_t q = (size_t)u * Nq + v;
+        codes[q] = (uint8_t)(f | (g << 1));
+        if (tri_valid) {
+            tri_valid[2 * q] = (uint8_t)f;
+            tri_valid[2 * q + 1] = (uint8_t)g;
+        }
+        cnt = f + g;
+    }
+    cnt = wave_sum(cnt);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+#pragma unroll
+        for (int w = 0; w < kTileBlock / kWave; ++w) t += red[w];
+        seg_count[u * S + s] = t;
+    }
+}
+
+// T_map, T and HE of segment s of quad row u (the whole-row emit restricted
+// to one quad per thread; see mesh_emit_row for the twin rules).  The last
+// segment of the last row writes |T|.
+__device__ __forceinline__ void mesh_emit_seg(const uint8_t *__restrict__ codes,
+                                              const int *__restrict__ seg_count, int Mq, int N,
+                                              int u, int s, int S, int32_t *__restrict__ tri_map,
+                                              int32_t *__restrict__ tris,
+                                              int32_t *__restrict__ he, int cap,
+                                              int32_t *__restrict__ n_tri) {
+    __shared__ int red[kTileBlock / kWave];
+    __shared__ int stage[3 * 2 * kMeshSeg];
+    const int Nq = N - 1;
+    const int v0 = s * kMeshSeg;
+    const int ku = u * S + s;                 // this segment
+    const int lo = u > 0 ? ku - S : ku;       // the first of the segments above and here
+    int a = 0;
+    for (int k = threadIdx.x; k < lo; k += kTileBlock) a += seg_count[k];
+    a = wave_sum(a);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = a;
+    __syncthreads();
+    int sum_lo = 0;
+#pragma unroll
+    for (int w = 0; w < kTileBlock / kWave; ++w) sum_lo += red[w];
+    const int basem = sum_lo;                 // first triangle of segment ku - S (u > 0)
+    int base0 = sum_lo;                       // first triangle of this segment
+    if (u > 0)
+        for (int k = ku - S; k < ku; ++k) base0 += seg_count[k];
+    int basep = base0;                        // first triangle of segment ku + S
+    if (u + 1 < Mq)
+        for (int k = ku; k < ku + S; ++k) basep += seg_count[k];
+    if (u == Mq - 1 && s == S - 1 && threadIdx.x == 0) *n_tri = base0 + seg_count[ku];
+
+    const uint8_t *cr0 = codes + (size_t)u * Nq;
+    const int v = v0 + (int)threadIdx.x;
+    const bool in = v < Nq;
+    const int c0 = in ? cr0[v] : 0;
+    const int cm = (in && u > 0) ? cr0[v - Nq] : 0;
+    const int cp = (in && u + 1 < Mq) ? cr0[v + Nq] : 0;
+    const int cl = (in && v > 0) ? cr0[v - 1] : 0;
+    const int cr = v + 1 < Nq ? cr0[v + 1] : 0;
+    unsigned long long total;
+    const unsigned long long ex = mesh_block_scan(
+        (unsigned long long)popc2(c0) | ((unsigned long long)popc2(cm) << 21) |
+            ((unsigned long long)popc2(cp) << 42),
+        &total);
+    const int r0 = base0 + (int)(ex & kField);           // this quad's first triangle
+    const int rm = basem + (int)((ex >> 21) & kField);
+    const int rp = basep + (int)((ex >> 42) & kField);
+    const int nq = min(kMeshSeg, Nq - v0);                // quads in this segment
+    const int nt = (int)(total & kField);                 // triangles in this segment
+    const int nw = max(0, min(nt, cap - base0));          // of them below cap
+    const int f = c0 & 1, g = (c0 >> 1) & 1;
+
+    // T_map: two entries per quad, -1 for an invalid triangle
+    if (in) {
+        stage[2 * threadIdx.x] = f ? r0 : -1;
+        stage[2 * threadIdx.x + 1] = g ? r0 + f : -1;
+    }
+    emit_flush(stage, tri_map + 2 * ((size_t)u * Nq + v0), 2 * nq);
+    // T: first triangle (p3, p2, p1), second (p1, p4, p3)
+    {
+        const int i1 = u * N + v, i2 = i1 + 1, i3 = i1 + N + 1, i4 = i1 + N;
+        const int at = 3 * (r0 - base0);
+        if (f) { stage[at] = i3; stage[at + 1] = i2; stage[at + 2] = i1; }
+        if (g) { stage[at + 3 * f] = i1; stage[at + 3 * f + 1] = i4; stage[at + 3 * f + 2] = i3; }
+        emit_flush(stage, tris + 3 * (size_t)base0, 3 * nw);
+    }
+    // HE: Right = (u, v+1, 1), Top = (u-1, v, 1), Left = (u, v-1, 0),
+    // Bottom = (u+1, v, 0)
+    if (he) {
+        const int right = (cr & 2) ? r0 + f + g + (cr & 1) : -1;
+        const int left = (cl & 1) ? r0 - popc2(cl) : -1;
+        const int top = (cm & 2) ? rm + (cm & 1) : -1;
+        const int bottom = (cp & 1) ? rp : -1;
+        const int at = 3 * (r0 - base0);
+        if (f) {
+            stage[at] = right >= 0 ? 3 * right : -1;
+            stage[at + 1] = top >= 0 ? 3 * top + 1 : -1;
+            stage[at + 2] = g ? 3 * (r0 + f) + 2 : -1;
+        }
+        if (g) {
+            stage[at + 3 * f] = left >= 0 ? 3 * left : -1;
+            stage[at + 3 * f + 1] = bottom >= 0 ? 3 * bottom + 1 : -1;
+            stage[at + 3 * f + 2] = f ? 3 * r0 + 2 : -1;
+        }
+        emit_flush(stage, he + 3 * (size_t)base0, 3 * nw);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Laplacian (Sec. 2.3 Eqs. 1-2 on the image neighbourhood of Sec. 5.1):
 // F Jacobi sweeps of one TH x TW tile, temporally blocked in LDS.
 //

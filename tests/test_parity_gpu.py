@@ -86,7 +86,10 @@ def check_normals(gpu, ref, tol=NORMAL_ATOL):
 
 MESH_GRIDS = [(2, 2, 0.0), (2, 3, 0.2), (3, 2, 0.2), (7, 7, 0.15), (5, 300, 0.1),
               (300, 5, 0.1), (4, 600, 0.3), (33, 260, 0.05), (2, 1000, 0.5), (17, 513, 0.0),
-              (3, 1025, 0.1), (2, 1026, 0.0), (4, 2100, 0.2), (3, 3075, 0.05)]
+              (3, 1025, 0.1), (2, 1026, 0.0), (4, 2100, 0.2), (3, 3075, 0.05),
+              # 256 x 32 = 8192 row segments of 256 quads: the largest frame
+              # meshed by segments; 299 x 28 = 8372 takes the whole-row kernels
+              (257, 8193, 0.1), (300, 7000, 0.1)]
 
 
 def mesh_compare(pl, pts, cap=None):
@@ -122,6 +125,10 @@ def test_mesh_all_nan_and_cap(pl):
     g = random_grid(20, 40, 3, nan_frac=0.2)
     mesh_compare(pl, g, cap=100)
     mesh_compare(pl, g, cap=0)
+    big = random_grid(300, 7000, 5, nan_frac=0.2)          # whole-row kernels
+    mesh_compare(pl, big, cap=123457)
+    seg = random_grid(64, 1100, 6, nan_frac=0.2)           # segments, cap inside a segment
+    mesh_compare(pl, seg, cap=70001)
 
 
 def test_mesh_optional_outputs(pl):
