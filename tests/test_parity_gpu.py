@@ -87,6 +87,8 @@ def check_normals(gpu, ref, tol=NORMAL_ATOL):
 MESH_GRIDS = [(2, 2, 0.0), (2, 3, 0.2), (3, 2, 0.2), (7, 7, 0.15), (5, 300, 0.1),
               (300, 5, 0.1), (4, 600, 0.3), (33, 260, 0.05), (2, 1000, 0.5), (17, 513, 0.0),
               (3, 1025, 0.1), (2, 1026, 0.0), (4, 2100, 0.2), (3, 3075, 0.05),
+              # one full 256-quad segment; a second segment of one quad
+              (4, 257, 0.1), (6, 258, 0.1),
               # 256 x 32 = 8192 row segments of 256 quads: the largest frame
               # meshed by segments; 299 x 28 = 8372 takes the whole-row kernels
               (257, 8193, 0.1), (300, 7000, 0.1)]
