@@ -93,6 +93,27 @@ __device__ __forceinline__ float f32_rounded(float v) {
 }
 __device__ __forceinline__ void st_f(__half *p, float v) { *p = __float2half_rn(f32_rounded(v)); }
 
+// Streaming stores for outputs a kernel writes once and never reads back: the
+// non-temporal hint sends them on towards memory instead of leaving them
+// dirty in L2 for the write-back at the kernel's end.  Same bits as a plain
+// store; the next kernel reads them after its own cache acquire.  Used where
+// it measured faster (480x640 frame: mesh emit 8.6 -> 7.2 us, normals 5.7
+// -> 4.7 us, vertex update 7.6 -> 6.5 us, same bytes; the bilateral's
+// float32 outputs: 2.4 us less per frame over the whole path, although their
+// strided pieces then reach memory as partial lines); the Laplacian's
+// outputs (no change) keep plain stores.
+__device__ __forceinline__ void st_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(int32_t *p, int32_t v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+// two consecutive floats, 8-byte aligned, in one store
+__device__ __forceinline__ void st_stream2(float *p, float a, float b) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    f2v v;
+    v.x = a;
+    v.y = b;
+    __builtin_nontemporal_store(v, reinterpret_cast<f2v *>(p));
+}
+
 // ---- host side -----------------------------------------------------------
 
 void set_error(const char *fmt, ...);

@@ -97,13 +97,13 @@ __global__ __launch_bounds__(kVuBlock) void k_vertex_update(const float *__restr
     }
     if (count) {
         const float inv = __builtin_amdgcn_rcpf((float)count);   // count in 1..6
-        o[0] = fmaf(sx, inv, x.x);
-        o[1] = fmaf(sy, inv, x.y);
-        o[2] = fmaf(sz, inv, x.z);
+        st_stream(&o[0], fmaf(sx, inv, x.x));
+        st_stream(&o[1], fmaf(sy, inv, x.y));
+        st_stream(&o[2], fmaf(sz, inv, x.z));
     } else {
-        o[0] = x.x;
-        o[1] = x.y;
-        o[2] = x.z;
+        st_stream(&o[0], x.x);
+        st_stream(&o[1], x.y);
+        st_stream(&o[2], x.z);
     }
 }
 
