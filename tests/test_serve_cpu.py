@@ -157,3 +157,21 @@ def test_slot_bytes_accounts_for_every_buffer():
     assert b32 - b16 >= 3 * T * 2 * 3               # three normal arrays shrink by 2 B/comp
     assert b16 >= 24 * P + 12 * T + T + 4 * T + 24 * T + 3 * T * 2 * 3
     assert b16 < 80e6
+
+
+def test_arrival_wait_neither_oversleeps_nor_returns_late():
+    # a short gap is spun out on the clock (returns once it has passed, not
+    # much later); a long one is only half slept, leaving the rest to the
+    # caller's next wait, so the OS sleep's overshoot cannot delay an arrival
+    import time
+
+    from paper_2007_12065_amd.serve import arrival_wait
+    for dt in (0.0, 2e-5, 1.5e-4):
+        t0 = time.perf_counter()
+        arrival_wait(dt)
+        took = time.perf_counter() - t0
+        assert dt <= took < dt + 0.02
+    t0 = time.perf_counter()
+    arrival_wait(0.2)
+    took = time.perf_counter() - t0
+    assert 0.099 <= took < 0.19
