@@ -133,8 +133,9 @@ def test_mesh_all_nan_and_cap(pl):
     mesh_compare(pl, seg, cap=70001)
 
 
-def test_mesh_optional_outputs(pl):
-    g = random_grid(30, 70, 4, nan_frac=0.2)
+@pytest.mark.parametrize("M,N", [(30, 70), (300, 7000)])   # segment and whole-row kernels
+def test_mesh_optional_outputs(pl, M, N):
+    g = random_grid(M, N, 4, nan_frac=0.2)
     r = pl.pl_mesh_opc(to_dev(g), tri_valid=False, halfedges=False)
     tri_map, tris = oracle.mesh(g)
     assert r["tri_valid"] is None and r["halfedges"] is None
