@@ -65,103 +65,130 @@ static void tri_vertices(int u, int v, int k, int N, int64_t out[3])
     else        { out[0] = c[1]; out[1] = c[4]; out[2] = c[3]; }
 }
 
+/* A triangle of T_FC is valid iff its three vertices are (Sec. 4.2). */
+static int gid_valid(const double *pts, int64_t g, int Nq, int N)
+{
+    const int64_t q = g / 2;
+    const int u = (int)(q / Nq), v = (int)(q % Nq);
+    int64_t vert[3];
+    tri_vertices(u, v, (int)(g % 2), N, vert);
+    return point_valid(pts + 3 * vert[0]) && point_valid(pts + 3 * vert[1]) &&
+           point_valid(pts + 3 * vert[2]);
+}
+
 /*
- * Alg. 1 (Extract Triangles from OPC), Sec. 4.2.
+ * T and T_map, Sec. 4.2 (computed by Alg. 1): T lists the valid triangles of
+ * T_FC in increasing GID, each as its three point indices in the order
+ * above, and T_map sends a GID to its position in T (-1 if not valid).
+ * Written as that definition: validity per GID, then the rank of each valid
+ * GID among the valid GIDs before it, then T filled at those ranks.
  * pts:       [M*N*3] doubles.
- * tri_map:   [2(M-1)(N-1)] out; rank of each GID in T, or -1.
- * triangles: [3 * 2(M-1)(N-1)] out; T in append order, 3 point indices each.
+ * tri_map:   [2(M-1)(N-1)] out.
+ * triangles: [3 * 2(M-1)(N-1)] out (the first |T| rows are set).
  * Returns |T|.
  */
 OR_EXPORT int64_t oracle_mesh_triangles(const double *pts, int M, int N,
                                         int32_t *tri_map, int32_t *triangles)
 {
     const int Mq = M - 1, Nq = N - 1;
-    int64_t n_tri = 0;
-    for (int64_t g = 0; g < 2LL * Mq * Nq; ++g) tri_map[g] = -1;
-    for (int u = 0; u < Mq; ++u) {
-        for (int v = 0; v < Nq; ++v) {
-            int64_t c[5];
-            quad_corners(u, v, N, c);
-            const int64_t first = 2LL * ((int64_t)u * Nq + v);
-            const int64_t second = first + 1;
-            const int ok1 = point_valid(pts + 3 * c[1]);
-            const int ok2 = point_valid(pts + 3 * c[2]);
-            const int ok3 = point_valid(pts + 3 * c[3]);
-            const int ok4 = point_valid(pts + 3 * c[4]);
-            if (ok1 && ok2 && ok3) {              /* first triangle {p3,p2,p1} */
-                triangles[3 * n_tri + 0] = (int32_t)c[3];
-                triangles[3 * n_tri + 1] = (int32_t)c[2];
-                triangles[3 * n_tri + 2] = (int32_t)c[1];
-                tri_map[first] = (int32_t)n_tri;
-                ++n_tri;
-            }
-            if (ok1 && ok3 && ok4) {              /* second triangle {p1,p4,p3} */
-                triangles[3 * n_tri + 0] = (int32_t)c[1];
-                triangles[3 * n_tri + 1] = (int32_t)c[4];
-                triangles[3 * n_tri + 2] = (int32_t)c[3];
-                tri_map[second] = (int32_t)n_tri;
-                ++n_tri;
-            }
-        }
+    const int64_t n_gid = 2LL * Mq * Nq;
+    int64_t rank = 0;
+    for (int64_t g = 0; g < n_gid; ++g)
+        tri_map[g] = gid_valid(pts, g, Nq, N) ? (int32_t)rank++ : -1;
+    for (int64_t g = 0; g < n_gid; ++g) {
+        if (tri_map[g] < 0) continue;
+        const int64_t q = g / 2;
+        int64_t vert[3];
+        tri_vertices((int)(q / Nq), (int)(q % Nq), (int)(g % 2), N, vert);
+        for (int j = 0; j < 3; ++j) triangles[3LL * tri_map[g] + j] = (int32_t)vert[j];
     }
-    return n_tri;
+    return rank;
 }
 
-/* GID of t_{u,v,k}, or -1 when (u, v) lies outside the quad grid.
- * Reading: the paper's GetNeighborsGID is undefined and says nothing about
- * the grid border; a neighbour off the grid is treated as absent. */
-static int64_t gid_or_none(int u, int v, int k, int Mq, int Nq)
+/* Half-edge records keyed by their ordered point pair (a, b), for the twin
+ * search by reversed pairs (Sec. 4.3). */
+typedef struct {
+    uint64_t key;
+    int64_t id;
+} he_rec;
+
+static uint64_t he_key(int32_t a, int32_t b) { return ((uint64_t)(uint32_t)a << 32) | (uint32_t)b; }
+
+static int he_cmp(const void *x, const void *y)
 {
-    if (u < 0 || u >= Mq || v < 0 || v >= Nq) return -1;
-    return 2LL * ((int64_t)u * Nq + v) + k;
+    const he_rec *p = (const he_rec *)x, *q = (const he_rec *)y;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return p->id < q->id ? -1 : (p->id > q->id);
 }
 
-static int32_t map_at(const int32_t *tri_map, int64_t gid)
+/* Lowest half-edge id keyed `key` in the sorted records, or -1. */
+static int64_t he_first(const he_rec *r, int64_t n, uint64_t key)
 {
-    return gid < 0 ? -1 : tri_map[gid];
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (r[mid].key < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && r[lo].key == key) ? r[lo].id : -1;
 }
 
 /*
- * Alg. 2 (Extract Half-Edges from OPC), Sec. 4.2.
- * Half-edge j of triangle t has id 3t + j and runs from vertex j to vertex
- * (j+1) mod 3 (Sec. 4.2: the first triangle's half-edges are p3->p2, p2->p1,
- * p1->p3).  The neighbours of quad (u, v) are
- *   Right  = second triangle of (u, v+1)   (twin of the first's edge 0)
- *   Top    = second triangle of (u-1, v)   (twin of the first's edge 1)
- *   Left   = first triangle of (u, v-1)    (twin of the second's edge 0)
- *   Bottom = first triangle of (u+1, v)    (twin of the second's edge 1)
- * and the two triangles of a quad share their edge 2 across the cut.
- * he: [3 n_tri] out, -1 where no twin exists (Sec. 3).
+ * Twins of the half-edges of a triangle list by their definition (Sec. 3,
+ * Sec. 4.3): half-edge 3t + j runs from vertex j to vertex (j+1) mod 3 of
+ * triangle t, and its twin is a half-edge running the other way between the
+ * same two points.  Where a point pair carries more than one half-edge
+ * (meshes that are not two-manifold), the paper's option 1 keeps the first
+ * pair found: h = (a, b) is paired only if no lower id is also (a, b), and
+ * then with the lowest id running (b, a).  Half-edges from a point to itself
+ * are never paired.  he: [3 n_tri] out, -1 where there is no twin.
+ */
+static void twins_by_point_pairs(const int32_t *tris, int64_t n_tri, int32_t *he)
+{
+    he_rec *r = (he_rec *)malloc(sizeof(he_rec) * (size_t)(3 * n_tri + 1));
+    int64_t n = 0;
+    for (int64_t t = 0; t < n_tri; ++t)
+        for (int j = 0; j < 3; ++j) {
+            const int32_t a = tris[3 * t + j], b = tris[3 * t + (j + 1) % 3];
+            if (a != b) {
+                r[n].key = he_key(a, b);
+                r[n].id = 3 * t + j;
+                ++n;
+            }
+        }
+    qsort(r, (size_t)n, sizeof(he_rec), he_cmp);
+    for (int64_t h = 0; h < 3 * n_tri; ++h) he[h] = -1;
+    for (int64_t k = 0; k < n; ++k) {
+        if (k > 0 && r[k - 1].key == r[k].key) continue;     /* not the first of its key */
+        const int32_t a = (int32_t)(r[k].key >> 32), b = (int32_t)(r[k].key & 0xffffffffu);
+        he[r[k].id] = (int32_t)he_first(r, n, he_key(b, a));
+    }
+    free(r);
+}
+
+/*
+ * HE of the organized mesh, Sec. 4.2 (computed there by Alg. 2): the twin of
+ * every half-edge of T.  Taken from the definition -- the half-edge running
+ * the other way between the same two points -- over T recovered from T_map
+ * (an organized mesh is two-manifold, so every point pair carries at most one
+ * half-edge each way).  Reading: a half-edge on the grid border or next to a
+ * missing triangle has no twin (-1).
+ * he: [3 n_tri] out.
  */
 OR_EXPORT void oracle_mesh_halfedges(const int32_t *tri_map, int M, int N,
                                      int64_t n_tri, int32_t *he)
 {
     const int Mq = M - 1, Nq = N - 1;
-    for (int64_t h = 0; h < 3 * n_tri; ++h) he[h] = -1;
-    for (int u = 0; u < Mq; ++u) {
-        for (int v = 0; v < Nq; ++v) {
-            const int32_t first = map_at(tri_map, gid_or_none(u, v, 0, Mq, Nq));
-            const int32_t second = map_at(tri_map, gid_or_none(u, v, 1, Mq, Nq));
-            const int64_t top_gid = gid_or_none(u - 1, v, 1, Mq, Nq);
-            const int64_t right_gid = gid_or_none(u, v + 1, 1, Mq, Nq);
-            const int64_t bottom_gid = gid_or_none(u + 1, v, 0, Mq, Nq);
-            const int64_t left_gid = gid_or_none(u, v - 1, 0, Mq, Nq);
-            if (first != -1) {
-                const int32_t top = map_at(tri_map, top_gid);
-                const int32_t right = map_at(tri_map, right_gid);
-                if (right != -1) he[3LL * first] = 3 * right;
-                if (top != -1) he[3LL * first + 1] = 3 * top + 1;
-                if (second != -1) he[3LL * first + 2] = 3 * second + 2;
-            }
-            if (second != -1) {
-                const int32_t bottom = map_at(tri_map, bottom_gid);
-                const int32_t left = map_at(tri_map, left_gid);
-                if (left != -1) he[3LL * second] = 3 * left;
-                if (bottom != -1) he[3LL * second + 1] = 3 * bottom + 1;
-                if (first != -1) he[3LL * second + 2] = 3 * first + 2;
-            }
-        }
+    int32_t *tris = (int32_t *)malloc(sizeof(int32_t) * (size_t)(3 * n_tri + 1));
+    for (int64_t g = 0; g < 2LL * Mq * Nq; ++g) {
+        const int32_t t = tri_map[g];
+        if (t < 0 || t >= n_tri) continue;
+        const int64_t q = g / 2;
+        int64_t vert[3];
+        tri_vertices((int)(q / Nq), (int)(q % Nq), (int)(g % 2), N, vert);
+        for (int j = 0; j < 3; ++j) tris[3LL * t + j] = (int32_t)vert[j];
     }
+    twins_by_point_pairs(tris, n_tri, he);
+    free(tris);
 }
 
 /*
@@ -627,58 +654,11 @@ OR_EXPORT void oracle_ga_integrate(const float *cells, int n_cells, const float 
  * half-edge with a == b, gets -1.  The twins are then a symmetric pairing.
  *
  * Written as a sort of (key, index) pairs followed by binary searches: the
- * first half-edge of a key is the head of its run.
+ * first half-edge of a key is the head of its run (twins_by_point_pairs).
  */
-typedef struct {
-    uint64_t key;
-    int64_t id;
-} he_rec;
-
-static int he_cmp(const void *x, const void *y)
-{
-    const he_rec *a = (const he_rec *)x, *b = (const he_rec *)y;
-    if (a->key != b->key) return a->key < b->key ? -1 : 1;
-    return a->id < b->id ? -1 : (a->id > b->id);
-}
-
-static uint64_t he_key(int32_t a, int32_t b)
-{
-    return ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
-}
-
-/* head of the run with `key` in the sorted records (its lowest id), or -1 */
-static int64_t he_first(const he_rec *r, int64_t n, uint64_t key)
-{
-    int64_t lo = 0, hi = n;                     /* first record with r.key >= key */
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (r[mid].key < key) lo = mid + 1; else hi = mid;
-    }
-    return (lo < n && r[lo].key == key) ? r[lo].id : -1;
-}
-
 OR_EXPORT void oracle_user_halfedges(const int32_t *tris, int64_t n_tri, int32_t *he)
 {
-    he_rec *r = (he_rec *)malloc(sizeof(he_rec) * (size_t)(3 * n_tri + 1));
-    int64_t n = 0;
-    for (int64_t t = 0; t < n_tri; ++t)
-        for (int j = 0; j < 3; ++j) {
-            const int32_t a = tris[3 * t + j], b = tris[3 * t + (j + 1) % 3];
-            if (a != b) {
-                r[n].key = he_key(a, b);
-                r[n].id = 3 * t + j;
-                ++n;
-            }
-        }
-    qsort(r, (size_t)n, sizeof(he_rec), he_cmp);
-    for (int64_t h = 0; h < 3 * n_tri; ++h) he[h] = -1;
-    for (int64_t k = 0; k < n; ++k) {
-        if (k > 0 && r[k - 1].key == r[k].key) continue;     /* not the first of its key */
-        const int32_t a = (int32_t)(r[k].key >> 32), b = (int32_t)(r[k].key & 0xffffffffu);
-        const int64_t g = he_first(r, n, he_key(b, a));
-        he[r[k].id] = (int32_t)g;
-    }
-    free(r);
+    twins_by_point_pairs(tris, n_tri, he);
 }
 
 /*

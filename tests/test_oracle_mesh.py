@@ -1,8 +1,11 @@
-"""Pins for the oracle's mesh extraction (Alg. 1 and Alg. 2, Sec. 4.2).
+"""Pins for the oracle's mesh extraction (T, T_map and HE of Sec. 4.2).
 
-Each check ties the oracle to something other than itself: the paper's printed
-triangle counts, the independent hashmap twin search of Sec. 4.3, closed-form
-counts, and geometric facts (winding, twin involution).
+The oracle computes T and T_map from their definition (valid triangles of
+T_FC ranked in GID order) and HE from the twin definition (the half-edge of
+the reversed point pair).  Each check ties it to something other than itself:
+the paper's printed triangle counts, the neighbour rules by which Alg. 2
+builds HE, a brute-force pair search, closed-form counts, and geometric facts
+(winding, twin involution).
 """
 import os
 
@@ -19,9 +22,42 @@ def full_grid(M, N):
     return np.stack([v, u, np.ones_like(u)], axis=-1)
 
 
+def alg2_twins(tri_map, M, N):
+    """HE as Alg. 2 builds it from T_map alone (Sec. 4.2): the first triangle
+    of quad (u, v) meets the second triangle of its Right (u, v+1) and Top
+    (u-1, v) neighbours across its edges 0 and 1, the second triangle meets
+    the first triangle of its Left (u, v-1) and Bottom (u+1, v) neighbours
+    across its edges 0 and 1, and the two share edge 2 across the cut; a
+    neighbour off the grid or missing gives -1.  Vectorised over the quads."""
+    Mq, Nq = M - 1, N - 1
+    tm = tri_map.reshape(Mq, Nq, 2).astype(np.int64)
+    pad = np.full((Mq + 2, Nq + 2, 2), -1, dtype=np.int64)
+    pad[1:-1, 1:-1] = tm
+    F, S = tm[..., 0], tm[..., 1]
+    right = pad[1:-1, 2:, 1]
+    top = pad[:-2, 1:-1, 1]
+    left = pad[1:-1, :-2, 0]
+    bottom = pad[2:, 1:-1, 0]
+    n = int((tm >= 0).sum())
+    he = np.full(3 * n, -1, dtype=np.int64)
+
+    def link(src, j, dst, k):
+        ok = (src >= 0) & (dst >= 0)
+        he[3 * src[ok] + j] = 3 * dst[ok] + k
+
+    link(F, 0, right, 0)
+    link(F, 1, top, 1)
+    link(F, 2, S, 2)
+    link(S, 0, left, 0)
+    link(S, 1, bottom, 1)
+    link(S, 2, F, 2)
+    return he.astype(np.int32)
+
+
 def hashmap_twins(tris):
-    """Sec. 4.3's method for user meshes: key every half-edge by its ordered
-    point pair; the twin of (a, b) is the half-edge keyed (b, a)."""
+    """Brute-force form of the twin definition (Sec. 3, Sec. 4.3): key every
+    half-edge by its ordered point pair in a dictionary; the twin of (a, b) is
+    the half-edge keyed (b, a)."""
     table = {}
     for t, tri in enumerate(tris):
         for j in range(3):
@@ -77,6 +113,26 @@ def test_halfedges_equal_hashmap(orc, seed):
     tri_map, tris = orc.mesh(g)
     he = orc.halfedges(tri_map, M, N, len(tris))
     assert np.array_equal(he, hashmap_twins(tris))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_halfedges_equal_alg2_neighbour_rules(orc, seed):
+    """Alg. 2's Right/Top/Left/Bottom links give the same twins as the
+    reversed-pair definition the oracle uses."""
+    rng = np.random.default_rng(500 + seed)
+    M, N = int(rng.integers(2, 12)), int(rng.integers(2, 12))
+    g = random_grid(M, N, 500 + seed, nan_frac=float(rng.uniform(0.0, 0.5)))
+    tri_map, tris = orc.mesh(g)
+    he = orc.halfedges(tri_map, M, N, len(tris))
+    assert np.array_equal(he, alg2_twins(tri_map, M, N))
+
+
+def test_halfedges_alg2_full_and_holed_frames(orc):
+    for M, N, nan in ((2, 2, 0.0), (7, 7, 0.0), (31, 47, 0.2), (60, 9, 0.5)):
+        g = random_grid(M, N, M * N, nan_frac=nan)
+        tri_map, tris = orc.mesh(g)
+        he = orc.halfedges(tri_map, M, N, len(tris))
+        assert np.array_equal(he, alg2_twins(tri_map, M, N))
 
 
 @pytest.mark.parametrize("seed", range(5))
