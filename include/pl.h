@@ -102,6 +102,28 @@ pl_status pl_mesh_opc(const float *pts, int32_t M, int32_t N,
                       void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * pl_mesh_opc without a workspace, for callers that cannot allocate device
+ * memory: code being captured into a HIP graph, tight serving loops, and
+ * harnesses that forbid allocation.  Arguments, outputs and errors are those
+ * of pl_mesh_opc, whose outputs it reproduces bit for bit; the validity codes
+ * and segment counts that pl_mesh_opc keeps in the workspace live instead in
+ * a static device array of 8 MiB (one per GPU, held until the process ends,
+ * its address looked up on the first call on that GPU).
+ * Limit: frames with pl_mesh_opc_workspace(M, N) <= 8 MiB (about 8.3
+ * million quads, e.g. 2000 x 4096); larger frames get PL_ERR_SHAPE and
+ * nothing is enqueued.  The call allocates nothing and writes no memory the
+ * caller did not pass except that array; nothing in it needs clearing (every
+ * code and count a call reads, the same call writes first).
+ * Calls that overlap in time on one GPU (on different streams, or from
+ * different threads) share the array and race: order them on one stream.
+ * `stream` must belong to a device in 0..63.
+ */
+pl_status pl_mesh_opc_static(const float *pts, int32_t M, int32_t N,
+                             uint8_t *tri_valid, int32_t *tri_map, int32_t *triangles,
+                             int32_t *halfedges, int32_t cap, int32_t *n_tri,
+                             hipStream_t stream);
+
+/*
  * Laplacian vertex filter, Sec. 2.3 Eqs. (1)-(2) on the image-space
  * neighbourhood of Sec. 5.1, `iterations` Jacobi sweeps:
  *     v_o = v_i + lambda * sum_j w_j (v_j - v_i) / sum_j w_j,

@@ -34,6 +34,8 @@ _lib.pl_mesh_opc_workspace.argtypes = [_i32, _i32]
 _lib.pl_mesh_opc_workspace.restype = _sz
 _lib.pl_mesh_opc.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.pl_mesh_opc.restype = _i32
+_lib.pl_mesh_opc_static.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp]
+_lib.pl_mesh_opc_static.restype = _i32
 _lib.pl_laplacian_workspace.argtypes = [_i32, _i32, _i32]
 _lib.pl_laplacian_workspace.restype = _sz
 _lib.pl_laplacian_fused_sweeps.argtypes = [_i32]
@@ -114,6 +116,7 @@ _lib.pl_vertex_update.restype = _i32
 PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL, PL_STAGE_BATCH_LAPLACIAN, PL_STAGE_BATCH_BILATERAL = 0, 1, 2, 3
 
 EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc",
+           "pl_mesh_opc_static",
            "pl_laplacian_workspace", "pl_laplacian_fused_sweeps", "pl_laplacian", "pl_tri_normals",
            "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
            "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
@@ -203,6 +206,33 @@ def pl_mesh_opc(pts: torch.Tensor, *, tri_valid: bool = True, halfedges: bool = 
     _check(_lib.pl_mesh_opc(_ptr(pts), M, N, _ptr(out["tri_valid"]), _ptr(out["tri_map"]),
                             _ptr(out["triangles"]), _ptr(out["halfedges"]), cap,
                             _ptr(out["n_tri"]), _ptr(ws), ws_n, _stream(dev)), "pl_mesh_opc")
+    return out
+
+
+def pl_mesh_opc_static(pts: torch.Tensor, *, tri_valid: bool = True, halfedges: bool = True,
+                       cap: int | None = None, out: dict | None = None) -> dict:
+    """pl_mesh_opc without a workspace (the library's static scratch).  With
+    `out` (a dict of preallocated tensors with pl_mesh_opc's keys) nothing is
+    allocated, so the call can sit in a graph capture or a serving loop."""
+    _dev_tensor(pts, torch.float32, "pts")
+    if pts.dim() != 3 or pts.shape[2] != 3:
+        raise ValueError("pts must be [M, N, 3]")
+    M, N = int(pts.shape[0]), int(pts.shape[1])
+    dev = pts.device
+    T = 2 * max(M - 1, 0) * max(N - 1, 0)
+    cap = T if cap is None else int(cap)
+    if out is None:
+        out = dict(
+            tri_valid=torch.empty(T, dtype=torch.uint8, device=dev) if tri_valid else None,
+            tri_map=torch.empty(T, dtype=torch.int32, device=dev),
+            triangles=torch.empty((max(cap, 1), 3), dtype=torch.int32, device=dev),
+            halfedges=torch.empty(3 * max(cap, 1), dtype=torch.int32, device=dev) if halfedges else None,
+            n_tri=torch.empty(1, dtype=torch.int32, device=dev),
+        )
+    _check(_lib.pl_mesh_opc_static(_ptr(pts), M, N, _ptr(out.get("tri_valid")),
+                                   _ptr(out["tri_map"]), _ptr(out["triangles"]),
+                                   _ptr(out.get("halfedges")), cap, _ptr(out["n_tri"]),
+                                   _stream(dev)), "pl_mesh_opc_static")
     return out
 
 

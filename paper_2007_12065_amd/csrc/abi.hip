@@ -30,6 +30,11 @@ pl_status hip_check(hipError_t e, const char *what) {
     return PL_ERR_HIP;
 }
 
+#define PL_TRY(x)                          \
+    do {                                   \
+        if (pl_status _s = (x)) return _s; \
+    } while (0)
+
 namespace {
 
 struct Range {
@@ -92,15 +97,53 @@ pl_status check_ws(const void *ws, size_t have, size_t need) {
     return PL_OK;
 }
 
+// Arguments of the mesh entry points (pl_mesh_opc, pl_mesh_opc_static).
+pl_status check_mesh(const float *pts, int32_t M, int32_t N, uint8_t *tri_valid,
+                     int32_t *tri_map, int32_t *triangles, int32_t *halfedges, int32_t cap,
+                     int32_t *n_tri) {
+    PL_TRY(check_shape(M, N));
+    if (cap < 0) {
+        set_error("cap %d < 0", cap);
+        return PL_ERR_ARG;
+    }
+    PL_TRY(check_ptrs({{pts, "pts"}, {tri_map, "tri_map"}, {n_tri, "n_tri"}}));
+    if (cap > 0) PL_TRY(check_ptrs({{triangles, "triangles"}}));
+    if (halfedges && cap > 0) PL_TRY(check_ptrs({{halfedges, "halfedges"}}));
+    if (tri_valid) PL_TRY(check_ptrs({{tri_valid, "tri_valid"}}));
+    return PL_OK;
+}
+
+// No output of a mesh call may overlap the points or another output
+// (`ws` is the workspace, if any).
+pl_status check_mesh_alias(const float *pts, int32_t M, int32_t N, uint8_t *tri_valid,
+                           int32_t *tri_map, int32_t *triangles, int32_t *halfedges,
+                           int32_t cap, int32_t *n_tri, Range ws) {
+    const size_t T = 2 * (size_t)(M - 1) * (N - 1);
+    const Range in{pts, sizeof(float) * 3 * (size_t)M * N};
+    const Range outs[] = {{tri_valid, tri_valid ? T : 0},
+                          {tri_map, 4 * T},
+                          {triangles, 12 * (size_t)cap},
+                          {halfedges, halfedges ? 12 * (size_t)cap : 0},
+                          {n_tri, 4},
+                          ws};
+    for (size_t i = 0; i < sizeof(outs) / sizeof(outs[0]); ++i) {
+        if (overlap(in, outs[i])) {
+            set_error("output %zu overlaps pts", i);
+            return PL_ERR_ALIAS;
+        }
+        for (size_t j = i + 1; j < sizeof(outs) / sizeof(outs[0]); ++j)
+            if (overlap(outs[i], outs[j])) {
+                set_error("outputs %zu and %zu overlap", i, j);
+                return PL_ERR_ALIAS;
+            }
+    }
+    return PL_OK;
+}
+
 }  // namespace
 }  // namespace pl
 
 using namespace pl;
-
-#define PL_TRY(x)                          \
-    do {                                   \
-        if (pl_status _s = (x)) return _s; \
-    } while (0)
 
 static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
                   (int)PL_STAGE_BILATERAL == (int)pl::kStageBilateral &&
@@ -124,37 +167,32 @@ __attribute__((visibility("default"))) pl_status pl_mesh_opc(
     int32_t *triangles, int32_t *halfedges, int32_t cap, int32_t *n_tri, void *ws,
     size_t ws_bytes, hipStream_t stream) {
     g_err[0] = 0;
-    PL_TRY(check_shape(M, N));
-    if (cap < 0) {
-        set_error("cap %d < 0", cap);
-        return PL_ERR_ARG;
-    }
-    PL_TRY(check_ptrs({{pts, "pts"}, {tri_map, "tri_map"}, {n_tri, "n_tri"}}));
-    if (cap > 0) PL_TRY(check_ptrs({{triangles, "triangles"}}));
-    if (halfedges && cap > 0) PL_TRY(check_ptrs({{halfedges, "halfedges"}}));
-    if (tri_valid) PL_TRY(check_ptrs({{tri_valid, "tri_valid"}}));
+    PL_TRY(check_mesh(pts, M, N, tri_valid, tri_map, triangles, halfedges, cap, n_tri));
     PL_TRY(check_ws(ws, ws_bytes, mesh_workspace(M, N)));
-    const size_t T = 2 * (size_t)(M - 1) * (N - 1);
-    const Range in{pts, sizeof(float) * 3 * (size_t)M * N};
-    const Range outs[] = {{tri_valid, tri_valid ? T : 0},
-                          {tri_map, 4 * T},
-                          {triangles, 12 * (size_t)cap},
-                          {halfedges, halfedges ? 12 * (size_t)cap : 0},
-                          {n_tri, 4},
-                          {ws, mesh_workspace(M, N)}};
-    for (size_t i = 0; i < sizeof(outs) / sizeof(outs[0]); ++i) {
-        if (overlap(in, outs[i])) {
-            set_error("output %zu overlaps pts", i);
-            return PL_ERR_ALIAS;
-        }
-        for (size_t j = i + 1; j < sizeof(outs) / sizeof(outs[0]); ++j)
-            if (overlap(outs[i], outs[j])) {
-                set_error("outputs %zu and %zu overlap", i, j);
-                return PL_ERR_ALIAS;
-            }
-    }
+    PL_TRY(check_mesh_alias(pts, M, N, tri_valid, tri_map, triangles, halfedges, cap, n_tri,
+                            {ws, mesh_workspace(M, N)}));
     return launch_mesh(pts, M, N, tri_valid, tri_map, triangles, cap > 0 ? halfedges : nullptr,
                        cap, n_tri, ws, stream);
+}
+
+__attribute__((visibility("default"))) pl_status pl_mesh_opc_static(
+    const float *pts, int32_t M, int32_t N, uint8_t *tri_valid, int32_t *tri_map,
+    int32_t *triangles, int32_t *halfedges, int32_t cap, int32_t *n_tri, hipStream_t stream) {
+    g_err[0] = 0;
+    PL_TRY(check_mesh(pts, M, N, tri_valid, tri_map, triangles, halfedges, cap, n_tri));
+    const size_t need = mesh_workspace(M, N);
+    if (need > mesh_static_scratch_bytes()) {
+        set_error("shape %d x %d needs %zu bytes of mesh scratch; the static scratch of "
+                  "pl_mesh_opc_static holds %zu (use pl_mesh_opc with a workspace)",
+                  M, N, need, mesh_static_scratch_bytes());
+        return PL_ERR_SHAPE;
+    }
+    PL_TRY(check_mesh_alias(pts, M, N, tri_valid, tri_map, triangles, halfedges, cap, n_tri,
+                            {nullptr, 0}));
+    void *scr = nullptr;
+    PL_TRY(mesh_static_scratch(stream, &scr));
+    return launch_mesh(pts, M, N, tri_valid, tri_map, triangles, cap > 0 ? halfedges : nullptr,
+                       cap, n_tri, scr, stream);
 }
 
 __attribute__((visibility("default"))) size_t pl_laplacian_workspace(int32_t M, int32_t N,

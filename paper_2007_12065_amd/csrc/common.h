@@ -125,6 +125,10 @@ pl_status launch_mesh(const float *pts, int M, int N, uint8_t *tri_valid,
                       int32_t *tri_map, int32_t *triangles, int32_t *halfedges,
                       int32_t cap, int32_t *n_tri, void *ws, hipStream_t s);
 size_t mesh_workspace(int M, int N);
+// The allocation-free mesh entry's scratch: capacity in bytes, and its device
+// address on the device of stream `s` (looked up on the first call there).
+size_t mesh_static_scratch_bytes();
+pl_status mesh_static_scratch(hipStream_t s, void **out);
 
 pl_status launch_laplacian(const float *in, float *out, int M, int N, int kernel,
                            float lambda, int iterations, void *ws, hipStream_t s);

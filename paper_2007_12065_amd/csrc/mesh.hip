@@ -15,6 +15,8 @@
 // append order and every output is bit-exact and deterministic.
 #include "tiles.h"
 
+#include <mutex>
+
 namespace pl {
 
 namespace {
@@ -63,7 +65,52 @@ __global__ __launch_bounds__(kTileBlock) void k_mesh_emit_rows(const uint8_t *__
                   tris, he, cap, n_tri);
 }
 
+// Scratch of the allocation-free entry point (pl_mesh_opc_static): the
+// validity codes and per-segment counts that pl_mesh_opc keeps in the
+// caller's workspace.  Every device the library runs on holds one copy until
+// the process ends.  Host code never passes this name to a kernel (in host
+// code it is a host-side stand-in, not a device address): it uses the
+// address hipGetSymbolAddress returns for the device in question.
+constexpr size_t kMeshScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) uint8_t scratch[kMeshScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];    // device address of `scratch` per device, once looked up
+
 }  // namespace
+
+size_t mesh_static_scratch_bytes() { return kMeshScratchBytes; }
+
+pl_status mesh_static_scratch(hipStream_t s, void **out) {
+    int cur = 0;
+    if (pl_status st = hip_check(hipGetDevice(&cur), "hipGetDevice")) return st;
+    int dev = cur;
+    if (s) {
+        hipDevice_t d;
+        if (pl_status st = hip_check(hipStreamGetDevice(s, &d), "hipStreamGetDevice")) return st;
+        dev = (int)d;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d: the static mesh scratch serves devices 0..%d", dev, kMaxDevices - 1);
+        return PL_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        // look the array up with its device current: each device holds its
+        // own copy at its own address
+        if (dev != cur)
+            if (pl_status st = hip_check(hipSetDevice(dev), "hipSetDevice")) return st;
+        void *p = nullptr;
+        const pl_status st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                                       "hipGetSymbolAddress(scratch)");
+        if (dev != cur) (void)hipSetDevice(cur);
+        if (st) return st;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return PL_OK;
+}
 
 size_t mesh_workspace(int M, int N) {
     const size_t Q = (size_t)(M - 1) * (N - 1);

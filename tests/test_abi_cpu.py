@@ -54,6 +54,27 @@ def err(pl):
     return pl._lib.pl_last_error().decode()
 
 
+def test_mesh_static_argument_errors(pl):
+    """The allocation-free mesh entry validates like pl_mesh_opc and rejects
+    frames whose codes and counts exceed its static scratch, all before it
+    looks up the scratch or launches anything."""
+    lib = pl._lib
+    f = lib.pl_mesh_opc_static
+    assert f(A, 10, 1, None, B, C, None, 10, C + 4096, None) == -2
+    assert f(A, 10, 10, None, B, C, None, -1, C + 4096, None) == -1
+    assert f(A, 10, 10, None, None, C, None, 10, C + 4096, None) == -1
+    assert "tri_map" in err(pl)
+    assert f(A, 10, 10, None, B + 4, C, None, 10, C + 4096, None) == -1
+    # 3000 x 3000: 9 M quads of codes, above the 8 MiB scratch
+    assert lib.pl_mesh_opc_workspace(3000, 3000) > 8 << 20
+    assert f(A, 3000, 3000, None, B, C, None, 10, C + 4096, None) == -2
+    assert "static scratch" in err(pl)
+    # 2000 x 4096 fits
+    assert lib.pl_mesh_opc_workspace(2000, 4096) <= 8 << 20
+    # an output overlapping the points
+    assert f(A, 10, 10, None, A + 16, C, None, 10, C + 4096, None) == -4
+
+
 def test_laplacian_argument_errors(pl):
     lib = pl._lib
     assert lib.pl_laplacian(A, B, 1, 5, 3, 1.0, 1, None, 0, None) == -2
