@@ -464,6 +464,38 @@ pl_status pl_batch_capture_bounded(pl_batch batch, const uint8_t *active, int32_
 pl_status pl_batch_replay_bounded(pl_batch batch, int32_t n_active, hipStream_t stream);
 
 /*
+ * The whole path on ONE frame in as few kernel launches as its dependencies
+ * allow: mesh (Sec. 4.2, Alg. 1 and Alg. 2), Laplacian (Sec. 2.3 Eqs. 1-2,
+ * Sec. 5.1), centroids and normals, bilateral filter and the gather onto T
+ * (Eqs. 3-6, Sec. 5.2), and the group labels of Alg. 4 (Sec. 7.1) when
+ * frame->groups is set.  The outputs are exactly those of the single-frame
+ * calls listed for the batched path below (pl_mesh_opc, pl_laplacian,
+ * pl_tri_normals, pl_bilateral with the gather, pl_group_assign), bit for
+ * bit; frame->normals receives the FILTERED normals (T_FC layout) and the
+ * unfiltered normals are not stored.  The mesh's validity pass runs in the
+ * same launch as the Laplacian's first pass, the mesh emit in the launch
+ * after it, and the first bilateral pass computes the normals and centroids
+ * itself (a 480 x 640 frame with the default tuning: 3 launches instead of
+ * 6).
+ *
+ * frame      HOST pointer to one pl_frame (the layout is documented with the
+ *            batched path below); its buffers are device memory owned by
+ *            the caller, 16-byte aligned, sized as listed there.
+ * ndt        storage type of the normals.
+ * ws         pl_smooth_frame_workspace(frame, ndt) bytes of device memory
+ *            (codes and counts of the mesh, ping-pong buffers when a filter
+ *            takes more than one sweep); must not overlap the frame's
+ *            buffers.  pl_smooth_frame_workspace returns 0 for an invalid
+ *            frame.
+ * Errors are those of pl_batch_create for a one-frame list, plus
+ * PL_ERR_WORKSPACE.  Device-only work on `stream`: no allocation, no
+ * synchronisation, legal under graph capture.
+ */
+size_t pl_smooth_frame_workspace(const pl_frame *frame, pl_dtype ndt);
+pl_status pl_smooth_frame(const pl_frame *frame, pl_dtype ndt, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/*
  * One-shot form for callers that run a frame list once: pl_batch_create,
  * pl_batch_run over all frames, pl_batch_destroy.  `ws` holds
  * pl_batch_workspace(frames, n, ndt) bytes and must stay allocated and

@@ -81,6 +81,10 @@ _lib.pl_batch_capture_bounded.argtypes = [_vp, _vp, _i32, _vp]
 _lib.pl_batch_capture_bounded.restype = _i32
 _lib.pl_batch_replay_bounded.argtypes = [_vp, _i32, _vp]
 _lib.pl_batch_replay_bounded.restype = _i32
+_lib.pl_smooth_frame_workspace.argtypes = [ctypes.POINTER(PLFrame), _i32]
+_lib.pl_smooth_frame_workspace.restype = _sz
+_lib.pl_smooth_frame.argtypes = [ctypes.POINTER(PLFrame), _i32, _vp, _sz, _vp]
+_lib.pl_smooth_frame.restype = _i32
 _lib.pl_smooth_batch.argtypes = [_vp, _i32, _i32, _vp, _sz, _vp]
 _lib.pl_smooth_batch.restype = _i32
 _lib.pl_batch_destroy.argtypes = [_vp]
@@ -121,7 +125,7 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
            "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
            "pl_batch_replay", "pl_batch_capture_bounded", "pl_batch_replay_bounded",
-           "pl_batch_destroy", "pl_smooth_batch", "pl_group_assign", "pl_ga_workspace",
+           "pl_batch_destroy", "pl_smooth_batch", "pl_smooth_frame_workspace", "pl_smooth_frame", "pl_group_assign", "pl_ga_workspace",
            "pl_ga_workspace_cells", "pl_ga_create", "pl_ga_create_cells", "pl_ga_cell_count",
            "pl_ga_cells", "pl_ga_integrate", "pl_ga_destroy", "pl_user_halfedges_workspace",
            "pl_user_halfedges", "pl_vertex_update_workspace", "pl_vertex_update"]
@@ -541,6 +545,37 @@ class FramePlan:
         self.run_normals(s)
         self.run_bilateral(s)
 
+    def _fused_frame(self, pts):
+        if getattr(self, "_frame", None) is None:
+            f = PLFrame()
+            f.M, f.N = self.M, self.N
+            f.kernel_lap, f.iters_lap, f.lambda_ = self.kernel_lap, self.iters_lap, self.lam
+            f.kernel_bil, f.iters_bil = self.kernel_bil, self.iters_bil
+            f.sigma_length, f.sigma_angle = self.sigma_length, self.sigma_angle
+            for buf, field in ((self.points, "pts_out"), (self.filtered, "normals"),
+                               (self.centroids, "centroids"), (self.tri_valid, "tri_valid"),
+                               (self.tri_map, "tri_map"), (self.triangles, "triangles"),
+                               (self.halfedges, "halfedges"), (self.n_tri, "n_tri"),
+                               (self.normals_T, "normals_T")):
+                setattr(f, field, buf.data_ptr())
+            f.pts = pts.data_ptr()
+            self._ws_frame_n = _lib.pl_smooth_frame_workspace(ctypes.byref(f), self.ndt)
+            if self._ws_frame_n == 0:
+                raise PLError(-1, "pl_smooth_frame_workspace")
+            self.ws_frame = _ws(self._ws_frame_n, self.device)
+            self._frame = f
+        return self._frame
+
+    def run_fused(self, pts: torch.Tensor, s=None) -> None:
+        """The same outputs as run() (except the unfiltered normals, which
+        stay internal) through pl_smooth_frame: three to a few launches
+        instead of six."""
+        f = self._fused_frame(pts)
+        f.pts = pts.data_ptr()
+        s = _stream(self.device) if s is None else s
+        _check(_lib.pl_smooth_frame(ctypes.byref(f), self.ndt, _ptr(self.ws_frame),
+                                    self._ws_frame_n, s), "pl_smooth_frame")
+
 
 def pl_tune_get(stage: int, kernel: int) -> tuple[int, int, int]:
     """(tile_rows, tile_cols, fuse) used for a stage and window size."""
@@ -623,6 +658,25 @@ def pl_smooth_batch(frames: list, normal_dtype=torch.float32) -> list:
         o["_ws"] = ws
         o["_dominant"] = f.get("dominant")
     return outputs
+
+
+def pl_smooth_frame(frame: dict, normal_dtype=torch.float32) -> dict:
+    """The whole path on one frame (keys as for Batch) through the fused
+    single-frame entry point; returns the output dict (points, normals =
+    filtered T_FC normals, centroids, tri_valid, tri_map, triangles,
+    halfedges, n_tri, normals_T, and groups if dominant normals are given)."""
+    ndt = _ndt(normal_dtype)
+    device = frame["pts"].device
+    arr, outputs = _marshal_frames([frame], ndt)
+    ws_n = _lib.pl_smooth_frame_workspace(arr, ndt)
+    if ws_n == 0:
+        raise PLError(-1, "pl_smooth_frame_workspace")
+    ws = torch.empty(ws_n, dtype=torch.uint8, device=device)
+    _check(_lib.pl_smooth_frame(arr, ndt, _ptr(ws), ws_n, _stream(device)), "pl_smooth_frame")
+    out = outputs[0]
+    out["_ws"] = ws                 # the caching allocator keeps it until the stream is past
+    out["_dominant"] = frame.get("dominant")
+    return out
 
 
 class Batch:

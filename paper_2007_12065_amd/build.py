@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpl.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["abi.hip", "mesh.hip", "laplacian.hip", "normals.hip", "bilateral.hip", "tuning.hip", "batch.hip",
-           "groups.hip", "ga.hip", "halfedges.hip", "vertex.hip"]
+           "frame.hip", "groups.hip", "ga.hip", "halfedges.hip", "vertex.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

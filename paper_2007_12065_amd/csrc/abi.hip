@@ -450,6 +450,40 @@ pl_status check_batch(const pl_frame *frames, int32_t n, pl_dtype ndt) {
 
 extern "C" {
 
+__attribute__((visibility("default"))) size_t pl_smooth_frame_workspace(const pl_frame *frame,
+                                                                        pl_dtype ndt) {
+    if (check_batch(frame, 1, ndt)) return 0;
+    return smooth_frame_workspace(*frame, ndt);
+}
+
+__attribute__((visibility("default"))) pl_status pl_smooth_frame(const pl_frame *frame,
+                                                                 pl_dtype ndt, void *ws,
+                                                                 size_t ws_bytes,
+                                                                 hipStream_t stream) {
+    g_err[0] = 0;
+    PL_TRY(check_batch(frame, 1, ndt));
+    const pl_frame &f = *frame;
+    const size_t need = smooth_frame_workspace(f, ndt);
+    PL_TRY(check_ws(ws, ws_bytes, need));
+    const size_t P = (size_t)f.M * f.N, T = 2 * (size_t)(f.M - 1) * (f.N - 1);
+    const size_t nb = 3 * T * (ndt == PL_F32 ? 4 : 2);
+    const Range wr{ws, need};
+    const Range bufs[] = {{f.pts, 12 * P},         {f.pts_out, 12 * P},
+                          {f.normals, nb},         {f.centroids, 12 * T},
+                          {f.tri_valid, f.tri_valid ? T : 0},
+                          {f.tri_map, 4 * T},      {f.triangles, 12 * T},
+                          {f.halfedges, f.halfedges ? 12 * T : 0},
+                          {f.n_tri, 4},            {f.normals_T, nb},
+                          {f.groups, f.groups ? T : 0},
+                          {f.dominant, f.groups ? 12 * (size_t)f.n_dominant : 0}};
+    for (const Range &b : bufs)
+        if (overlap(wr, b)) {
+            set_error("the workspace overlaps a buffer of the frame");
+            return PL_ERR_ALIAS;
+        }
+    return launch_smooth_frame(f, ndt, ws, stream);
+}
+
 __attribute__((visibility("default"))) size_t pl_batch_workspace(const pl_frame *frames,
                                                                  int32_t n, pl_dtype ndt) {
     if (check_batch(frames, n, ndt)) return 0;

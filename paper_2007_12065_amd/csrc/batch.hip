@@ -147,16 +147,18 @@ __device__ __forceinline__ bool queue_tile(const QueueDev &Q, int n, int *s_star
 __global__ __launch_bounds__(kTileBlock) void k_batch_mesh_count(const BFrame *__restrict__ fr,
                                                                  QueueDev Q, int n) {
     PL_QUEUE_TILE(Q, n, t)
+    __shared__ MeshCountRowLds L;
     const BFrame &f = fr[t.x];
-    mesh_count_row(f.pts, f.N, t.y, f.codes, f.tri_valid, f.row_count);
+    mesh_count_row(f.pts, f.N, t.y, f.codes, f.tri_valid, f.row_count, L);
 }
 
 __global__ __launch_bounds__(kTileBlock) void k_batch_mesh_emit(const BFrame *__restrict__ fr,
                                                                 QueueDev Q, int n) {
     PL_QUEUE_TILE(Q, n, t)
     const BFrame &f = fr[t.x];
+    __shared__ MeshEmitRowLds L;
     mesh_emit_row(f.codes, f.row_count, f.Mq, f.N, t.y, f.tri_map, f.triangles, f.halfedges,
-                  2 * f.Mq * f.Nq, f.n_tri);
+                  2 * f.Mq * f.Nq, f.n_tri, L);
 }
 
 template <int R>

@@ -28,8 +28,9 @@ __global__ __launch_bounds__(kTileBlock) void k_mesh_count(const float *__restri
     // each XCD takes a contiguous run of segments (whole rows but for its
     // ends): the point row that two neighbouring quad rows share is then
     // fetched once into one L2
+    __shared__ MeshCountSegLds L;
     const int k = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    mesh_count_seg(pts, N, k / S, k % S, S, codes, tri_valid, seg_count);
+    mesh_count_seg(pts, N, k / S, k % S, S, codes, tri_valid, seg_count, L);
 }
 
 __global__ __launch_bounds__(kTileBlock) void k_mesh_emit(const uint8_t *__restrict__ codes,
@@ -41,8 +42,9 @@ __global__ __launch_bounds__(kTileBlock) void k_mesh_emit(const uint8_t *__restr
                                                           int32_t *__restrict__ n_tri) {
     // contiguous segments per XCD, as for the count (the twins read the
     // neighbouring rows' codes)
+    __shared__ MeshEmitSegLds L;
     const int k = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    mesh_emit_seg(codes, seg_count, Mq, N, k / S, k % S, S, tri_map, tris, he, cap, n_tri);
+    mesh_emit_seg(codes, seg_count, Mq, N, k / S, k % S, S, tri_map, tris, he, cap, n_tri, L);
 }
 
 __global__ __launch_bounds__(kTileBlock) void k_mesh_count_rows(const float *__restrict__ pts,
@@ -50,8 +52,9 @@ __global__ __launch_bounds__(kTileBlock) void k_mesh_count_rows(const float *__r
                                                                 uint8_t *__restrict__ codes,
                                                                 uint8_t *__restrict__ tri_valid,
                                                                 int *__restrict__ row_count) {
+    __shared__ MeshCountRowLds L;
     mesh_count_row(pts, N, xcd_remap((int)blockIdx.x, (int)gridDim.x), codes, tri_valid,
-                   row_count);
+                   row_count, L);
 }
 
 __global__ __launch_bounds__(kTileBlock) void k_mesh_emit_rows(const uint8_t *__restrict__ codes,
@@ -61,8 +64,9 @@ __global__ __launch_bounds__(kTileBlock) void k_mesh_emit_rows(const uint8_t *__
                                                                int32_t *__restrict__ tris,
                                                                int32_t *__restrict__ he, int cap,
                                                                int32_t *__restrict__ n_tri) {
+    __shared__ MeshEmitRowLds L;
     mesh_emit_row(codes, row_count, Mq, N, xcd_remap((int)blockIdx.x, (int)gridDim.x), tri_map,
-                  tris, he, cap, n_tri);
+                  tris, he, cap, n_tri, L);
 }
 
 // Scratch of the allocation-free entry point (pl_mesh_opc_static): the

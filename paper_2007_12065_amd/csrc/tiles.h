@@ -21,11 +21,16 @@ constexpr int kMeshChunk = 4 * kTileBlock;    // columns staged per pass
 // Validity codes of quad row u (bit 0: first triangle, bit 1: second) and the
 // row's triangle count.  All point loads of a 1024-column chunk are issued
 // before any is used; point validity is staged in LDS.
+struct MeshCountRowLds {
+    uint8_t ok[2][kMeshChunk + 1];
+};
+
 __device__ __forceinline__ void mesh_count_row(const float *__restrict__ pts, int N, int u,
                                                uint8_t *__restrict__ codes,
                                                uint8_t *__restrict__ tri_valid,
-                                               int *__restrict__ row_count) {
-    __shared__ uint8_t ok[2][kMeshChunk + 1];
+                                               int *__restrict__ row_count,
+                                               MeshCountRowLds &L) {
+    auto &ok = L.ok;
     __shared__ int red[kTileBlock / kWave];
     const int Nq = N - 1;
     const float *r0 = pts + (size_t)u * N * 3;
@@ -129,14 +134,18 @@ __device__ __forceinline__ void emit_flush(const int *stage, int32_t *__restrict
 // lane), so each of the pass's three contiguous output ranges -- its T_map
 // entries, its rows of T, its rows of HE -- is assembled in LDS and then
 // written with coalesced stores.  The last row writes |T|.
+struct MeshEmitRowLds {
+    int stage[3 * 2 * kEmitChunk];
+};
+
 __device__ __forceinline__ void mesh_emit_row(const uint8_t *__restrict__ codes,
                                               const int *__restrict__ row_count, int Mq, int N,
                                               int u, int32_t *__restrict__ tri_map,
                                               int32_t *__restrict__ tris,
                                               int32_t *__restrict__ he, int cap,
-                                              int32_t *__restrict__ n_tri) {
+                                              int32_t *__restrict__ n_tri, MeshEmitRowLds &L) {
     __shared__ int red[kTileBlock / kWave];
-    __shared__ int stage[3 * 2 * kEmitChunk];
+    int *stage = L.stage;
     const int Nq = N - 1;
     const uint8_t *cr0 = codes + (size_t)u * Nq;
     const uint8_t *crm = u > 0 ? cr0 - Nq : cr0;        // row u-1
@@ -267,11 +276,15 @@ __host__ __device__ constexpr int mesh_segments(int Nq) { return (Nq + kMeshSeg 
 
 // Validity codes of segment s of quad row u and its triangle count
 // seg_count[u S + s].
+struct MeshCountSegLds {
+    uint8_t ok[2][kMeshSeg + 1];
+};
+
 __device__ __forceinline__ void mesh_count_seg(const float *__restrict__ pts, int N, int u, int s,
                                                int S, uint8_t *__restrict__ codes,
                                                uint8_t *__restrict__ tri_valid,
-                                               int *__restrict__ seg_count) {
-    __shared__ uint8_t ok[2][kMeshSeg + 1];
+                                               int *__restrict__ seg_count, MeshCountSegLds &L) {
+    auto &ok = L.ok;
     __shared__ int red[kTileBlock / kWave];
     const int Nq = N - 1;
     const int v0 = s * kMeshSeg;
@@ -326,14 +339,18 @@ __device__ __forceinline__ void mesh_count_seg(const float *__restrict__ pts, in
 // T_map, T and HE of segment s of quad row u (the whole-row emit restricted
 // to one quad per thread; see mesh_emit_row for the twin rules).  The last
 // segment of the last row writes |T|.
+struct MeshEmitSegLds {
+    int stage[3 * 2 * kMeshSeg];
+};
+
 __device__ __forceinline__ void mesh_emit_seg(const uint8_t *__restrict__ codes,
                                               const int *__restrict__ seg_count, int Mq, int N,
                                               int u, int s, int S, int32_t *__restrict__ tri_map,
                                               int32_t *__restrict__ tris,
                                               int32_t *__restrict__ he, int cap,
-                                              int32_t *__restrict__ n_tri) {
+                                              int32_t *__restrict__ n_tri, MeshEmitSegLds &L) {
     __shared__ int red[kTileBlock / kWave];
-    __shared__ int stage[3 * 2 * kMeshSeg];
+    int *stage = L.stage;
     const int Nq = N - 1;
     const int v0 = s * kMeshSeg;
     const int ku = u * S + s;                 // this segment
