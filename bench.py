@@ -1,20 +1,29 @@
 """Benchmark of the whole OPC meshing + smoothing path on one MI355X.
 
-One step = one pass of the plain per-frame path over one 480x640 synthetic
-RGBD frame (floor, two walls, six boxes, 8% NaN holes): mesh extraction
-(Alg. 1-2), 4 Laplacian sweeps (3x3, lambda = 1), triangle normals and
-centroids, 2 bilateral sweeps (3x3 quads, sigma_length = sigma_angle = 0.1)
-and the gather onto T, all in float32.  Inputs are resident in HBM before the
-timed region; 16 frames with separate input and output buffers rotate so the
-working set (~1.1 GB) exceeds the 256 MB last-level cache.
+One step = one pass of the single-frame path (pl_smooth_frame, three
+launches) over one 480x640 synthetic RGBD frame (floor, two walls, six boxes,
+8% NaN holes): mesh extraction (Alg. 1-2), 4 Laplacian sweeps (3x3,
+lambda = 1), triangle normals and centroids, 2 bilateral sweeps (3x3 quads,
+sigma_length = sigma_angle = 0.1) and the gather onto T, all in float32.
+Inputs are resident in HBM before the timed region; 16 frames with separate
+input and output buffers rotate so the working set (~1.1 GB) exceeds the
+256 MB last-level cache.  The same frames also go through the four separate
+single-frame calls (pl_mesh_opc, pl_laplacian, pl_tri_normals, pl_bilateral),
+the baseline of the batched and served comparisons.
 
-The timed steps run the path alone on the stream; a separate pass with HIP
-events between the calls gives the per-call breakdown and the dominant
-kernel's launch time (events cost the stream a few microseconds each, so
-that pass is slower than the timed one).
+Tile shapes and fusion come from the committed tuning file
+(profiles/tune.json) unless --retune is given.  The timed steps run the path
+alone on the stream; a separate pass with HIP events between the launches
+(pl_smooth_frame_events) gives each launch's duration, from which the
+roofline of the dominant launch is computed: algorithmic bytes against the
+8 TB/s HBM peak and algorithmic VALU lane-operations against the 3.93e13/s
+non-packed FP32 issue rate (256 CUs x 64 lanes x 2.4 GHz; transcendental
+operations count four slots), the larger of the two fractions naming the
+bound.
 
-Prints one JSON line (the contract fields plus the dominant kernel's
-roofline and the FP64 oracle's CPU throughput).
+Prints one JSON line (the contract fields plus the roofline, per-workload
+records, the auxiliary kernels, the batched and served comparisons and the
+FP64 oracle's CPU throughput).
 """
 from __future__ import annotations
 
@@ -29,8 +38,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "smoothed triangles/s (Laplacian+bilateral) & %HBM peak; p99 frame latency batched vs plain"
-HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9   # non-packed FP32 issue: 3.93e13 lane-operations/s
+TUNE_FILE = os.path.join(ROOT, "profiles", "tune.json")
+
+# Algorithmic VALU lane-slots per unit of work (each floating-point operation
+# of the formulas one slot, a transcendental -- rsqrt, exp2, rcp -- four).
+#  Laplacian, per updated point and sweep, per neighbour: difference 3,
+#  squared distance 3, rsqrt 4, weight sum 1, weighted sum 3; then 1/W 4 and
+#  the update 4.
+#  Bilateral, per triangle and sweep, per neighbour: two squared differences
+#  12, exponent 2, shift 1, exp2 4, accumulation 4; then renormalisation 10.
+#  Centroid and normal of a triangle: 31.
+
+
+def lap_lane_ops(kernel):
+    return (kernel * kernel - 1) * 14 + 8
+
+
+def bil_lane_ops(kernel):
+    return 2 * (kernel * kernel - 1) * 23 + 10
+
+
+GEOM_LANE_OPS = 31
 
 
 def parse():
@@ -41,60 +71,109 @@ def parse():
     ap.add_argument("--sets", type=int, default=16, help="rotating frame buffer sets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="bound on the oracle's CPU-baseline sample (0 = skip)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also measure the 64-frame mixed batch (0 = skip)")
-    ap.add_argument("--tune-cache", default=None,
-                    help="JSON tuning cache: load it if present, else tune and write it "
-                         "(default: tune in-process, nothing written)")
-    ap.add_argument("--serving-seconds", type=float, default=6.0,
+    ap.add_argument("--per-config", type=int, default=1,
+                    help="also measure the 120x160, 64x1024 and 128x2048 workloads (0 = skip)")
+    ap.add_argument("--aux", type=int, default=1,
+                    help="also measure group assignment, the accumulator, user half-edges "
+                         "and the vertex update (0 = skip)")
+    ap.add_argument("--tune-file", default=TUNE_FILE,
+                    help="tuning file to load (default: the committed profiles/tune.json)")
+    ap.add_argument("--retune", default=None, metavar="PATH",
+                    help="tune in-process instead of loading a file, and write the result to PATH")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="measured seconds of the Poisson serving run after 1 s warm-up (0 = skip)")
+    ap.add_argument("--pool", type=int, default=64, help="served frames pre-generated per size class")
     return ap.parse_args()
 
 
-def kernel_specs(k, M, N, n_tri_mean):
-    """Per-call launch counts and algorithmic traffic / arithmetic per launch.
+def frame_counts(M, N, k, n_tri, pts_np=None):
+    """Units of work of one frame: points P, quads Q, T_FC triangles T, valid
+    triangles |T|, and the points a Laplacian sweep updates (valid pixels
+    outside the border band)."""
+    P, Q = M * N, (M - 1) * (N - 1)
+    r = k.kernel_lap // 2
+    if pts_np is not None:
+        import numpy as np
+        inner = pts_np[r:M - r, r:N - r]
+        upd = float(np.mean([int((~np.isnan(inner).any(-1)).sum())]))
+    else:
+        upd = float((M - 2 * r) * (N - 2 * r))
+    return {"P": P, "Q": Q, "T": 2 * Q, "n_tri": float(n_tri), "lap_points": upd}
 
-    Bytes are the minimal HBM traffic of one launch (each input read once,
-    each output written once).  Flops count the arithmetic of the paper's
-    formulas per output: Laplacian 17 per neighbour (difference 3, squared
-    norm 5, inverse root 1, weight sum 1, weighted sum 6, + update), bilateral
-    26 per neighbour pair (two squared differences 16, exponent 3, exp 1,
-    weighted sum 6).  A launch runs F fused sweeps (the installed tuning)."""
+
+def launch_model(kind, c, k):
+    """Algorithmic bytes and VALU lane-slots of one launch of the fused path,
+    from the work its kind bits say it carries (each input read once, each
+    output written once; see the lane-slot counts above)."""
     import paper_2007_12065_amd as pl
-    P = M * N
-    T = 2 * (M - 1) * (N - 1)
-    nb_lap = k.kernel_lap ** 2 - 1
-    nb_bil = 2 * (k.kernel_bil ** 2 - 1)
-    Fl = pl.lap_fused_sweeps(k.kernel_lap)
-    lap_launches = -(-k.iters_lap // Fl)
-    Fb = pl.pl_tune_get(pl.PL_STAGE_BILATERAL, k.kernel_bil)[2]
-    bil_launches = -(-k.iters_bil // Fb)
-    return {
-        "pl_laplacian": dict(kernel="k_laplacian", launches=lap_launches,
-                             bytes=24 * P, flops=P * (k.iters_lap / lap_launches) * (17 * nb_lap + 7)),
-        "pl_tri_normals": dict(kernel="k_tri_normals", launches=1, bytes=12 * P + 24 * T,
-                               flops=T * 30),
-        "pl_bilateral": dict(kernel="k_bilateral", launches=bil_launches,
-                             bytes=36 * T + (4 * T + 12 * n_tri_mean) / bil_launches,
-                             flops=T * (k.iters_bil / bil_launches) * (26 * nb_bil + 10)),
-        "pl_mesh_opc": dict(kernel="k_mesh_*", launches=2,
-                            bytes=(12 * P + T // 2 + 4 * T + 24 * n_tri_mean) / 2, flops=0),
-    }
+    F = (kind >> 8) & 0xff
+    P, Q, T, nt = c["P"], c["Q"], c["T"], c["n_tri"]
+    nbytes = 0.0
+    ops = 0.0
+    parts = []
+    reads_pts = False
+    if kind & pl.PL_LAUNCH_LAPLACIAN:
+        nbytes += 24 * P
+        reads_pts = True
+        ops += F * c["lap_points"] * lap_lane_ops(k.kernel_lap)
+        parts.append(f"laplacian x{F}")
+    if kind & pl.PL_LAUNCH_MESH_COUNT:
+        nbytes += (0 if reads_pts else 12 * P) + Q + T
+        parts.append("mesh count")
+    if kind & pl.PL_LAUNCH_MESH_EMIT:
+        nbytes += Q + 4 * T + 24 * nt
+        parts.append("mesh emit")
+    if kind & pl.PL_LAUNCH_BILATERAL:
+        if kind & pl.PL_LAUNCH_NORMALS:
+            nbytes += 12 * P + 24 * T          # smoothed points in; centroids, normals out
+            ops += nt * GEOM_LANE_OPS
+            parts.append("normals")
+        else:
+            nbytes += 36 * T
+        ops += F * nt * bil_lane_ops(k.kernel_bil)
+        parts.append(f"bilateral x{F}")
+    if kind & pl.PL_LAUNCH_GATHER:
+        nbytes += 4 * T + 12 * nt
+        parts.append("gather")
+    return {"work": " + ".join(parts), "bytes": nbytes, "lane_ops": ops}
 
 
-FILTER_SOURCES = ("paper_2007_12065_amd/csrc/tiles.h", "paper_2007_12065_amd/csrc/common.h",
-                  "paper_2007_12065_amd/csrc/bilateral.hip", "paper_2007_12065_amd/csrc/laplacian.hip",
-                  "paper_2007_12065_amd/csrc/normals.hip")
+def staged_bytes(c, k):
+    """The staged algorithmic bytes of the whole path (each call reading its
+    inputs and writing its outputs once, 24P per Laplacian sweep, 36T per
+    bilateral sweep): mesh 12P + T/8 + 4T + 24|T|, Laplacian, normals
+    12P + 24T, bilateral, gather 4T + 24|T|."""
+    P, T, nt = c["P"], c["T"], c["n_tri"]
+    return (12 * P + T / 8 + 4 * T + 24 * nt) + 24 * P * k.iters_lap + (12 * P + 24 * T) \
+        + 36 * T * k.iters_bil + (4 * T + 24 * nt)
+
+
+def roofline(nbytes, ops, seconds):
+    gbs = nbytes / seconds / 1e9
+    lanes = ops / seconds
+    hf, vf = gbs / HBM_PEAK_GBS, lanes / VALU_PEAK_LANE_OPS
+    if hf >= vf:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(hf, 4)}
+    else:
+        r = {"bound": "alu", "achieved": round(lanes / 1e12, 3),
+             "peak": round(VALU_PEAK_LANE_OPS / 1e12, 3), "unit": "Tlane-op/s",
+             "frac": round(vf, 4)}
+    r.update({"hbm_frac": round(hf, 4), "valu_frac": round(vf, 4)})
+    return r
+
+
+FRAME_SOURCES = ("paper_2007_12065_amd/csrc/tiles.h", "paper_2007_12065_amd/csrc/common.h",
+                 "paper_2007_12065_amd/csrc/frame.hip")
 GROUP_SOURCES = ("paper_2007_12065_amd/csrc/common.h", "paper_2007_12065_amd/csrc/groups.h",
                  "paper_2007_12065_amd/csrc/groups.hip")
-KERNEL_SOURCES = {"k_bilateral": FILTER_SOURCES, "k_group_assign": GROUP_SOURCES}
 
 
-def kernel_source_digest(files=FILTER_SOURCES):
-    """SHA-256 over the sources a kernel is built from (default: the
-    single-frame filter kernels)."""
+def kernel_source_digest(files=FRAME_SOURCES):
+    """SHA-256 over the sources a kernel is built from (default: the fused
+    single-frame path's kernels)."""
     import hashlib
     h = hashlib.sha256()
     for f in files:
@@ -103,18 +182,19 @@ def kernel_source_digest(files=FILTER_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, launches_per_call):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy of known size), or
-    None when there is none or the kernel sources changed since it was taken."""
+def measured_traffic(key, files=FRAME_SOURCES):
+    """HBM bytes per launch for `key` from the committed counter summary
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE runs, calibrated on a
+    copy of known size), or None when there is none or the kernel's sources
+    changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    r = rec.get(kernel)
-    if not r or r.get("source_digest") != kernel_source_digest(KERNEL_SOURCES.get(kernel, FILTER_SOURCES)):
+    r = rec.get(key)
+    if not r or r.get("source_digest") != kernel_source_digest(files):
         return None
     return r.get("bytes_per_launch")
 
@@ -211,7 +291,7 @@ def groups_bench(plans, k, stream, s, reps=300):
             "labels_per_s": round(n_tri / (us * 1e-6), 1),
             "bytes_per_launch": int(nbytes), "achieved_gbs": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("k_group_assign", 1),
+            "traffic": measured_traffic("k_group_assign:rgbd", GROUP_SOURCES),
             "assigned_frac": round(float(np.mean(labels != 255)), 4),
             "l_max": k.l_max, "ang_min": k.ang_min, "dominant_normals": 3,
             "cpu_oracle_labels_per_s": round(n_tri / cpu_s, 1), "cpu_oracle_threads": 1}
@@ -310,6 +390,9 @@ def vertex_update_bench(plans, stream, reps=100, iterations=1):
     us = graph_us([lambda i=i: call(i) for i in range(sets)])
     nbytes = 24 * M * N + 12 * 2 * (M - 1) * (N - 1)
     return {"kernel": "k_vertex_update", "sweeps": iterations, "launch_us": round(us, 2),
+            "parity": "unpinned: the paper cites this update (Sec. 2.3, Sec. 5.2) but prints no "
+                      "formula; the oracle restates it and the kernel matches the oracle within "
+                      "1e-5 relative",
             "points_per_s": round(M * N / (us * 1e-6), 1), "bytes_per_launch": int(nbytes),
             "achieved_gbs": round(nbytes / (us * 1e-6) / 1e9, 1),
             "hbm_frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -324,15 +407,17 @@ def angle_stats(got, ref):
     return {"p50": float(np.median(a)), "p99": float(np.percentile(a, 99)), "max": float(a.max())}
 
 
-def batched_bench(reps=20, tune_cache=None):
+def batched_bench(tuning, reps=20):
     """The 64-frame mix (16x 120x160, 24x 480x640, 16x 64x1024, 8x 128x2048):
-    plain per-frame float32 path vs one batch plan (graph replay), float32
-    and float16 normals, with the batched path's tile shapes tuned on this
-    mix (or loaded from the cache).  Angular error of a sample against the
-    FP64 oracle."""
+    the plain per-frame float32 path (the four single-frame calls per frame,
+    and the fused single-frame entry) vs one batch plan (graph replay),
+    float32 and float16 normals.  The batched path's tile shapes come from
+    `tuning` (the tuning file's batch_* entries) or are tuned on this mix.
+    Angular error against the FP64 oracle for one frame of each size."""
     import numpy as np
     import torch
 
+    import oracle
     import paper_2007_12065_amd as pl
     from synth import KINDS, batch_mix, make_frame
     dev = torch.device("cuda:0")
@@ -346,14 +431,9 @@ def batched_bench(reps=20, tune_cache=None):
                           sigma_angle=k.sigma_angle, iters_bil=k.iters_bil))
     T = sum(2 * (f.shape[0] - 1) * (f.shape[1] - 1) for f, _ in host)
     from paper_2007_12065_amd import tune
-    cached = {}
-    if tune_cache and os.path.exists(tune_cache):
-        cached = {k: v for k, v in json.load(open(tune_cache)).get(tune.arch_name(), {}).items()
-                  if k.startswith("batch_")}
-    if cached:
-        batch_tuning = {k: {"best": tuple(v["best"])} for k, v in cached.items()}
-    else:
-        batch_tuning = tune.autotune_batch(specs, cache_path=tune_cache, reps=10)
+    batch_tuning = {k: v for k, v in tuning.items() if k.startswith("batch_")}
+    if not batch_tuning:
+        batch_tuning = tune.autotune_batch(specs, cache_path=None, reps=10)
     plans = [pl.FramePlan(f.shape[0], f.shape[1], k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
                           k.sigma_length, k.sigma_angle, k.iters_bil, torch.float32, dev)
              for f, k in host]
@@ -371,46 +451,69 @@ def batched_bench(reps=20, tune_cache=None):
     def plain():
         for p, sp in zip(plans, specs):
             p.run(sp["pts"])
+
+    def plain_fused():
+        for p, sp in zip(plans, specs):
+            p.run_fused(sp["pts"])
     t_plain = timed(plain)
+    t_fused = timed(plain_fused)
     out = {"frames": len(specs), "triangles": T,
            "tuning": {name: {"tile": list(r["best"][:2]), "fuse": r["best"][2]}
                       for name, r in batch_tuning.items()},
-           "plain_f32": {"ms": round(t_plain * 1e3, 3), "triangles_per_s": T / t_plain}}
-    sample = [0, 16, 40, 56]          # one frame of each kind for the error report
+           "plain_f32": {"ms": round(t_plain * 1e3, 3), "triangles_per_s": T / t_plain,
+                         "path": "four single-frame calls per frame"},
+           "plain_fused_f32": {"ms": round(t_fused * 1e3, 3), "triangles_per_s": T / t_fused,
+                               "path": "pl_smooth_frame per frame"}}
+    sample = {"rgbd_small": 0, "rgbd": 16, "lidar": 40, "lidar128": 56}
+    refs = {}
+    for kind, i in sample.items():
+        f, k = host[i]
+        refs[kind] = oracle.pipeline(f, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
+                                     k.sigma_length, k.sigma_angle, k.iters_bil,
+                                     threads=min(16, os.cpu_count() or 1))["normals_T"]
     for name, dt in (("batched_f32", torch.float32), ("batched_f16", torch.float16)):
         b = pl.Batch(specs, dt)
         b.run()
         b.capture()
         t = timed(b.replay)
-        errs = []
-        import oracle
-        for i in sample:
-            f, k = host[i]
-            ref = oracle.pipeline(f, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil, k.sigma_length,
-                                  k.sigma_angle, k.iters_bil, threads=min(16, os.cpu_count() or 1))
+        errs = {}
+        for kind, i in sample.items():
             n = int(b.outputs[i]["n_tri"].item())
-            errs.append(angle_stats(b.outputs[i]["normals_T"][:n].float().cpu().numpy(), ref["normals_T"]))
+            errs[kind] = angle_stats(b.outputs[i]["normals_T"][:n].float().cpu().numpy(), refs[kind])
         out[name] = {"ms": round(t * 1e3, 3), "triangles_per_s": T / t, "vs_plain_f32": t_plain / t,
-                     "angle_err_rad_vs_fp64": {kk: max(e[kk] for e in errs) if kk == "max" else
-                                               float(np.median([e[kk] for e in errs])) for kk in errs[0]}}
+                     "vs_plain_fused_f32": t_fused / t, "angle_err_rad_vs_fp64": errs}
         b.close()
     return out
 
 
-def serving_bench(seconds):
+def serving_pool(pool_per_kind):
+    """The served frames: `pool_per_kind` seeded frames per size class,
+    generated in worker processes (call before the GPU is initialised)."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    from synth import KINDS, make_frame
+    jobs = [(k, 4000 + 100 * j + i) for j, k in enumerate(KINDS) for i in range(pool_per_kind)]
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        made = list(ex.map(make_frame, [a for a, _ in jobs], [b for _, b in jobs], chunksize=4))
+    host = {k: [] for k in KINDS}
+    for (k, _), f in zip(jobs, made):
+        host[k].append(f)
+    return host
+
+
+def serving_bench(seconds, host):
     """Poisson arrivals at 1500 frames/s, sizes 40% 480x640, 30% 64x1024,
     20% 128x2048, 10% 120x160, 16 GB budget, float16 normals, graph replay;
-    the same stream through the plain per-frame float32 path."""
+    the same stream through the plain per-frame float32 path.  `host` holds
+    the pre-generated frames of each class (serving_pool)."""
     import torch
 
     from paper_2007_12065_amd.serve import FrameClass, PlainServer, Server
-    from synth import KINDS, make_frame, poisson_arrivals
+    from synth import KINDS, poisson_arrivals
     classes = {k: FrameClass(k, v.M, v.N, v.kernel_lap, v.lam, v.iters_lap, v.kernel_bil,
                              v.sigma_length, v.sigma_angle, v.iters_bil)
                for k, v in KINDS.items()}
-    pool_per_kind = 4
-    host = {k: [make_frame(k, 4000 + 100 * j + i) for i in range(pool_per_kind)]
-            for j, k in enumerate(classes)}
+    pool_per_kind = min(len(v) for v in host.values())
     warm = 1.0
     times, kinds = poisson_arrivals(1500.0, warm + seconds, seed=4000)
     srv = Server(classes, host, 16 << 30, torch.float16)
@@ -418,7 +521,8 @@ def serving_bench(seconds):
     batched = srv.serve(times, kinds, warmup_s=warm)
     plain_srv = PlainServer(classes, host)
     plain = plain_srv.serve(times, kinds, warmup_s=warm)
-    out = {"rate_hz": 1500.0, "measured_s": seconds, "continuous_batching_f16": batched,
+    out = {"rate_hz": 1500.0, "measured_s": seconds, "pool_per_kind": pool_per_kind,
+           "continuous_batching_f16": batched,
            "plain_f32": plain,
            "throughput_ratio": batched.get("triangles_per_s", 0) / max(plain.get("triangles_per_s", 1), 1)}
     # capacity: the same size mix offered far above what either server
@@ -447,6 +551,98 @@ def serving_bench(seconds):
     return out
 
 
+def fused_pass(plans, frames, k, steps, warmup, stream):
+    """Time `steps` fused single-frame calls (frames rotating over the plans),
+    then a separate pass with events between the launches.  Returns the
+    frame time (s), the mean duration of each launch (s) and their kinds."""
+    import numpy as np
+    import torch
+    sets = len(plans)
+    for i in range(warmup):
+        plans[i % sets].run_fused(frames[i % sets], stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        plans[i % sets].run_fused(frames[i % sets], stream)
+    torch.cuda.synchronize()
+    frame_s = (time.perf_counter() - t0) / steps
+    kinds = plans[0].run_fused_events(frames[0], [torch.cuda.Event(enable_timing=True)
+                                                  for _ in range(17)], stream)
+    nl = len(kinds)
+    reps = max(20, min(steps, 200))
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nl + 1)] for _ in range(reps)]
+    for i in range(reps):
+        plans[i % sets].run_fused_events(frames[i % sets], evs[i], stream)
+    torch.cuda.synchronize()
+    dur = np.array([[evs[i][j].elapsed_time(evs[i][j + 1]) * 1e-3 for j in range(nl)]
+                    for i in range(reps)])
+    lat = np.array([evs[i][0].elapsed_time(evs[i][nl]) * 1e-3 for i in range(reps)])
+    return frame_s, dur.mean(axis=0), kinds, lat
+
+
+def path_record(kind_name, k, M, N, frame_s, launch_s, kinds, n_tri, pts_np, traffic_key=None):
+    """Throughput, effective bandwidth and the per-launch roofline of one
+    workload on the fused single-frame path."""
+    import paper_2007_12065_amd as pl
+    c = frame_counts(M, N, k, n_tri, pts_np)
+    launches = []
+    for j, (kind, t) in enumerate(zip(kinds, launch_s)):
+        m = launch_model(kind, c, k)
+        r = roofline(m["bytes"], m["lane_ops"], t)
+        launches.append({"launch": j + 1, "work": m["work"], "kind_bits": kind,
+                         "us": round(t * 1e6, 2), "bytes": int(m["bytes"]),
+                         "lane_ops": int(m["lane_ops"]), "bound": r["bound"],
+                         "hbm_frac": r["hbm_frac"], "valu_frac": r["valu_frac"]})
+    dom = max(range(len(kinds)), key=lambda j: launch_s[j])
+    m = launch_model(kinds[dom], c, k)
+    roof = roofline(m["bytes"], m["lane_ops"], launch_s[dom])
+    roof.update({"kernel": "k_frame_bilateral" if kinds[dom] & pl.PL_LAUNCH_BILATERAL
+                 else "k_frame_laplacian", "launch": dom + 1, "work": m["work"],
+                 "launch_us": round(launch_s[dom] * 1e6, 2), "bytes_per_launch": int(m["bytes"]),
+                 "lane_ops_per_launch": int(m["lane_ops"]),
+                 "traffic": measured_traffic(traffic_key) if traffic_key else None,
+                 "timing": "HIP events around each launch of the fused call on its stream "
+                           "(upper bounds: each event adds a few us)"})
+    staged = staged_bytes(c, k)
+    T = c["T"]
+    return {"workload": kind_name, "frame": [M, N], "triangles_per_frame": T,
+            "valid_triangles_mean": c["n_tri"], "ms_per_frame": round(frame_s * 1e3, 5),
+            "triangles_per_s": round(T / frame_s, 1),
+            "hbm_effective_gbs": round(staged / frame_s / 1e9, 1),
+            "hbm_effective_frac": round(staged / frame_s / 1e9 / HBM_PEAK_GBS, 4),
+            "staged_bytes_per_frame": int(staged),
+            "frame_valu_frac": round(sum(launch_model(kd, c, k)["lane_ops"] for kd in kinds)
+                                     / frame_s / VALU_PEAK_LANE_OPS, 4),
+            "launches": launches, "roofline": roof}
+
+
+def angle_records(kind, k, pts_np, plans_by_dtype, stream, threads):
+    """End-to-end normal angle error (p50/p99/max) of the fused path in
+    float32 and float16 normal storage against the FP64 oracle on one frame,
+    beside the yardstick: the FP64 pipeline restarted from its own smoothed
+    vertices rounded to float32 (the spread exact arithmetic shows for a
+    float32-sized perturbation)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    ref = oracle.pipeline(pts_np, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil, k.sigma_length,
+                          k.sigma_angle, k.iters_bil, threads)
+    n = len(ref["triangles"])
+    n32, c32 = oracle.tri_normals(ref["points"].astype(np.float32), threads)
+    f32 = oracle.bilateral(n32, c32, k.kernel_bil, k.sigma_length, k.sigma_angle, k.iters_bil,
+                           threads)
+    yard = angle_stats(oracle.gather(f32, ref["tri_map"], n), ref["normals_T"])
+    out = {"yardstick_fp64_on_f32_vertices": yard}
+    x = torch.from_numpy(pts_np).to(plans_by_dtype["f32"].device)
+    for name, p in plans_by_dtype.items():
+        p.run_fused(x, stream)
+        torch.cuda.synchronize()
+        assert int(p.n_tri.item()) == n
+        out[name] = angle_stats(p.normals_T[:n].float().cpu().numpy(), ref["normals_T"])
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -457,186 +653,200 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    from synth import KINDS, make_frame
+
+    # host inputs first (worker processes, before the GPU is initialised)
+    serve_host = serving_pool(args.pool) if args.serving_seconds > 0 else None
+    k = KINDS["rgbd"]
+    M, N = k.M, k.N
+    sets = args.sets
+    frames_np = [make_frame("rgbd", 1000 + i) for i in range(sets)]
+    print("[bench] inputs ready", file=sys.stderr, flush=True)
+
     import torch
 
     import paper_2007_12065_amd as pl
-    from synth import KINDS, make_frame
-
-    k = KINDS["rgbd"]
-    M, N = k.M, k.N
+    from paper_2007_12065_amd import tune
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    sets = args.sets
-    frames_np = [make_frame("rgbd", 1000 + i) for i in range(sets)]
+    threads = min(16, os.cpu_count() or 1)
     frames = [torch.from_numpy(f).to(dev) for f in frames_np]
-    plans = [pl.FramePlan(M, N, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
-                          k.sigma_length, k.sigma_angle, k.iters_bil, torch.float32, dev)
-             for _ in range(sets)]
-    stream = torch.cuda.current_stream(dev)
-    s = pl._stream(dev)
-    # tile shapes and sweep fusion for the window sizes in use (3x3 on the
-    # 480x640 frames, 5x5 on the LiDAR frames of the batched and served mixes)
-    from paper_2007_12065_amd import tune
-    lidar = torch.from_numpy(make_frame("lidar128", 7)).to(dev)
-    if args.tune_cache and os.path.exists(args.tune_cache) and tune.load_cache(args.tune_cache) > 0:
-        tuning = {name: {"best": tuple(v["best"])}
-                  for name, v in json.load(open(args.tune_cache)).get(tune.arch_name(), {}).items()}
+    mk = lambda kk, dt=torch.float32: pl.FramePlan(kk.M, kk.N, kk.kernel_lap, kk.lam, kk.iters_lap,
+                                                   kk.kernel_bil, kk.sigma_length, kk.sigma_angle,
+                                                   kk.iters_bil, dt, dev)
+    plans = [mk(k) for _ in range(sets)]
+    stream = pl._stream(dev)
+
+    # tile shapes and sweep fusion: the committed tuning file, or tuned here
+    if args.retune:
+        per = {}
+        for kind in ("rgbd", "lidar128"):
+            kk = KINDS[kind]
+            fr = frames if kind == "rgbd" else [torch.from_numpy(make_frame(kind, 7 + i)).to(dev)
+                                                for i in range(4)]
+            per[kind] = (fr, kk.kernel_lap, kk.lam, kk.iters_lap, kk.kernel_bil, kk.sigma_length,
+                         kk.sigma_angle, kk.iters_bil)
+        tune.tune_frame(list(per.values()), cache_path=args.retune)
+        from synth import batch_mix
+        specs = [dict(pts=torch.from_numpy(make_frame(kd, sd)).to(dev), kernel_lap=KINDS[kd].kernel_lap,
+                      lam=KINDS[kd].lam, iters_lap=KINDS[kd].iters_lap, kernel_bil=KINDS[kd].kernel_bil,
+                      sigma_length=KINDS[kd].sigma_length, sigma_angle=KINDS[kd].sigma_angle,
+                      iters_bil=KINDS[kd].iters_bil) for kd, sd in batch_mix()]
+        tune.autotune_batch(specs, cache_path=args.retune, reps=10)
+        del specs
+        tune_path = args.retune
     else:
-        tuning = tune.autotune([(frames[0], k.kernel_lap, k.iters_lap, k.kernel_bil, k.iters_bil),
-                                (lidar, 5, 4, 5, 3)], cache_path=args.tune_cache, reps=20)
+        tune_path = args.tune_file
+        if tune.load_cache(tune_path) == 0:
+            print(f"bench.py: no tuning for {tune.arch_name()} in {tune_path}; run with --retune PATH",
+                  file=sys.stderr)
+            sys.exit(3)
+    tuning = json.load(open(tune_path)).get(tune.arch_name(), {})
     print(f"[bench] {sets} frame sets ready; warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
 
+    # the headline: the fused single-frame path, timed alone on the stream
+    K = args.steps
+    frame_s, launch_s, kinds, lat = fused_pass(plans, frames, k, K, args.warmup, stream)
+    n_tri = [int(p.n_tri.item()) for p in plans]
+    rec = path_record("rgbd", k, M, N, frame_s, launch_s, kinds, float(np.mean(n_tri)),
+                      frames_np[0], traffic_key="rgbd:dominant")
+    T = rec["triangles_per_frame"]
+
+    # the four single-frame calls (the plain baseline of the batched and
+    # served comparisons), uninstrumented, then with events between calls
     calls = ["pl_mesh_opc", "pl_laplacian", "pl_tri_normals", "pl_bilateral"]
 
-    def step(i, ev=None):
+    def four(i, ev=None):
         p, x = plans[i % sets], frames[i % sets]
+        for j, fn in enumerate((lambda: p.run_mesh(x, stream), lambda: p.run_laplacian(x, stream),
+                                lambda: p.run_normals(stream), lambda: p.run_bilateral(stream))):
+            if ev is not None:
+                ev[j].record()
+            fn()
         if ev is not None:
-            ev[0].record(stream)
-        p.run_mesh(x, s)
-        if ev is not None:
-            ev[1].record(stream)
-        p.run_laplacian(x, s)
-        if ev is not None:
-            ev[2].record(stream)
-        p.run_normals(s)
-        if ev is not None:
-            ev[3].record(stream)
-        p.run_bilateral(s)
-        if ev is not None:
-            ev[4].record(stream)
-
+            ev[4].record()
     for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize(dev)
-
-    K = args.steps
-    # the timed steps: the whole path, nothing else on the stream
-    torch.cuda.synchronize(dev)
+        four(i)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
-        step(i)
-    torch.cuda.synchronize(dev)
-    elapsed = time.perf_counter() - t0
-
-    # the paper's rate: smoothing only (Laplacian, normals, bilateral with the
-    # gather onto T from the mesh of the steps above), again uninstrumented
-    torch.cuda.synchronize(dev)
+        four(i)
+    torch.cuda.synchronize()
+    four_s = (time.perf_counter() - t0) / K
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
         p, x = plans[i % sets], frames[i % sets]
-        p.run_laplacian(x, s)
-        p.run_normals(s)
-        p.run_bilateral(s)
-    torch.cuda.synchronize(dev)
-    smooth_elapsed = time.perf_counter() - t0
-
-    # a separate instrumented pass for the per-call breakdown and the roofline:
-    # an event between calls costs the stream about 4 us per boundary, so these
-    # durations are upper bounds and are not used for `value`
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
-    torch.cuda.synchronize(dev)
-    for i in range(K):
-        step(i, evs[i])
-    torch.cuda.synchronize(dev)
-
-    per_call = {c: np.array([evs[i][j].elapsed_time(evs[i][j + 1]) * 1e3 for i in range(K)])
+        p.run_laplacian(x, stream)
+        p.run_normals(stream)
+        p.run_bilateral(stream)
+    torch.cuda.synchronize()
+    smooth_s = (time.perf_counter() - t0) / K
+    reps = min(K, 200)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
+    for i in range(reps):
+        four(i, evs[i])
+    torch.cuda.synchronize()
+    per_call = {c: float(np.median([evs[i][j].elapsed_time(evs[i][j + 1]) * 1e3 for i in range(reps)]))
                 for j, c in enumerate(calls)}
-    lat = np.array([evs[i][0].elapsed_time(evs[i][4]) * 1e3 for i in range(K)])
-    n_tri = [int(p.n_tri.item()) for p in plans]
-    T = 2 * (M - 1) * (N - 1)
-    ms = elapsed / K * 1e3
-    value = T / (elapsed / K)
-
-    specs = kernel_specs(k, M, N, float(np.mean(n_tri)))
-    launch_us = {c: float(per_call[c].mean() / specs[c]["launches"]) for c in calls}
-    dom = max(("pl_laplacian", "pl_tri_normals", "pl_bilateral"), key=lambda c: per_call[c].mean())
-    sp = specs[dom]
-    t_launch = launch_us[dom] * 1e-6
-    gbs = sp["bytes"] / t_launch / 1e9
-    tflops = sp["flops"] / t_launch / 1e12
-    byte_frac = gbs / HBM_PEAK_GBS
-    alu_frac = tflops / FP32_VECTOR_PEAK_TFLOPS
-    if byte_frac >= alu_frac:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(byte_frac, 4)}
-    else:
-        roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
-    roof.update({"kernel": sp["kernel"], "launch_us": round(launch_us[dom], 2),
-                 "bytes_per_launch": int(sp["bytes"]), "flops_per_launch": int(sp["flops"]),
-                 "hbm_frac": round(byte_frac, 4),
-                 "traffic": measured_traffic(sp["kernel"], sp["launches"]),
-                 "peak_note": "published fp32 vector peak (packed); this code is built without "
-                              "packed FP32, whose ceiling is half (78.6 TFLOP/s)"})
 
     # measured HBM ceiling: a 256 MiB device-to-device copy (read + write)
     ca = torch.empty(64 << 20, dtype=torch.float32, device=dev)
     cb = torch.empty_like(ca)
     cb.copy_(ca)
     c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
+    c0.record()
     for _ in range(5):
         cb.copy_(ca)
-    c1.record(stream)
-    torch.cuda.synchronize(dev)
+    c1.record()
+    torch.cuda.synchronize()
     copy_gbs = 2 * ca.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del ca, cb
 
-    if args.copy_probe:
-        # plain copy of known size for counter calibration: 256 MiB read and
-        # 256 MiB written by one device-to-device copy kernel, larger than L2
-        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        b_ = torch.empty_like(a)
-        torch.cuda.synchronize(dev)
-        b_.copy_(a)
-        torch.cuda.synchronize(dev)
-        del a, b_
-
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "triangles/s", "n_gpus": 1,
-        "steps": K, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "metric": METRIC, "value": round(T / frame_s, 1), "unit": "triangles/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(frame_s * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "rgbd 480x640 plain per-frame path (mesh + Laplacian 3x3 x4 + "
-                               "normals + bilateral 3x3 x2 + gather), float32 normals",
-                   "frame": [M, N], "triangles_per_frame": T, "valid_triangles_mean": float(np.mean(n_tri)),
-                   "frame_sets": sets},
-        "stage_us": {c: round(float(np.median(per_call[c])), 2) for c in calls},
-        "stage_note": "medians per call from a separate event-instrumented pass (each event "
-                      "boundary adds about 4 us to the stream); value, ms_per_step and the "
-                      "smoothing rate come from uninstrumented passes",
-        "smoothing_triangles_per_s": round(T / (smooth_elapsed / K), 1),
-        "mesh_us": round(float(np.median(per_call["pl_mesh_opc"])), 2),
+        "config": {"workload": "rgbd 480x640 single-frame path (pl_smooth_frame: mesh + Laplacian "
+                               "3x3 x4 + normals + bilateral 3x3 x2 + gather), float32 normals",
+                   "frame": [M, N], "triangles_per_frame": T,
+                   "valid_triangles_mean": float(np.mean(n_tri)), "frame_sets": sets,
+                   "tuning_file": os.path.relpath(tune_path, ROOT)},
+        "roofline": rec["roofline"],
+        "launches": rec["launches"],
+        "hbm_effective_gbs": rec["hbm_effective_gbs"],
+        "hbm_effective_frac": rec["hbm_effective_frac"],
+        "staged_bytes_per_frame": rec["staged_bytes_per_frame"],
+        "frame_valu_frac": rec["frame_valu_frac"],
         "hbm_copy_ceiling_gbs": round(copy_gbs, 1),
-        "instrumented_frame_us": {"p50": round(float(np.median(lat)), 2),
-                             "p99": round(float(np.percentile(lat, 99)), 2)},
-        "hbm_effective_gbs": round(sum(specs[c]["bytes"] * specs[c]["launches"] for c in calls)
-                                   / (elapsed / K) / 1e9, 1),
-        "roofline": roof,
+        "instrumented_frame_us": {"p50": round(float(np.median(lat)) * 1e6, 2),
+                                  "p99": round(float(np.percentile(lat, 99)) * 1e6, 2)},
+        "four_call_path": {"ms_per_frame": round(four_s * 1e3, 5),
+                           "triangles_per_s": round(T / four_s, 1),
+                           "smoothing_only_triangles_per_s": round(T / smooth_s, 1),
+                           "call_us_instrumented": {c: round(v, 2) for c, v in per_call.items()},
+                           "note": "medians per call from a separate event-instrumented pass"},
         "tuning": {name: {"tile": list(r["best"][:2]), "fuse": r["best"][2]}
                    for name, r in tuning.items()},
     }
-    print("[bench] group assignment", file=sys.stderr, flush=True)
-    out["groups"] = groups_bench(plans, k, stream, s)
-    print("[bench] gaussian accumulator", file=sys.stderr, flush=True)
-    out["gaussian_accumulator"] = ga_bench(plans, stream)
-    # the paper integrates a sample of about 12% of the normals (sample_pct)
-    out["gaussian_accumulator_sampled"] = ga_bench(plans, stream, stride=8)
-    print("[bench] user-mesh half-edges", file=sys.stderr, flush=True)
-    out["user_halfedges"] = user_halfedges_bench(plans, stream)
-    print("[bench] vertex update", file=sys.stderr, flush=True)
-    out["vertex_update"] = vertex_update_bench(plans, stream)
+    print(f"[bench] fused frame {frame_s * 1e6:.2f} us, four calls {four_s * 1e6:.2f} us",
+          file=sys.stderr, flush=True)
+
+    if args.per_config:
+        print("[bench] per-workload records", file=sys.stderr, flush=True)
+        per = {}
+        for name, kind in (("c0_rgbd_120x160", "rgbd_small"), ("c1_rgbd_480x640", "rgbd"),
+                           ("c2_lidar_64x1024", "lidar"), ("lidar_128x2048", "lidar128")):
+            kk = KINDS[kind]
+            if kind == "rgbd":
+                r = {kk2: v for kk2, v in rec.items() if kk2 != "launches"}
+                fnp = frames_np[0]
+            else:
+                fr_np = [make_frame(kind, 1000 * {"rgbd_small": 0, "lidar": 2}.get(kind, 5) + i)
+                         for i in range(sets)]
+                fr = [torch.from_numpy(f).to(dev) for f in fr_np]
+                pp = [mk(kk) for _ in range(sets)]
+                fs, ls, kd, _ = fused_pass(pp, fr, kk, K, args.warmup, stream)
+                nt = float(np.mean([int(p.n_tri.item()) for p in pp]))
+                r = path_record(kind, kk, kk.M, kk.N, fs, ls, kd, nt, fr_np[0],
+                                traffic_key=f"{kind}:dominant")
+                fnp = fr_np[0]
+                del fr, pp
+            r["angle_err_rad_vs_fp64"] = angle_records(kind, kk, fnp,
+                                                       {"f32": mk(kk), "f16": mk(kk, torch.float16)},
+                                                       stream, threads)
+            per[name] = r
+        out["per_config"] = per
+    if args.aux:
+        print("[bench] group assignment", file=sys.stderr, flush=True)
+        for p, x in zip(plans, frames):
+            p.run(x)          # T_FC normals for the vertex update
+        torch.cuda.synchronize()
+        out["groups"] = groups_bench(plans, k, stream, stream)
+        print("[bench] gaussian accumulator", file=sys.stderr, flush=True)
+        out["gaussian_accumulator"] = ga_bench(plans, stream)
+        # the paper integrates a sample of about 12% of the normals (sample_pct)
+        out["gaussian_accumulator_sampled"] = ga_bench(plans, stream, stride=8)
+        print("[bench] user-mesh half-edges", file=sys.stderr, flush=True)
+        out["user_halfedges"] = user_halfedges_bench(plans, stream)
+        print("[bench] vertex update", file=sys.stderr, flush=True)
+        out["vertex_update"] = vertex_update_bench(plans, stream)
     if args.batched:
         print("[bench] batched 64-frame mix", file=sys.stderr, flush=True)
-        out["batched"] = batched_bench(tune_cache=args.tune_cache)
+        out["batched"] = batched_bench(tuning)
     if args.serving_seconds > 0:
         print("[bench] serving stream", file=sys.stderr, flush=True)
-        out["serving"] = serving_bench(args.serving_seconds)
+        del plans, frames
+        torch.cuda.empty_cache()
+        out["serving"] = serving_bench(args.serving_seconds, serve_host)
     if args.cpu_seconds > 0:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(frames_np, k, args.cpu_seconds)
-        out["cpu_baseline_1thread"] = cpu_baseline(frames_np, k, max(2.0, args.cpu_seconds / 2), threads=1)
+        out["cpu_baseline_1thread"] = cpu_baseline(frames_np, k, max(2.0, args.cpu_seconds / 2),
+                                                   threads=1)
     print(json.dumps(out), flush=True)
 
 

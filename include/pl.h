@@ -496,6 +496,33 @@ pl_status pl_smooth_frame(const pl_frame *frame, pl_dtype ndt, void *ws, size_t 
                           hipStream_t stream);
 
 /*
+ * Measurement form of pl_smooth_frame, for profilers and benchmarks: the
+ * same work on `stream`, with events[0] recorded before the first launch and
+ * events[k] after launch k (as many as n_events allows; the events are
+ * created by the caller, hipEventCreate), and kinds[k-1] (HOST array of
+ * n_kinds entries, may be NULL) describing launch k: PL_LAUNCH_* bits of the
+ * work it carries and, in bits 8..15, the number of filter sweeps it fuses.
+ * *n_launches (HOST, may be NULL) receives the number of launches.  A frame
+ * meshed by whole rows reports pl_mesh_opc's two launches as one count and
+ * one emit launch.  Recording events costs the stream a few microseconds
+ * each, so the per-launch durations are upper bounds.
+ * Errors: those of pl_smooth_frame; PL_ERR_ARG for a negative count or a
+ * positive count with a NULL array.
+ */
+enum {
+    PL_LAUNCH_LAPLACIAN = 1,     /* Laplacian sweeps over point tiles       */
+    PL_LAUNCH_BILATERAL = 2,     /* bilateral sweeps over quad tiles        */
+    PL_LAUNCH_NORMALS = 4,       /* centroids and normals from the points  */
+    PL_LAUNCH_GATHER = 8,        /* filtered normals gathered onto T       */
+    PL_LAUNCH_MESH_COUNT = 16,   /* validity codes and counts (a1)         */
+    PL_LAUNCH_MESH_EMIT = 32,    /* T_map, T, HE (a2, a3)                  */
+    PL_LAUNCH_GROUPS = 64        /* group assignment (Alg. 4)              */
+};
+pl_status pl_smooth_frame_events(const pl_frame *frame, pl_dtype ndt, void *ws, size_t ws_bytes,
+                                 hipEvent_t *events, int32_t n_events, int32_t *kinds,
+                                 int32_t n_kinds, int32_t *n_launches, hipStream_t stream);
+
+/*
  * One-shot form for callers that run a frame list once: pl_batch_create,
  * pl_batch_run over all frames, pl_batch_destroy.  `ws` holds
  * pl_batch_workspace(frames, n, ndt) bytes and must stay allocated and

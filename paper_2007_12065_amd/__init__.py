@@ -85,6 +85,9 @@ _lib.pl_smooth_frame_workspace.argtypes = [ctypes.POINTER(PLFrame), _i32]
 _lib.pl_smooth_frame_workspace.restype = _sz
 _lib.pl_smooth_frame.argtypes = [ctypes.POINTER(PLFrame), _i32, _vp, _sz, _vp]
 _lib.pl_smooth_frame.restype = _i32
+_lib.pl_smooth_frame_events.argtypes = [ctypes.POINTER(PLFrame), _i32, _vp, _sz, _vp, _i32, _vp,
+                                        _i32, ctypes.POINTER(_i32), _vp]
+_lib.pl_smooth_frame_events.restype = _i32
 _lib.pl_smooth_batch.argtypes = [_vp, _i32, _i32, _vp, _sz, _vp]
 _lib.pl_smooth_batch.restype = _i32
 _lib.pl_batch_destroy.argtypes = [_vp]
@@ -125,7 +128,8 @@ EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc"
            "pl_bilateral_workspace", "pl_bilateral", "pl_tune_get", "pl_tune_set",
            "pl_batch_workspace", "pl_batch_create", "pl_batch_run", "pl_batch_capture",
            "pl_batch_replay", "pl_batch_capture_bounded", "pl_batch_replay_bounded",
-           "pl_batch_destroy", "pl_smooth_batch", "pl_smooth_frame_workspace", "pl_smooth_frame", "pl_group_assign", "pl_ga_workspace",
+           "pl_batch_destroy", "pl_smooth_batch", "pl_smooth_frame_workspace", "pl_smooth_frame", "pl_smooth_frame_events",
+           "pl_group_assign", "pl_ga_workspace",
            "pl_ga_workspace_cells", "pl_ga_create", "pl_ga_create_cells", "pl_ga_cell_count",
            "pl_ga_cells", "pl_ga_integrate", "pl_ga_destroy", "pl_user_halfedges_workspace",
            "pl_user_halfedges", "pl_vertex_update_workspace", "pl_vertex_update"]
@@ -566,6 +570,24 @@ class FramePlan:
             self._frame = f
         return self._frame
 
+    def run_fused_events(self, pts: torch.Tensor, events: list, s=None) -> list:
+        """run_fused with the torch.cuda.Event list `events` (enable_timing)
+        recorded before the first launch and after each launch; returns the
+        launches' kinds (PL_LAUNCH_* bits, fused sweeps in bits 8..15)."""
+        f = self._fused_frame(pts)
+        f.pts = pts.data_ptr()
+        s = _stream(self.device) if s is None else s
+        for e in events:          # torch creates an event at its first record
+            if not e.cuda_event:
+                e.record()
+        ev = (_vp * len(events))(*[e.cuda_event for e in events])
+        kinds = (_i32 * 16)()
+        n = _i32()
+        _check(_lib.pl_smooth_frame_events(ctypes.byref(f), self.ndt, _ptr(self.ws_frame),
+                                           self._ws_frame_n, ev, len(events), kinds, 16,
+                                           ctypes.byref(n), s), "pl_smooth_frame_events")
+        return [int(kinds[i]) for i in range(min(n.value, 16))]
+
     def run_fused(self, pts: torch.Tensor, s=None) -> None:
         """The same outputs as run() (except the unfiltered normals, which
         stay internal) through pl_smooth_frame: three to a few launches
@@ -575,6 +597,10 @@ class FramePlan:
         s = _stream(self.device) if s is None else s
         _check(_lib.pl_smooth_frame(ctypes.byref(f), self.ndt, _ptr(self.ws_frame),
                                     self._ws_frame_n, s), "pl_smooth_frame")
+
+
+PL_LAUNCH_LAPLACIAN, PL_LAUNCH_BILATERAL, PL_LAUNCH_NORMALS, PL_LAUNCH_GATHER = 1, 2, 4, 8
+PL_LAUNCH_MESH_COUNT, PL_LAUNCH_MESH_EMIT, PL_LAUNCH_GROUPS = 16, 32, 64
 
 
 def pl_tune_get(stage: int, kernel: int) -> tuple[int, int, int]:

@@ -446,20 +446,9 @@ pl_status check_batch(const pl_frame *frames, int32_t n, pl_dtype ndt) {
     return PL_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-__attribute__((visibility("default"))) size_t pl_smooth_frame_workspace(const pl_frame *frame,
-                                                                        pl_dtype ndt) {
-    if (check_batch(frame, 1, ndt)) return 0;
-    return smooth_frame_workspace(*frame, ndt);
-}
-
-__attribute__((visibility("default"))) pl_status pl_smooth_frame(const pl_frame *frame,
-                                                                 pl_dtype ndt, void *ws,
-                                                                 size_t ws_bytes,
-                                                                 hipStream_t stream) {
+pl_status smooth_frame_checked(const pl_frame *frame, pl_dtype ndt, void *ws, size_t ws_bytes,
+                               hipStream_t stream, hipEvent_t *events, int32_t n_events,
+                               int32_t *kinds, int32_t n_kinds, int32_t *n_launches) {
     g_err[0] = 0;
     PL_TRY(check_batch(frame, 1, ndt));
     const pl_frame &f = *frame;
@@ -481,7 +470,38 @@ __attribute__((visibility("default"))) pl_status pl_smooth_frame(const pl_frame 
             set_error("the workspace overlaps a buffer of the frame");
             return PL_ERR_ALIAS;
         }
-    return launch_smooth_frame(f, ndt, ws, stream);
+    return launch_smooth_frame(f, ndt, ws, stream, events, n_events, kinds, n_kinds, n_launches);
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) size_t pl_smooth_frame_workspace(const pl_frame *frame,
+                                                                        pl_dtype ndt) {
+    if (check_batch(frame, 1, ndt)) return 0;
+    return smooth_frame_workspace(*frame, ndt);
+}
+
+__attribute__((visibility("default"))) pl_status pl_smooth_frame(const pl_frame *frame,
+                                                                 pl_dtype ndt, void *ws,
+                                                                 size_t ws_bytes,
+                                                                 hipStream_t stream) {
+    return smooth_frame_checked(frame, ndt, ws, ws_bytes, stream, nullptr, 0, nullptr, 0,
+                                nullptr);
+}
+
+__attribute__((visibility("default"))) pl_status pl_smooth_frame_events(
+    const pl_frame *frame, pl_dtype ndt, void *ws, size_t ws_bytes, hipEvent_t *events,
+    int32_t n_events, int32_t *kinds, int32_t n_kinds, int32_t *n_launches,
+    hipStream_t stream) {
+    if (n_events < 0 || n_kinds < 0 || (n_events > 0 && !events) || (n_kinds > 0 && !kinds)) {
+        g_err[0] = 0;
+        set_error("events / kinds: a positive count needs an array");
+        return PL_ERR_ARG;
+    }
+    return smooth_frame_checked(frame, ndt, ws, ws_bytes, stream, events, n_events, kinds,
+                                n_kinds, n_launches);
 }
 
 __attribute__((visibility("default"))) size_t pl_batch_workspace(const pl_frame *frames,

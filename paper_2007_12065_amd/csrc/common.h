@@ -153,7 +153,10 @@ int group_assign_blocks(int cap);
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t smooth_frame_workspace(const pl_frame &f, pl_dtype ndt);
-pl_status launch_smooth_frame(const pl_frame &f, pl_dtype ndt, void *ws, hipStream_t s);
+pl_status launch_smooth_frame(const pl_frame &f, pl_dtype ndt, void *ws, hipStream_t s,
+                              hipEvent_t *events = nullptr, int n_events = 0,
+                              int32_t *kinds = nullptr, int n_kinds = 0,
+                              int32_t *n_launches = nullptr);
 
 size_t batch_workspace(const pl_frame *frames, int n, pl_dtype ndt);
 pl_status batch_create(const pl_frame *frames, int n, pl_dtype ndt, void *ws, hipStream_t s,

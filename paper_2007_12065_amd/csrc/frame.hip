@@ -112,6 +112,33 @@ __global__ __launch_bounds__(kTileBlock) void k_frame_mesh_emit(MeshJob mj) {
     if (g >= 0) mesh_job<kMeshEmit>(mj, g, lds);
 }
 
+// Optional record of the launches (pl_smooth_frame_events): an event before
+// the first launch and after each one, and what each launch carried.
+struct LaunchLog {
+    hipEvent_t *ev;
+    int n_ev;
+    int32_t *kinds;
+    int n_kinds;
+    int n;
+};
+
+pl_status log_start(LaunchLog *log, hipStream_t s) {
+    if (!log || log->n_ev < 1) return PL_OK;
+    return hip_check(hipEventRecord(log->ev[0], s), "hipEventRecord");
+}
+
+pl_status log_launch(LaunchLog *log, int32_t kind, hipStream_t s) {
+    if (!log) return PL_OK;
+    if (log->n < log->n_kinds && log->kinds) log->kinds[log->n] = kind;
+    ++log->n;
+    if (log->n < log->n_ev) return hip_check(hipEventRecord(log->ev[log->n], s), "hipEventRecord");
+    return PL_OK;
+}
+
+int mesh_bits(int kind) {
+    return kind == kMeshCount ? PL_LAUNCH_MESH_COUNT : kind == kMeshEmit ? PL_LAUNCH_MESH_EMIT : 0;
+}
+
 size_t mesh_lds(int kind) {
     if (kind == kMeshCount) return sizeof(MeshCountSegLds);
     if (kind == kMeshEmit) return sizeof(MeshEmitSegLds);
@@ -185,7 +212,7 @@ pl_status emit_launch(const MeshJob &mj, hipStream_t s) {
 }
 
 template <typename NT>
-pl_status run(const pl_frame &f, void *ws, hipStream_t s) {
+pl_status run(const pl_frame &f, void *ws, hipStream_t s, LaunchLog *log) {
     const int M = f.M, N = f.N, Mq = M - 1, Nq = N - 1;
     const size_t P = (size_t)M * N, Q = (size_t)Mq * Nq, T = 2 * Q;
     char *w = static_cast<char *>(ws);
@@ -208,10 +235,14 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s) {
     // frames meshed by whole rows: pl_mesh_opc's launches first, and no
     // mesh work in the filter launches
     const bool rows = (long)Mq * mj.S > kMeshSegMax;
-    if (rows)
+    if (pl_status st = log_start(log, s)) return st;
+    if (rows) {
         if (pl_status st = launch_mesh(f.pts, M, N, f.tri_valid, f.tri_map, f.triangles,
                                        f.halfedges, (int)T, f.n_tri, ws, s))
             return st;
+        if (pl_status st = log_launch(log, PL_LAUNCH_MESH_COUNT, s)) return st;
+        if (pl_status st = log_launch(log, PL_LAUNCH_MESH_EMIT, s)) return st;
+    }
     w += mesh_workspace(M, N);
     float *lap_tmp = f.iters_lap > 1 ? reinterpret_cast<float *>(w) : nullptr;
     w += f.iters_lap > 1 ? align_up(12 * P, 256) : 0;
@@ -240,6 +271,8 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s) {
         default: st = lap_dispatch<4>(kind, cur, dst, M, N, f.lambda, F, cl, mj, s); break;
         }
         if (st) return st;
+        if (pl_status e = log_launch(log, PL_LAUNCH_LAPLACIAN | mesh_bits(kind) | (F << 8), s))
+            return e;
         cur = dst;
     }
 
@@ -255,8 +288,10 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s) {
         left -= F;
         const bool last = l == Lb - 1;
         NT *dst = ((Lb - 1 - l) % 2 == 0) ? nout : bil_tmp;             // last lands in normals
-        if (last && emit_alone)
+        if (last && emit_alone) {
             if (pl_status st = emit_launch(mj, s)) return st;
+            if (pl_status st = log_launch(log, PL_LAUNCH_MESH_EMIT, s)) return st;
+        }
         const int kind = (!rows && Ll + l == 1 && !emit_alone) ? kMeshEmit : kMeshNone;
         const int32_t *tm = last ? f.tri_map : nullptr;
         pl_status st;
@@ -267,13 +302,20 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s) {
         default: st = bil_dispatch<4, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, s); break;
         }
         if (st) return st;
+        const int32_t what = PL_LAUNCH_BILATERAL | (l == 0 ? PL_LAUNCH_NORMALS : 0) |
+                             (last ? PL_LAUNCH_GATHER : 0) | mesh_bits(kind) | (F << 8);
+        if (pl_status e = log_launch(log, what, s)) return e;
         ncur = dst;
     }
 
-    if (f.groups)
-        return launch_group_assign(f.pts_out, (int)P, f.triangles, f.normals_T,
-                                   sizeof(NT) == 4 ? PL_F32 : PL_F16, f.n_tri, (int)T,
-                                   f.dominant, f.n_dominant, f.l_max, f.ang_min, f.groups, s);
+    if (f.groups) {
+        if (pl_status st = launch_group_assign(f.pts_out, (int)P, f.triangles, f.normals_T,
+                                               sizeof(NT) == 4 ? PL_F32 : PL_F16, f.n_tri,
+                                               (int)T, f.dominant, f.n_dominant, f.l_max,
+                                               f.ang_min, f.groups, s))
+            return st;
+        return log_launch(log, PL_LAUNCH_GROUPS, s);
+    }
     return PL_OK;
 }
 
@@ -285,8 +327,15 @@ size_t smooth_frame_workspace(const pl_frame &f, pl_dtype ndt) {
            (f.iters_bil > 1 ? align_up(T * 3 * (ndt == PL_F32 ? 4 : 2), 256) : 0);
 }
 
-pl_status launch_smooth_frame(const pl_frame &f, pl_dtype ndt, void *ws, hipStream_t s) {
-    return ndt == PL_F32 ? run<float>(f, ws, s) : run<__half>(f, ws, s);
+pl_status launch_smooth_frame(const pl_frame &f, pl_dtype ndt, void *ws, hipStream_t s,
+                              hipEvent_t *events, int n_events, int32_t *kinds, int n_kinds,
+                              int32_t *n_launches) {
+    LaunchLog log{events, n_events, kinds, n_kinds, 0};
+    LaunchLog *lp = (events && n_events > 0) || (kinds && n_kinds > 0) || n_launches ? &log
+                                                                                      : nullptr;
+    const pl_status st = ndt == PL_F32 ? run<float>(f, ws, s, lp) : run<__half>(f, ws, s, lp);
+    if (n_launches) *n_launches = log.n;
+    return st;
 }
 
 }  // namespace pl

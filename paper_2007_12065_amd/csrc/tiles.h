@@ -683,8 +683,13 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // the sums and the squared norm of Eq. 6 finite for windows up to 9 x 9
 // (160 neighbours).  If the total still drops below 2^-60 (every neighbour
 // far beyond the quad's own pair), that triangle is recomputed with every
-// exponent shifted by the smallest one, which puts the largest term at 1.
-// Only the lanes that need it take it.
+// exponent shifted by the smallest one, which puts the largest term at 1:
+// one more pass in the same order, the shift lowered as smaller exponents
+// come and the running sum rescaled with it.  A wave takes that pass if any
+// of its lanes needs it (isolated triangles: a few per thousand on the
+// LiDAR frames, which put one in about a tenth of the waves), so it has the
+// main pass's shape: one displacement's loads together, both triangles at
+// once.
 //
 // Summation order.  The window's displacements split into D+ (dy = 0 and
 // dx > 0, or dy > 0) and their negatives; a triangle sums its terms in a
@@ -763,35 +768,49 @@ __device__ __forceinline__ void bil_dplus(int i, int &dy, int &dx) {
 }
 template <int R> constexpr int bil_ndplus() { return 2 * R * R + 2 * R; }
 
+// s += 2^(m - e) n with the shift m lowered to e when e is smaller: the
+// running sum is rescaled by 2^(m_new - m_old) first, so that at the end the
+// shift is the smallest exponent seen and the largest term is 1.  m starts at
+// a large finite value (the first finite e rescales an empty sum by 0); a
+// missing neighbour (e = +inf) adds 2^-inf = 0.
+constexpr float kBilOnlineStart = 1e30f;
+
+__device__ __forceinline__ void bil_add_online(BilAcc &s, float &m, float e, const float4 n) {
+    const float mn = fminf(m, e);
+    const float f = __builtin_amdgcn_exp2f(mn - m);
+    const float w = __builtin_amdgcn_exp2f(mn - e);
+    s.w = fmaf(s.w, f, w);
+    s.x = fmaf(w, n.x, s.x * f);
+    s.y = fmaf(w, n.y, s.y * f);
+    s.z = fmaf(w, n.z, s.z * f);
+    m = mn;
+}
+
+// Both triangles' sums in the main pass's order, each shifted by its own
+// smallest exponent (one pass, online): the fallback when a sum underflows.
 template <int R>
-__device__ __forceinline__ BilAcc bil_shifted_sum(const BilOwn o, const float4 *sc,
-                                                  const float4 *sn, int a0, int pitch,
-                                                  int plane) {
-    const float inf = __builtin_inff();
-    float m = inf;
+__device__ __forceinline__ void bil_online_sums(const BilOwn &o0, const BilOwn &o1,
+                                                const float4 *sc, const float4 *sn, int a,
+                                                int pitch, int plane, BilAcc &s0, BilAcc &s1) {
+    s0 = BilAcc{0.f, 0.f, 0.f, 0.f};
+    s1 = s0;
+    float m0 = kBilOnlineStart, m1 = kBilOnlineStart;
 #pragma unroll 1
-    for (int dy = -R; dy <= R; ++dy)
-#pragma unroll 1
-        for (int dx = -R; dx <= R; ++dx) {
-            if (dy == 0 && dx == 0) continue;
+    for (int i = 0; i < bil_ndplus<R>(); ++i) {
+        int dy, dx;
+        bil_dplus<R>(i, dy, dx);
+        const int off = dy * pitch + dx;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int b = side == 0 ? a + off : a - off;
+#pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
-                const int b = a0 + dy * pitch + dx + kk * plane;
-                m = fminf(m, bil_pair_e(o, sc[b], sn[b]));
+                const float4 c = sc[b + kk * plane], n = sn[b + kk * plane];
+                bil_add_online(s0, m0, bil_pair_e(o0, c, n), n);
+                bil_add_online(s1, m1, bil_pair_e(o1, c, n), n);
             }
         }
-    BilAcc s{0.f, 0.f, 0.f, 0.f};
-    if (!(m < inf)) return s;               // no usable neighbour
-#pragma unroll 1
-    for (int dy = -R; dy <= R; ++dy)
-#pragma unroll 1
-        for (int dx = -R; dx <= R; ++dx) {
-            if (dy == 0 && dx == 0) continue;
-            for (int kk = 0; kk < 2; ++kk) {
-                const int b = a0 + dy * pitch + dx + kk * plane;
-                bil_add(s, m, bil_pair_e(o, sc[b], sn[b]), sn[b]);
-            }
-        }
-    return s;
+    }
 }
 
 template <typename NT>
@@ -828,8 +847,13 @@ __device__ __forceinline__ void bil_close(const BilQuad &q, BilAcc s0, BilAcc s1
                                           const float4 *sn, int a, int pitch, int plane,
                                           float4 &r0, float4 &r1) {
     const bool ok0 = q.c0.w != 0.f, ok1 = q.c1.w != 0.f;
-    if (ok0 && !(s0.w >= kBilUnderflow)) s0 = bil_shifted_sum<R>(q.o0, sc, sn, a, pitch, plane);
-    if (ok1 && !(s1.w >= kBilUnderflow)) s1 = bil_shifted_sum<R>(q.o1, sc, sn, a, pitch, plane);
+    const bool re0 = ok0 && !(s0.w >= kBilUnderflow), re1 = ok1 && !(s1.w >= kBilUnderflow);
+    if (re0 || re1) {
+        BilAcc t0, t1;
+        bil_online_sums<R>(q.o0, q.o1, sc, sn, a, pitch, plane, t0, t1);
+        if (re0) s0 = t0;
+        if (re1) s1 = t1;
+    }
     r0 = ok0 ? bil_finish<NT>(s0, q.n0) : q.n0;
     r1 = ok1 ? bil_finish<NT>(s1, q.n1) : q.n1;
 }

@@ -109,6 +109,61 @@ def autotune(workloads, cache_path: str | None = DEFAULT_CACHE, reps: int = 30) 
     return report
 
 
+def tune_frame(workloads, cache_path: str | None = None, reps: int = 40) -> dict:
+    """Tune the single-frame table entries on the fused entry point: for each
+    window size, every pair of (Laplacian shape, bilateral shape) candidates
+    is timed on pl_smooth_frame (FramePlan.run_fused, preallocated buffers,
+    HIP events, frames rotating over `sets` buffer sets) and the fastest pair
+    is installed.  `workloads` is a list of (frames: list of [M, N, 3] device
+    tensors, kernel_lap, lam, iters_lap, kernel_bil, sigma_length,
+    sigma_angle, iters_bil) with kernel_lap == kernel_bil; the frames of one
+    window size should be its most important workload.  Cached like
+    autotune() (entries laplacian_k*, bilateral_k*)."""
+    arch = arch_name()
+    report = {}
+    for frames, kl, lam, il, kb, sl, sa, ib in workloads:
+        M, N = int(frames[0].shape[0]), int(frames[0].shape[1])
+        dev = frames[0].device
+        plans = [pl.FramePlan(M, N, kl, lam, il, kb, sl, sa, ib, torch.float32, dev)
+                 for _ in frames]
+        stream = pl._stream(dev)
+        before = (pl.pl_tune_get(pl.PL_STAGE_LAPLACIAN, kl), pl.pl_tune_get(pl.PL_STAGE_BILATERAL, kb))
+        times = {}
+        for lc in LAP_CANDIDATES.get(kl, [(8, 32, 1)]):
+            for bc in BIL_CANDIDATES.get(kb, [(8, 32, 1)]):
+                try:
+                    pl.pl_tune_set(pl.PL_STAGE_LAPLACIAN, kl, *lc)
+                    pl.pl_tune_set(pl.PL_STAGE_BILATERAL, kb, *bc)
+                except pl.PLError:
+                    continue
+                for p in plans:          # the workspace size depends on the shapes
+                    p._frame = None
+                k = [0]
+
+                def call():
+                    i = k[0] % len(plans)
+                    plans[i].run_fused(frames[i], stream)
+                    k[0] += 1
+                times[(lc, bc)] = _time(call, reps)
+        if not times:
+            pl.pl_tune_set(pl.PL_STAGE_LAPLACIAN, kl, *before[0])
+            pl.pl_tune_set(pl.PL_STAGE_BILATERAL, kb, *before[1])
+            continue
+        lc, bc = min(times, key=times.get)
+        pl.pl_tune_set(pl.PL_STAGE_LAPLACIAN, kl, *lc)
+        pl.pl_tune_set(pl.PL_STAGE_BILATERAL, kb, *bc)
+        ranked = sorted(times.items(), key=lambda x: x[1])[:8]
+        common = {"frame": [M, N], "objective": "pl_smooth_frame",
+                  "frame_us": round(times[(lc, bc)], 2),
+                  "fastest_pairs_us": {f"{a[0]}x{a[1]}/{a[2]} + {b[0]}x{b[1]}/{b[2]}": round(t, 2)
+                                       for (a, b), t in ranked}}
+        report[STAGE_NAMES[pl.PL_STAGE_LAPLACIAN] + f"_k{kl}"] = dict(common, best=lc)
+        report[STAGE_NAMES[pl.PL_STAGE_BILATERAL] + f"_k{kb}"] = dict(common, best=bc)
+    if cache_path:
+        save_cache(cache_path, arch, report)
+    return report
+
+
 def tune_batch_stage(stage: int, kernel: int, frames: list, reps: int = 10,
                      normal_dtype=None) -> dict:
     """Time each candidate shape for a batched stage (PL_STAGE_BATCH_*) by
@@ -164,7 +219,8 @@ def save_cache(path: str, arch: str, report: dict) -> None:
             data = {}
     data.setdefault(arch, {})
     for name, r in report.items():
-        data[arch][name] = {"best": list(r["best"]), "frame": r.get("frame")}
+        data[arch][name] = {k: (list(v) if k == "best" else v) for k, v in r.items()
+                            if k in ("best", "frame", "objective", "frame_us", "fastest_pairs_us")}
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
