@@ -559,10 +559,14 @@ __device__ __forceinline__ void tri_geom(const V3 &a, const V3 &b, const V3 &c, 
     cen.z = (a.z + b.z + c.z) * third;
     const float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
     const float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
-    // explicit fused forms: the same bits wherever this is inlined
-    const float nx = fmaf(e1y, e2z, -(e1z * e2y));
-    const float ny = fmaf(e1z, e2x, -(e1x * e2z));
-    const float nz = fmaf(e1x, e2y, -(e1y * e2x));
+    // two rounded products and a difference (contraction is off, so the same
+    // bits wherever this is inlined): when two corners coincide the edges are
+    // equal and the products cancel exactly, so a zero-area triangle gets a
+    // zero cross product and a NaN normal.  A fused form would leave the
+    // rounding error of one product there instead.
+    const float nx = e1y * e2z - e1z * e2y;
+    const float ny = e1z * e2x - e1x * e2z;
+    const float nz = e1x * e2y - e1y * e2x;
     const float l2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
     if (l2 > 0.f) {
         const float k = __builtin_amdgcn_rsqf(l2);

@@ -331,12 +331,41 @@ def test_bilateral_fp16_vs_fp64(pl):
 
 # ---------------------------------------------------------------- whole path
 
+def yardsticks(ref, k, n):
+    """The spread exact arithmetic shows on the same path: the FP64 pipeline
+    restarted from its own smoothed vertices rounded to float32 (y32), and the
+    same with the normals rounded to float16 wherever the float16 mode stores
+    them -- the raw normals and each sweep's output (y16).  The bilateral
+    weights (sigma_angle = 0.1 on noisy normals) amplify such perturbations
+    by 1e2..1e3 where a window holds two balanced clusters of normals."""
+    n32, c32 = oracle.tri_normals(ref["points"].astype(np.float32), THREADS)
+    f = oracle.bilateral(n32, c32, k.kernel_bil, k.sigma_length, k.sigma_angle, k.iters_bil,
+                         THREADS)
+    y32 = angle(oracle.gather(f, ref["tri_map"], n), ref["normals_T"])
+    g = n32.astype(np.float16).astype(np.float64)
+    for _ in range(k.iters_bil):
+        g = oracle.bilateral(g, c32, k.kernel_bil, k.sigma_length, k.sigma_angle, 1, THREADS)
+        g = g.astype(np.float16).astype(np.float64)
+    y16 = angle(oracle.gather(g, ref["tri_map"], n), ref["normals_T"])
+    return y32, y16
+
+
+@pytest.mark.parametrize("dtype_name", ["float32", "float16"])
 @pytest.mark.parametrize("config", [0, 1, 2])
-def test_end_to_end(pl, config):
+def test_end_to_end(pl, config, dtype_name):
+    """The whole path against the FP64 oracle.  Integers exact, vertices within
+    1e-5; the filtered normals' error distribution is gated in full: the
+    median at 1e-4 rad (float32) and the 99th percentile at 1e-3 rad (both
+    modes; the float16 target is stated at that percentile), and the largest
+    error at three times the largest of the exact-arithmetic yardstick for
+    the same storage (plus 1e-4 rad), so the tail has to be the conditioning
+    of the filter and not the kernels' arithmetic."""
+    import torch
     pts, k = config_frame(config)
-    say("end to end", config)
+    say("end to end", config, dtype_name)
     r = pl.smooth_frame(to_dev(pts), k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
-                        k.sigma_length, k.sigma_angle, k.iters_bil)
+                        k.sigma_length, k.sigma_angle, k.iters_bil,
+                        normal_dtype=getattr(torch, dtype_name))
     ref = oracle.pipeline(pts, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil,
                           k.sigma_length, k.sigma_angle, k.iters_bil, THREADS)
     n = int(host(r["n_tri"])[0])
@@ -344,22 +373,20 @@ def test_end_to_end(pl, config):
     assert np.array_equal(host(r["triangles"])[:n], ref["triangles"])
     assert np.array_equal(host(r["halfedges"])[:3 * n], ref["halfedges"])
     check_points(host(r["points"]), ref["points"], pts)
-    ang = angle(host(r["normals_T"])[:n], ref["normals_T"])
-    # The same spread in exact arithmetic: the FP64 pipeline restarted from
-    # its own smoothed vertices rounded to float32.  The bilateral weights
-    # (sigma_angle = 0.1 on noisy normals) amplify a 1e-7 relative vertex
-    # perturbation by 1e2..1e3, so end-to-end errors are reported against
-    # this yardstick while the 1e-4 rad gate applies stage by stage.
-    n32, c32 = oracle.tri_normals(ref["points"].astype(np.float32), THREADS)
-    f32 = oracle.bilateral(n32, c32, k.kernel_bil, k.sigma_length, k.sigma_angle,
-                           k.iters_bil, THREADS)
-    yard = angle(oracle.gather(f32, ref["tri_map"], n), ref["normals_T"])
-    print(f"config {config} end to end: normal angle err p50 {np.median(ang):.2e} "
-          f"p99 {np.percentile(ang, 99):.2e} max {ang.max():.2e}; exact arithmetic on "
-          f"float32 vertices: p50 {np.median(yard):.2e} p99 {np.percentile(yard, 99):.2e} "
+    got = host(r["normals_T"])[:n].astype(np.float64)
+    nan_r = np.isnan(ref["normals_T"]).any(-1)
+    assert np.array_equal(np.isnan(got).any(-1), nan_r)
+    ang = angle(got[~nan_r], ref["normals_T"][~nan_r])
+    y32, y16 = yardsticks(ref, k, n)
+    yard = (y32 if dtype_name == "float32" else y16)[~nan_r]
+    print(f"config {config} {dtype_name} end to end: normal angle err p50 {np.median(ang):.2e} "
+          f"p99 {np.percentile(ang, 99):.2e} max {ang.max():.2e}; exact arithmetic on the same "
+          f"storage: p50 {np.median(yard):.2e} p99 {np.percentile(yard, 99):.2e} "
           f"max {yard.max():.2e}")
-    assert np.median(ang) <= NORMAL_ATOL
+    if dtype_name == "float32":
+        assert np.median(ang) <= NORMAL_ATOL
     assert np.percentile(ang, 99) <= max(1e-3, 3 * np.percentile(yard, 99))
+    assert ang.max() <= 3 * yard.max() + 1e-4, (ang.max(), yard.max())
 
 
 def test_deterministic(pl):
