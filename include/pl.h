@@ -64,7 +64,10 @@ typedef enum {
 } pl_status;
 
 /* Storage type of triangle normals.  Arithmetic is float32 either way. */
-typedef enum { PL_F32 = 0, PL_F16 = 1 } pl_dtype;
+/* Storage type of the normals.  A plain int32_t, not an enum type, so that a
+   value outside the list reaches the library's check (PL_ERR_ARG) as it is. */
+typedef int32_t pl_dtype;
+enum { PL_F32 = 0, PL_F16 = 1 };
 
 /* Version of this ABI (major * 100 + minor). */
 int32_t pl_version(void);
@@ -361,12 +364,13 @@ void pl_ga_destroy(pl_ga ga);
  * tile_rows * tile_cols <= 16384; the LDS the shape needs must fit 156 KB.
  * Returns PL_ERR_KERNEL / PL_ERR_ARG for an invalid request.
  */
-typedef enum {
+typedef int32_t pl_stage;     /* one of the values below (PL_ERR_ARG otherwise) */
+enum {
     PL_STAGE_LAPLACIAN = 0,
     PL_STAGE_BILATERAL = 1,
     PL_STAGE_BATCH_LAPLACIAN = 2,
     PL_STAGE_BATCH_BILATERAL = 3
-} pl_stage;
+};
 pl_status pl_tune_get(pl_stage stage, int32_t kernel, int32_t *tile_rows, int32_t *tile_cols,
                       int32_t *fuse);
 pl_status pl_tune_set(pl_stage stage, int32_t kernel, int32_t tile_rows, int32_t tile_cols,

@@ -25,7 +25,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pl_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PL_ORACLE_LIBRARY names another build of the same C file (the sanitizer
+# build of paper_2007_12065_amd/sanitize.py); by default the in-tree one
+_LIB = os.environ.get("PL_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 __all__ = ["build", "mesh", "halfedges", "laplacian", "tri_normals",
@@ -34,7 +36,10 @@ __all__ = ["build", "mesh", "halfedges", "laplacian", "tri_normals",
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction).
+    A library named by PL_ORACLE_LIBRARY is used as it is."""
+    if os.environ.get("PL_ORACLE_LIBRARY"):
+        return _LIB
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call([

@@ -15,7 +15,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpl.so")
+# PL_LIBRARY names another build of the same library (the host-sanitizer
+# build of sanitize.py); by default the in-tree libpl.so
+LIB_PATH = os.environ.get("PL_LIBRARY") or os.path.join(_HERE, "libpl.so")
 
 PL_F32, PL_F16 = 0, 1
 _STATUS = {0: "PL_OK", -1: "PL_ERR_ARG", -2: "PL_ERR_SHAPE", -3: "PL_ERR_KERNEL",
