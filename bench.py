@@ -681,10 +681,12 @@ def main():
     # tile shapes and sweep fusion: the committed tuning file, or tuned here
     if args.retune:
         per = {}
-        for kind in ("rgbd", "lidar128"):
+        # one workload per table entry: large frames (480x640 3x3, 128x2048
+        # 5x5) and small ones (120x160 3x3, 64x1024 5x5)
+        for kind in ("rgbd", "lidar128", "rgbd_small", "lidar"):
             kk = KINDS[kind]
             fr = frames if kind == "rgbd" else [torch.from_numpy(make_frame(kind, 7 + i)).to(dev)
-                                                for i in range(4)]
+                                                for i in range(8)]
             per[kind] = (fr, kk.kernel_lap, kk.lam, kk.iters_lap, kk.kernel_bil, kk.sigma_length,
                          kk.sigma_angle, kk.iters_bil)
         tune.tune_frame(list(per.values()), cache_path=args.retune)

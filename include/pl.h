@@ -355,9 +355,12 @@ void pl_ga_destroy(pl_ga ga);
  * do not depend on these values (the arithmetic of every output is the same
  * whatever the tiling), and float16 results do not depend on `fuse`.  The
  * single-frame calls read the PL_STAGE_LAPLACIAN / PL_STAGE_BILATERAL
- * entries; batch plans read the PL_STAGE_BATCH_* entries when they are
- * created (a launch over many frames favours other shapes than one over a
- * single frame).  The table is process-wide; pl_tune_set is meant for a
+ * entries, or the PL_STAGE_*_SMALL ones for frames of at most 131072 points
+ * (M * N <= 2^17: a 64 x 1024 frame fills the chip with other shapes than a
+ * 480 x 640 one); batch plans read the PL_STAGE_BATCH_* entries when they
+ * are created (a launch over many frames favours other shapes than one over
+ * a single frame).  pl_laplacian_fused_sweeps reports the large-frame
+ * entry.  The table is process-wide; pl_tune_set is meant for a
  * tuner run before work is enqueued (it does not affect launches already
  * enqueued or plans already created).
  * kernel      odd window size, 3..9.
@@ -369,7 +372,9 @@ enum {
     PL_STAGE_LAPLACIAN = 0,
     PL_STAGE_BILATERAL = 1,
     PL_STAGE_BATCH_LAPLACIAN = 2,
-    PL_STAGE_BATCH_BILATERAL = 3
+    PL_STAGE_BATCH_BILATERAL = 3,
+    PL_STAGE_LAPLACIAN_SMALL = 4,
+    PL_STAGE_BILATERAL_SMALL = 5
 };
 pl_status pl_tune_get(pl_stage stage, int32_t kernel, int32_t *tile_rows, int32_t *tile_cols,
                       int32_t *fuse);

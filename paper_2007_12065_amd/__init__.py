@@ -123,6 +123,8 @@ _lib.pl_vertex_update.argtypes = [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _s
 _lib.pl_vertex_update.restype = _i32
 
 PL_STAGE_LAPLACIAN, PL_STAGE_BILATERAL, PL_STAGE_BATCH_LAPLACIAN, PL_STAGE_BATCH_BILATERAL = 0, 1, 2, 3
+PL_STAGE_LAPLACIAN_SMALL, PL_STAGE_BILATERAL_SMALL = 4, 5
+SMALL_FRAME_POINTS = 1 << 17      # frames of at most this many points read the *_SMALL entries
 
 EXPORTS = ["pl_version", "pl_last_error", "pl_mesh_opc_workspace", "pl_mesh_opc",
            "pl_mesh_opc_static",

@@ -148,7 +148,9 @@ using namespace pl;
 static_assert((int)PL_STAGE_LAPLACIAN == (int)pl::kStageLaplacian &&
                   (int)PL_STAGE_BILATERAL == (int)pl::kStageBilateral &&
                   (int)PL_STAGE_BATCH_LAPLACIAN == (int)pl::kStageBatchLaplacian &&
-                  (int)PL_STAGE_BATCH_BILATERAL == (int)pl::kStageBatchBilateral,
+                  (int)PL_STAGE_BATCH_BILATERAL == (int)pl::kStageBatchBilateral &&
+                  (int)PL_STAGE_LAPLACIAN_SMALL == (int)pl::kStageLaplacianSmall &&
+                  (int)PL_STAGE_BILATERAL_SMALL == (int)pl::kStageBilateralSmall,
               "pl_stage and the tuning table's stages must agree");
 
 extern "C" {
@@ -313,7 +315,7 @@ __attribute__((visibility("default"))) pl_status pl_tune_get(pl_stage stage, int
                                                              int32_t *tile_cols, int32_t *fuse) {
     g_err[0] = 0;
     PL_TRY(check_kernel(kernel));
-    if (stage < PL_STAGE_LAPLACIAN || stage > PL_STAGE_BATCH_BILATERAL) {
+    if (stage < PL_STAGE_LAPLACIAN || stage > PL_STAGE_BILATERAL_SMALL) {
         set_error("unknown stage %d", (int)stage);
         return PL_ERR_ARG;
     }
@@ -329,7 +331,7 @@ __attribute__((visibility("default"))) pl_status pl_tune_set(pl_stage stage, int
                                                              int32_t tile_cols, int32_t fuse) {
     g_err[0] = 0;
     PL_TRY(check_kernel(kernel));
-    if (stage < PL_STAGE_LAPLACIAN || stage > PL_STAGE_BATCH_BILATERAL) {
+    if (stage < PL_STAGE_LAPLACIAN || stage > PL_STAGE_BILATERAL_SMALL) {
         set_error("unknown stage %d", (int)stage);
         return PL_ERR_ARG;
     }

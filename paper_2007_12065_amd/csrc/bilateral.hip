@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_bilateral(
 template <int R, typename NT>
 pl_status run(const NT *nin, const float *cen, int M, int N, float sl, float sa, int iterations,
               NT *nout, const int32_t *tri_map, NT *nT, NT *tmp, hipStream_t s) {
-    const TileCfg c = tile_cfg(kStageBilateral, R);
+    const TileCfg c = tile_cfg(frame_stage(false, M, N), R);
     const int Mq = M - 1, Nq = N - 1;
     const int tiles_x = (Nq + c.tw - 1) / c.tw;
     const int ntiles = tiles_x * ((Mq + c.th - 1) / c.th);

@@ -249,7 +249,7 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s, LaunchLog *log) {
     NT *bil_tmp = f.iters_bil > 1 ? reinterpret_cast<NT *>(w) : nullptr;
 
     const int Rl = f.kernel_lap / 2, Rb = f.kernel_bil / 2;
-    const TileCfg cl = tile_cfg(kStageLaplacian, Rl), cb = tile_cfg(kStageBilateral, Rb);
+    const TileCfg cl = tile_cfg(frame_stage(true, M, N), Rl), cb = tile_cfg(frame_stage(false, M, N), Rb);
     const int Ll = f.iters_lap == 0 ? 1 : (f.iters_lap + cl.fuse - 1) / cl.fuse;
     const int Lb = f.iters_bil == 0 ? 1 : (f.iters_bil + cb.fuse - 1) / cb.fuse;
     const int total = Ll + Lb;

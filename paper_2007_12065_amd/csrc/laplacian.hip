@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kTileBlock) void k_laplacian(const float *__restric
 template <int R>
 pl_status run(const float *in, float *out, int M, int N, float lam, int iterations, float *tmp,
               hipStream_t s) {
-    const TileCfg c = tile_cfg(kStageLaplacian, R);
+    const TileCfg c = tile_cfg(frame_stage(true, M, N), R);
     const int tiles_x = (N + c.tw - 1) / c.tw;
     const int ntiles = tiles_x * ((M + c.th - 1) / c.th);
     // zero sweeps: one copying launch (F = 0)

@@ -687,13 +687,15 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // the sums and the squared norm of Eq. 6 finite for windows up to 9 x 9
 // (160 neighbours).  If the total still drops below 2^-60 (every neighbour
 // far beyond the quad's own pair), that triangle is recomputed with every
-// exponent shifted by the smallest one, which puts the largest term at 1:
-// one more pass in the same order, the shift lowered as smaller exponents
-// come and the running sum rescaled with it.  A wave takes that pass if any
-// of its lanes needs it (isolated triangles: a few per thousand on the
-// LiDAR frames, which put one in about a tenth of the waves), so it has the
-// main pass's shape: one displacement's loads together, both triangles at
-// once.
+// exponent shifted by the smallest one, which puts the largest term at 1.
+// Such triangles are isolated ones (a few per thousand on the LiDAR frames,
+// which put one in about a tenth of the waves), so instead of the lane
+// redoing its window alone -- which held up its whole wave -- the lane
+// queues the triangle in LDS, and after the sweep one wave per queued
+// triangle takes its neighbours over the wave's lanes: the smallest exponent
+// by a wave minimum, then the shifted weights and weighted normals summed
+// over the lanes in a fixed tree.  The result depends on the triangle's
+// window only, not on the tile.
 //
 // Summation order.  The window's displacements split into D+ (dy = 0 and
 // dx > 0, or dy > 0) and their negatives; a triangle sums its terms in a
@@ -708,7 +710,9 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // re-rounded to float16, as if stored between launches, so results do not
 // depend on F.  F = 0 copies the tile (and gathers).
 // LDS: (TQH + 2RF) * (TQW + 2RF) float4 times 4 (centroids and normals of
-// both triangles) or, with F > 1, times 6 (a second normal buffer).
+// both triangles) or, with F > 1, times 6 (a second normal buffer), and the
+// queue of underflowed triangles (one int per triangle of the region, and
+// its count).
 // ---------------------------------------------------------------------------
 
 constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
@@ -716,8 +720,10 @@ constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
 // (<= 80 VGPRs), more than the LDS of a typical tile lets reside anyway
 constexpr int kBilWavesPerSimd = 6;
 constexpr float kBilShiftCap = 52.f;
+constexpr int kBilMaxSweeps = 8;                  // fused sweeps per launch at most
 __host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW) {
-    return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F);
+    return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) +
+           sizeof(int) * (2 * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) + kBilMaxSweeps + 1);
 }
 
 // Output stores of the filter: streaming for float32 normals, plain for
@@ -772,51 +778,6 @@ __device__ __forceinline__ void bil_dplus(int i, int &dy, int &dx) {
 }
 template <int R> constexpr int bil_ndplus() { return 2 * R * R + 2 * R; }
 
-// s += 2^(m - e) n with the shift m lowered to e when e is smaller: the
-// running sum is rescaled by 2^(m_new - m_old) first, so that at the end the
-// shift is the smallest exponent seen and the largest term is 1.  m starts at
-// a large finite value (the first finite e rescales an empty sum by 0); a
-// missing neighbour (e = +inf) adds 2^-inf = 0.
-constexpr float kBilOnlineStart = 1e30f;
-
-__device__ __forceinline__ void bil_add_online(BilAcc &s, float &m, float e, const float4 n) {
-    const float mn = fminf(m, e);
-    const float f = __builtin_amdgcn_exp2f(mn - m);
-    const float w = __builtin_amdgcn_exp2f(mn - e);
-    s.w = fmaf(s.w, f, w);
-    s.x = fmaf(w, n.x, s.x * f);
-    s.y = fmaf(w, n.y, s.y * f);
-    s.z = fmaf(w, n.z, s.z * f);
-    m = mn;
-}
-
-// Both triangles' sums in the main pass's order, each shifted by its own
-// smallest exponent (one pass, online): the fallback when a sum underflows.
-template <int R>
-__device__ __forceinline__ void bil_online_sums(const BilOwn &o0, const BilOwn &o1,
-                                                const float4 *sc, const float4 *sn, int a,
-                                                int pitch, int plane, BilAcc &s0, BilAcc &s1) {
-    s0 = BilAcc{0.f, 0.f, 0.f, 0.f};
-    s1 = s0;
-    float m0 = kBilOnlineStart, m1 = kBilOnlineStart;
-#pragma unroll 1
-    for (int i = 0; i < bil_ndplus<R>(); ++i) {
-        int dy, dx;
-        bil_dplus<R>(i, dy, dx);
-        const int off = dy * pitch + dx;
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int b = side == 0 ? a + off : a - off;
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                const float4 c = sc[b + kk * plane], n = sn[b + kk * plane];
-                bil_add_online(s0, m0, bil_pair_e(o0, c, n), n);
-                bil_add_online(s1, m1, bil_pair_e(o1, c, n), n);
-            }
-        }
-    }
-}
-
 template <typename NT>
 __device__ __forceinline__ float4 bil_finish(BilAcc s, float4 cur) {
     const float l2 = fmaf(s.x, s.x, fmaf(s.y, s.y, s.z * s.z));
@@ -845,32 +806,133 @@ __device__ __forceinline__ BilQuad bil_quad(const float4 *sc, const float4 *sn, 
     return q;
 }
 
-// Fallback for underflowed sums, Eq. 6, missing triangles copied through.
-template <int R, typename NT>
-__device__ __forceinline__ void bil_close(const BilQuad &q, BilAcc s0, BilAcc s1, const float4 *sc,
-                                          const float4 *sn, int a, int pitch, int plane,
-                                          float4 &r0, float4 &r1) {
+// Eq. 6 for both triangles of a quad, missing triangles copied through;
+// pend0 / pend1: the sum underflowed (the triangle goes to the queue and
+// r0 / r1 are not set).
+template <typename NT>
+__device__ __forceinline__ void bil_close(const BilQuad &q, BilAcc s0, BilAcc s1, float4 &r0,
+                                          float4 &r1, bool &pend0, bool &pend1) {
     const bool ok0 = q.c0.w != 0.f, ok1 = q.c1.w != 0.f;
-    const bool re0 = ok0 && !(s0.w >= kBilUnderflow), re1 = ok1 && !(s1.w >= kBilUnderflow);
-    if (re0 || re1) {
-        BilAcc t0, t1;
-        bil_online_sums<R>(q.o0, q.o1, sc, sn, a, pitch, plane, t0, t1);
-        if (re0) s0 = t0;
-        if (re1) s1 = t1;
-    }
+    pend0 = ok0 && !(s0.w >= kBilUnderflow);
+    pend1 = ok1 && !(s1.w >= kBilUnderflow);
     r0 = ok0 ? bil_finish<NT>(s0, q.n0) : q.n0;
     r1 = ok1 ? bil_finish<NT>(s1, q.n1) : q.n1;
 }
 
-// Both triangles of the quad at LDS index a, in the fixed summation order.
+__device__ __forceinline__ float wave_min_f(float x) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) x = fminf(x, __shfl_xor(x, m, kWave));
+    return x;
+}
+
+__device__ __forceinline__ float wave_sum_f(float x) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) x += __shfl_xor(x, m, kWave);
+    return x;
+}
+
+// The underflowed triangle k of the quad at LDS index a, by one whole wave:
+// lane l takes neighbours j = l, l + 64, ... in the main pass's order (j / 4
+// the displacement of D+, bit 1 the side, bit 0 the triangle), the shift is
+// the smallest exponent (a wave minimum, exact), and the shifted sums are
+// added lane by lane in a fixed butterfly.  Every lane returns the result.
+template <int R, typename NT>
+__device__ __forceinline__ float4 bil_fallback_wave(const float4 *sc, const float4 *sn, int a,
+                                                    int k, int pitch, int plane, float ka,
+                                                    float kb) {
+    constexpr int kN = 4 * bil_ndplus<R>();               // neighbours
+    constexpr int kPer = (kN + kWave - 1) / kWave;         // per lane
+    const int lane = (int)threadIdx.x & (kWave - 1);
+    const float4 c = sc[k * plane + a], n = sn[k * plane + a];
+    const BilOwn o{c.x, c.y, c.z, n.x, n.y, n.z, ka, kb};
+    const float inf = __builtin_inff();
+    float e[kPer];
+    float4 nj[kPer];
+    float mn = inf;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int j = lane + t * kWave;
+        e[t] = inf;
+        nj[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < kN) {
+            int dy, dx;
+            bil_dplus<R>(j >> 2, dy, dx);
+            const int off = dy * pitch + dx;
+            const int b = ((j >> 1) & 1) ? a - off : a + off;
+            const int kk = j & 1;
+            const float4 cj = sc[b + kk * plane];
+            nj[t] = sn[b + kk * plane];
+            e[t] = bil_pair_e(o, cj, nj[t]);
+            mn = fminf(mn, e[t]);
+        }
+    }
+    mn = wave_min_f(mn);
+    BilAcc s{0.f, 0.f, 0.f, 0.f};
+    if (mn < inf) {
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) bil_add(s, mn, e[t], nj[t]);
+    }
+    s.x = wave_sum_f(s.x);
+    s.y = wave_sum_f(s.y);
+    s.z = wave_sum_f(s.z);
+    s.w = wave_sum_f(s.w);
+    return bil_finish<NT>(s, n);
+}
+
+// Queue of underflowed triangles in LDS: entries 2 a + k (at most two per
+// quad of the staged region, so it cannot overflow) and one count per sweep
+// (sweep f counts into count[f], so no count is reset in between).
+struct BilQueue {
+    int *entry;
+    int *count;
+};
+
+__device__ __forceinline__ void bil_push(const BilQueue &qu, int a, int k, int sweep) {
+    const int i = atomicAdd(&qu.count[sweep], 1);
+    qu.entry[i] = 2 * a + k;
+}
+
+// Lanes per quad: the displacements of D+ are dealt over P adjacent lanes
+// (lane part p takes i = p, p + P, ...), whose partial sums are then added
+// in a fixed tree -- (s_0 + s_1) for P = 2, ((s_0 + s_1) + (s_2 + s_3)) for
+// P = 4 -- identical on every lane of the quad (addition commutes exactly).
+// Larger windows take more lanes: a 5x5 window has 48 neighbours per
+// triangle, and a LiDAR frame of 64 x 1024 quads filled only one wave per
+// SIMD at one lane per quad.  Every kernel uses the same P for a given
+// window, so all paths keep giving the same bits.
+#ifndef PL_BIL_PARTS_K3
+#define PL_BIL_PARTS_K3 1
+#endif
+#ifndef PL_BIL_PARTS_K5
+#define PL_BIL_PARTS_K5 4
+#endif
+template <int R> constexpr int bil_parts() { return R == 1 ? PL_BIL_PARTS_K3 : PL_BIL_PARTS_K5; }
+
+template <int P>
+__device__ __forceinline__ BilAcc bil_reduce(BilAcc s) {
+#pragma unroll
+    for (int m = 1; m < P; m <<= 1) {
+        s.x += __shfl_xor(s.x, m, kWave);
+        s.y += __shfl_xor(s.y, m, kWave);
+        s.z += __shfl_xor(s.z, m, kWave);
+        s.w += __shfl_xor(s.w, m, kWave);
+    }
+    return s;
+}
+
+// Both triangles of the quad at LDS index a, in the fixed summation order;
+// `part` is the lane's share (0 .. bil_parts<R>() - 1).  Every lane of the
+// quad returns the same r0, r1 (and pending flags: see bil_close).
 template <int R, typename NT>
 __device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *sn, int a,
                                                 int pitch, int plane, float ka, float kb,
-                                                float4 &r0, float4 &r1) {
+                                                int part, float4 &r0, float4 &r1, bool &pend0,
+                                                bool &pend1) {
+    constexpr int P = bil_parts<R>();
     const BilQuad q = bil_quad(sc, sn, a, plane, ka, kb);
     BilAcc s0{0.f, 0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-    for (int i = 0; i < bil_ndplus<R>(); ++i) {
+    for (int i = part; i < bil_ndplus<R>(); i += P) {
         int dy, dx;
         bil_dplus<R>(i, dy, dx);
         const int off = dy * pitch + dx;
@@ -885,7 +947,11 @@ __device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *
             }
         }
     }
-    bil_close<R, NT>(q, s0, s1, sc, sn, a, pitch, plane, r0, r1);
+    if constexpr (P > 1) {
+        s0 = bil_reduce<P>(s0);
+        s1 = bil_reduce<P>(s1);
+    }
+    bil_close<NT>(q, s0, s1, r0, r1, pend0, pend1);
 }
 
 // FromPts: the raw normals and centroids are not read but computed here from
@@ -905,6 +971,10 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     float4 *s_c = lds;                  // [2][S] centroids, w = 1 if usable
     float4 *s_n = lds + 2 * S;          // [2][S] normals
     float4 *s_m = lds + 4 * S;          // [2][S] second normal buffer (F > 1)
+    // queue of underflowed triangles: 2S entries, then one count per sweep
+    int *qbase = reinterpret_cast<int *>(lds + (F > 1 ? 6 : 4) * S);
+    const BilQueue qu{qbase, qbase + 2 * S};
+    if (threadIdx.x < kBilMaxSweeps + 1) qu.count[threadIdx.x] = 0;
     const float inf = __builtin_inff();
     const int oy = qy0 - halo, ox = qx0 - halo;
 
@@ -946,18 +1016,32 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
 
     const float4 *cur = s_n;
     float4 *nxt = s_m;
+    // lanes per quad (bil_parts): quad slot and share of this lane
+    constexpr int P = bil_parts<R>();
+    const int slot = (int)threadIdx.x / P, part = (int)threadIdx.x % P;
+    const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
     // intermediate sweeps: LDS to LDS over the shrinking exact region
     for (int f = 1; f < F; ++f) {
         const int lo = R * f;
         const int Hf = H - 2 * lo, Wf = W - 2 * lo;
         const DivBy byWf(Wf);
-        for (int idx = threadIdx.x; idx < Hf * Wf; idx += kTileBlock) {
+        for (int idx = slot; idx < Hf * Wf; idx += kTileBlock / P) {
             const int ry = byWf.div(idx);
             const int a = (lo + ry) * W + lo + (idx - ry * Wf);
             float4 r0, r1;
-            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r0, r1);
-            nxt[a] = r0;
-            nxt[S + a] = r1;
+            bool p0, p1;
+            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, part, r0, r1, p0, p1);
+            if (part == 0) {
+                if (p0) bil_push(qu, a, 0, f); else nxt[a] = r0;
+                if (p1) bil_push(qu, a, 1, f); else nxt[S + a] = r1;
+            }
+        }
+        __syncthreads();
+        const int nq = qu.count[f];
+        for (int e = wave; e < nq; e += kTileBlock / kWave) {
+            const int a = qu.entry[e] >> 1, k = qu.entry[e] & 1;
+            const float4 r = bil_fallback_wave<R, NT>(s_c, cur, a, k, W, S, ka, kb);
+            if (lane == 0) nxt[k * S + a] = r;
         }
         __syncthreads();
         float4 *t = const_cast<float4 *>(cur);
@@ -967,11 +1051,16 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
 
     // last sweep (or the copy when F = 0): the tile itself, to global memory
     const DivBy byTQW(TQW);
-    for (int idx = threadIdx.x; idx < TQH * TQW; idx += kTileBlock) {
+    for (int idx = slot; idx < TQH * TQW; idx += kTileBlock / P) {
         const int ty = byTQW.div(idx), tx = idx - ty * TQW;
         const int qy = qy0 + ty, qx = qx0 + tx;
         if (qy >= Mq || qx >= Nq) continue;
         const size_t q = (size_t)qy * Nq + qx;
+        const int a = (ty + halo) * W + tx + halo;
+        float4 r[2];
+        bool pend[2] = {false, false};
+        if (F > 0) bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, part, r[0], r[1], pend[0], pend[1]);
+        if (part != 0) continue;             // the quad's first lane stores
         NT v[6];
         NT raw[6];                           // raw normals as stored (FromPts)
         if constexpr (FromPts) {
@@ -988,12 +1077,11 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
             else return nin[6 * q + i];
         };
         if (F > 0) {
-            const int a = (ty + halo) * W + tx + halo;
-            float4 r[2];
-            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, r[0], r[1]);
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                if (s_c[k * S + a].w != 0.f) {
+                if (pend[k]) {                 // queued: written after the sweep
+                    bil_push(qu, a, k, F);
+                } else if (s_c[k * S + a].w != 0.f) {
                     st_f(&v[3 * k], r[k].x); st_f(&v[3 * k + 1], r[k].y); st_f(&v[3 * k + 2], r[k].z);
                 } else {                       // missing triangle: input bits unchanged
                     v[3 * k] = raw_at(3 * k);
@@ -1007,18 +1095,48 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
         }
         // streaming stores (float32 normals): they write partial lines, about
         // 2 MB more per launch on a 480x640 frame, but the whole path gains
-        // 2.4 us per frame
+        // 2.4 us per frame.  A queued triangle is written after the sweep.
+        const int t0 = tri_map ? tri_map[2 * q] : -1, t1 = tri_map ? tri_map[2 * q + 1] : -1;
+        if (!(pend[0] | pend[1])) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) bil_store(&nout[6 * q + i], v[i]);
-        if (tri_map) {
-            const int t0 = tri_map[2 * q], t1 = tri_map[2 * q + 1];
-            if (t0 >= 0) {
+            for (int i = 0; i < 6; ++i) bil_store(&nout[6 * q + i], v[i]);
+        } else {
 #pragma unroll
-                for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t0 + i], v[i]);
+            for (int i = 0; i < 3; ++i) {
+                if (!pend[0]) bil_store(&nout[6 * q + i], v[i]);
+                if (!pend[1]) bil_store(&nout[6 * q + 3 + i], v[3 + i]);
             }
-            if (t1 >= 0) {
+        }
+        if (t0 >= 0 && !pend[0]) {
 #pragma unroll
-                for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t1 + i], v[3 + i]);
+            for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t0 + i], v[i]);
+        }
+        if (t1 >= 0 && !pend[1]) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t1 + i], v[3 + i]);
+        }
+    }
+    if (F > 0) {
+        // the queued triangles of the last sweep, one wave each
+        __syncthreads();
+        const int nq = qu.count[F];
+        for (int e = wave; e < nq; e += kTileBlock / kWave) {
+            const int a = qu.entry[e] >> 1, k = qu.entry[e] & 1;
+            const float4 r = bil_fallback_wave<R, NT>(s_c, cur, a, k, W, S, ka, kb);
+            if (lane == 0) {
+                const int ly = a / W, lx = a - ly * W;
+                const size_t q = (size_t)(oy + ly) * Nq + (ox + lx);
+                NT v[3];
+                st_f(&v[0], r.x); st_f(&v[1], r.y); st_f(&v[2], r.z);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) bil_store(&nout[6 * q + 3 * k + i], v[i]);
+                if (tri_map) {
+                    const int t = tri_map[2 * q + k];
+                    if (t >= 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t + i], v[i]);
+                    }
+                }
             }
         }
     }

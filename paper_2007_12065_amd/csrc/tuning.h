@@ -11,9 +11,22 @@ enum Stage {
     kStageBilateral = 1,
     kStageBatchLaplacian = 2,      // the batched path's entries
     kStageBatchBilateral = 3,
-    kNumStages = 4
+    kStageLaplacianSmall = 4,      // single frames of at most kSmallFramePoints points
+    kStageBilateralSmall = 5,
+    kNumStages = 6
 };
-inline bool is_laplacian(Stage s) { return s == kStageLaplacian || s == kStageBatchLaplacian; }
+inline bool is_laplacian(Stage s) {
+    return s == kStageLaplacian || s == kStageBatchLaplacian || s == kStageLaplacianSmall;
+}
+// Single frames up to this many points read the *Small entries: a 64 x 1024
+// frame has a quarter of the tiles of a 480 x 640 one, and the shapes that
+// fill the chip differ.
+constexpr long kSmallFramePoints = 1L << 17;
+inline Stage frame_stage(bool laplacian, int M, int N) {
+    const bool small = (long)M * N <= kSmallFramePoints;
+    if (laplacian) return small ? kStageLaplacianSmall : kStageLaplacian;
+    return small ? kStageBilateralSmall : kStageBilateral;
+}
 constexpr int kMaxRadius = 4;                 // kernel sizes 3, 5, 7, 9
 
 struct TileCfg {

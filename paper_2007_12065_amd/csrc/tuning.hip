@@ -20,6 +20,10 @@ TileCfg g_cfg[kNumStages][kMaxRadius + 1] = {
     {{0, 0, 0}, {16, 32, 4}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}},
     // batched bilateral
     {{0, 0, 0}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}, {8, 32, 1}},
+    // Laplacian, small frames
+    {{0, 0, 0}, {16, 32, 4}, {8, 16, 2}, {8, 32, 1}, {8, 32, 1}},
+    // bilateral, small frames
+    {{0, 0, 0}, {8, 32, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}},
 };
 
 // gfx950 LDS per workgroup, less room for the batched kernels' static LDS

@@ -21,21 +21,31 @@ import paper_2007_12065_amd as pl
 
 LAP_CANDIDATES = {
     3: [(16, 32, 4), (16, 64, 4), (32, 32, 4), (16, 16, 4), (8, 64, 2), (16, 32, 2), (32, 32, 2),
-        (32, 16, 2), (16, 16, 2), (8, 32, 1), (4, 64, 1), (32, 32, 1)],
+        (32, 16, 2), (16, 16, 2), (8, 32, 1), (4, 64, 1), (32, 32, 1), (8, 16, 4), (8, 32, 4)],
     5: [(8, 32, 1), (4, 64, 1), (16, 32, 1), (8, 64, 2), (16, 32, 2), (16, 16, 2), (32, 32, 2),
-        (16, 16, 4), (32, 32, 1)],
+        (16, 16, 4), (32, 32, 1), (8, 16, 2), (8, 16, 1), (4, 32, 1)],
 }
 BIL_CANDIDATES = {
     3: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (8, 32, 2), (4, 32, 1), (8, 64, 1),
-        (2, 128, 1)],
-    5: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (4, 32, 1), (8, 64, 1)],
+        (2, 128, 1), (4, 16, 1)],
+    5: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (4, 32, 1), (8, 64, 1), (4, 16, 1),
+        (8, 8, 1), (2, 32, 1)],
 }
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pl_tune.json")
 
 
 STAGE_NAMES = {pl.PL_STAGE_LAPLACIAN: "laplacian", pl.PL_STAGE_BILATERAL: "bilateral",
                pl.PL_STAGE_BATCH_LAPLACIAN: "batch_laplacian",
-               pl.PL_STAGE_BATCH_BILATERAL: "batch_bilateral"}
+               pl.PL_STAGE_BATCH_BILATERAL: "batch_bilateral",
+               pl.PL_STAGE_LAPLACIAN_SMALL: "laplacian_small",
+               pl.PL_STAGE_BILATERAL_SMALL: "bilateral_small"}
+
+
+def frame_stages(M: int, N: int) -> tuple[int, int]:
+    """The (Laplacian, bilateral) table entries a single M x N frame reads."""
+    if M * N <= pl.SMALL_FRAME_POINTS:
+        return pl.PL_STAGE_LAPLACIAN_SMALL, pl.PL_STAGE_BILATERAL_SMALL
+    return pl.PL_STAGE_LAPLACIAN, pl.PL_STAGE_BILATERAL
 
 
 def arch_name(device=None) -> str:
@@ -60,10 +70,10 @@ def tune_stage(stage: int, kernel: int, pts: torch.Tensor, iterations: int, reps
                candidates=None) -> dict:
     """Time each candidate shape for one stage and window size on `pts`
     (a [M, N, 3] device frame); install and return the fastest."""
-    cands = candidates or (LAP_CANDIDATES if stage == pl.PL_STAGE_LAPLACIAN else BIL_CANDIDATES).get(
-        kernel, [(8, 32, 1)])
+    bilateral = stage in (pl.PL_STAGE_BILATERAL, pl.PL_STAGE_BILATERAL_SMALL)
+    cands = candidates or (BIL_CANDIDATES if bilateral else LAP_CANDIDATES).get(kernel, [(8, 32, 1)])
     before = pl.pl_tune_get(stage, kernel)
-    if stage == pl.PL_STAGE_BILATERAL:
+    if bilateral:
         n, c = pl.pl_tri_normals(pts)
         out = torch.empty_like(n)
         call = lambda: pl.pl_bilateral(n, c, kernel, 0.1, 0.1, iterations, out=out)
@@ -94,7 +104,8 @@ def autotune(workloads, cache_path: str | None = DEFAULT_CACHE, reps: int = 30) 
     arch = arch_name()
     reps_by = {}
     for pts, kl, il, kb, ib in workloads:
-        for stage, k, it in ((pl.PL_STAGE_LAPLACIAN, kl, il), (pl.PL_STAGE_BILATERAL, kb, ib)):
+        ls, bs = frame_stages(int(pts.shape[0]), int(pts.shape[1]))
+        for stage, k, it in ((ls, kl, il), (bs, kb, ib)):
             key = (stage, k)
             size = int(pts.shape[0]) * int(pts.shape[1])
             if key not in reps_by or size > reps_by[key][1]:
@@ -123,17 +134,18 @@ def tune_frame(workloads, cache_path: str | None = None, reps: int = 40) -> dict
     report = {}
     for frames, kl, lam, il, kb, sl, sa, ib in workloads:
         M, N = int(frames[0].shape[0]), int(frames[0].shape[1])
+        sl_stage, sb_stage = frame_stages(M, N)
         dev = frames[0].device
         plans = [pl.FramePlan(M, N, kl, lam, il, kb, sl, sa, ib, torch.float32, dev)
                  for _ in frames]
         stream = pl._stream(dev)
-        before = (pl.pl_tune_get(pl.PL_STAGE_LAPLACIAN, kl), pl.pl_tune_get(pl.PL_STAGE_BILATERAL, kb))
+        before = (pl.pl_tune_get(sl_stage, kl), pl.pl_tune_get(sb_stage, kb))
         times = {}
         for lc in LAP_CANDIDATES.get(kl, [(8, 32, 1)]):
             for bc in BIL_CANDIDATES.get(kb, [(8, 32, 1)]):
                 try:
-                    pl.pl_tune_set(pl.PL_STAGE_LAPLACIAN, kl, *lc)
-                    pl.pl_tune_set(pl.PL_STAGE_BILATERAL, kb, *bc)
+                    pl.pl_tune_set(sl_stage, kl, *lc)
+                    pl.pl_tune_set(sb_stage, kb, *bc)
                 except pl.PLError:
                     continue
                 for p in plans:          # the workspace size depends on the shapes
@@ -146,19 +158,19 @@ def tune_frame(workloads, cache_path: str | None = None, reps: int = 40) -> dict
                     k[0] += 1
                 times[(lc, bc)] = _time(call, reps)
         if not times:
-            pl.pl_tune_set(pl.PL_STAGE_LAPLACIAN, kl, *before[0])
-            pl.pl_tune_set(pl.PL_STAGE_BILATERAL, kb, *before[1])
+            pl.pl_tune_set(sl_stage, kl, *before[0])
+            pl.pl_tune_set(sb_stage, kb, *before[1])
             continue
         lc, bc = min(times, key=times.get)
-        pl.pl_tune_set(pl.PL_STAGE_LAPLACIAN, kl, *lc)
-        pl.pl_tune_set(pl.PL_STAGE_BILATERAL, kb, *bc)
+        pl.pl_tune_set(sl_stage, kl, *lc)
+        pl.pl_tune_set(sb_stage, kb, *bc)
         ranked = sorted(times.items(), key=lambda x: x[1])[:8]
         common = {"frame": [M, N], "objective": "pl_smooth_frame",
                   "frame_us": round(times[(lc, bc)], 2),
                   "fastest_pairs_us": {f"{a[0]}x{a[1]}/{a[2]} + {b[0]}x{b[1]}/{b[2]}": round(t, 2)
                                        for (a, b), t in ranked}}
-        report[STAGE_NAMES[pl.PL_STAGE_LAPLACIAN] + f"_k{kl}"] = dict(common, best=lc)
-        report[STAGE_NAMES[pl.PL_STAGE_BILATERAL] + f"_k{kb}"] = dict(common, best=bc)
+        report[STAGE_NAMES[sl_stage] + f"_k{kl}"] = dict(common, best=lc)
+        report[STAGE_NAMES[sb_stage] + f"_k{kb}"] = dict(common, best=bc)
     if cache_path:
         save_cache(cache_path, arch, report)
     return report

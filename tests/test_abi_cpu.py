@@ -234,16 +234,20 @@ def test_vertex_update_argument_errors(pl):
 
 
 def test_tuning_table_stages(pl):
-    # four independent tables: single-frame and batched, Laplacian and bilateral
-    saved = {(s, k): pl.pl_tune_get(s, k) for s in range(4) for k in (3, 5)}
+    # six independent tables: single large frames, single small frames and
+    # batches, each for the Laplacian and the bilateral
+    saved = {(s, k): pl.pl_tune_get(s, k) for s in range(6) for k in (3, 5)}
     try:
-        for s in range(4):
+        for s in range(6):
             pl.pl_tune_set(s, 3, 4 + s, 32, 1)
-        for s in range(4):
+        for s in range(6):
             assert pl.pl_tune_get(s, 3) == (4 + s, 32, 1)
         assert pl.pl_tune_get(pl.PL_STAGE_BATCH_BILATERAL, 5) == saved[(3, 5)]
+        assert pl.pl_tune_get(pl.PL_STAGE_BILATERAL_SMALL, 5) == saved[(5, 5)]
         with pytest.raises(pl.PLError):
-            pl.pl_tune_set(4, 3, 8, 32, 1)                   # no such stage
+            pl.pl_tune_set(6, 3, 8, 32, 1)                   # no such stage
+        with pytest.raises(pl.PLError):
+            pl.pl_tune_set(-1, 3, 8, 32, 1)
         with pytest.raises(pl.PLError):
             pl.pl_tune_set(pl.PL_STAGE_BATCH_LAPLACIAN, 3, 8, 32, 0)   # fuse < 1
         with pytest.raises(pl.PLError):

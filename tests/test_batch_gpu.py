@@ -246,11 +246,12 @@ def test_tiling_invariance(pl):
     ref_lap = host(pl.pl_laplacian(pts, 5, 1.0, 4)).copy()
     n, c = pl.pl_tri_normals(dev_t(make_frame("rgbd", 32)))
     ref_bil = host(pl.pl_bilateral(n, c, 3, 0.1, 0.1, 3)[0]).copy()
-    saved = [pl.pl_tune_get(0, 5), pl.pl_tune_get(1, 3), pl.pl_tune_get(1, 5)]
+    # the 64 x 1024 frame reads the small-frame entry
+    saved = [pl.pl_tune_get(4, 5), pl.pl_tune_get(1, 3), pl.pl_tune_get(1, 5)]
     try:
         for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 128, 4), (32, 8, 3)]:
             print("[case] laplacian tile", th, tw, fu, flush=True)
-            pl.pl_tune_set(0, 5, th, tw, fu)
+            pl.pl_tune_set(4, 5, th, tw, fu)
             assert np.array_equal(host(pl.pl_laplacian(pts, 5, 1.0, 4)).view(np.uint8),
                                   ref_lap.view(np.uint8))
         for th, tw, fu in [(4, 64, 1), (16, 16, 2), (8, 32, 3), (2, 128, 1), (16, 32, 1), (16, 32, 2)]:
@@ -271,7 +272,7 @@ def test_tiling_invariance(pl):
                                       refb.view(np.uint8))
             pl.pl_tune_set(1, k, *saved[1 if k == 3 else 2])
     finally:
-        pl.pl_tune_set(0, 5, *saved[0])
+        pl.pl_tune_set(4, 5, *saved[0])
         pl.pl_tune_set(1, 3, *saved[1])
         pl.pl_tune_set(1, 5, *saved[2])
 
@@ -293,20 +294,22 @@ def test_autotune_installs_a_candidate_and_keeps_results(pl, tmp_path):
     from paper_2007_12065_amd import tune
     pts = dev_t(make_frame("rgbd_small", 3))
     ref = host(pl.pl_laplacian(pts, 3, 1.0, 3)).copy()
-    saved = [pl.pl_tune_get(0, 3), pl.pl_tune_get(1, 3)]
+    ls, bs = tune.frame_stages(120, 160)          # a small frame: the *_SMALL entries
+    assert (ls, bs) == (pl.PL_STAGE_LAPLACIAN_SMALL, pl.PL_STAGE_BILATERAL_SMALL)
+    saved = [pl.pl_tune_get(ls, 3), pl.pl_tune_get(bs, 3)]
     try:
         cache = str(tmp_path / "tune.json")
         rep = tune.autotune([(pts, 3, 3, 3, 2)], cache_path=cache, reps=3)
-        assert tuple(rep["laplacian_k3"]["best"]) in tune.LAP_CANDIDATES[3]
-        assert tuple(rep["bilateral_k3"]["best"]) in tune.BIL_CANDIDATES[3]
-        assert pl.pl_tune_get(0, 3) == tuple(rep["laplacian_k3"]["best"])
+        assert tuple(rep["laplacian_small_k3"]["best"]) in tune.LAP_CANDIDATES[3]
+        assert tuple(rep["bilateral_small_k3"]["best"]) in tune.BIL_CANDIDATES[3]
+        assert pl.pl_tune_get(ls, 3) == tuple(rep["laplacian_small_k3"]["best"])
         assert np.array_equal(host(pl.pl_laplacian(pts, 3, 1.0, 3)).view(np.uint8), ref.view(np.uint8))
-        pl.pl_tune_set(0, 3, *saved[0])
+        pl.pl_tune_set(ls, 3, *saved[0])
         assert tune.load_cache(cache) == 2
-        assert pl.pl_tune_get(0, 3) == tuple(rep["laplacian_k3"]["best"])
+        assert pl.pl_tune_get(ls, 3) == tuple(rep["laplacian_small_k3"]["best"])
     finally:
-        pl.pl_tune_set(0, 3, *saved[0])
-        pl.pl_tune_set(1, 3, *saved[1])
+        pl.pl_tune_set(ls, 3, *saved[0])
+        pl.pl_tune_set(bs, 3, *saved[1])
 
 
 def test_autotune_batch_stages(pl, tmp_path):

@@ -71,9 +71,12 @@ class tuned:
         self.pl, self.entries, self.saved = pl, entries, []
 
     def __enter__(self):
+        # a single-frame entry is set for both frame size classes (stage + 4:
+        # the small-frame entry; the random grids here are small frames)
         for stage, kernel, cfg in self.entries:
-            self.saved.append((stage, kernel, self.pl.pl_tune_get(stage, kernel)))
-            self.pl.pl_tune_set(stage, kernel, *cfg)
+            for st in (stage, stage + 4) if stage in (0, 1) else (stage,):
+                self.saved.append((st, kernel, self.pl.pl_tune_get(st, kernel)))
+                self.pl.pl_tune_set(st, kernel, *cfg)
 
     def __exit__(self, *a):
         for stage, kernel, cfg in self.saved:
