@@ -521,6 +521,7 @@ def serving_bench(seconds, host):
     batched = srv.serve(times, kinds, warmup_s=warm)
     plain_srv = PlainServer(classes, host)
     plain = plain_srv.serve(times, kinds, warmup_s=warm)
+    batched["steps_per_frame"] = round(batched.get("steps", 0) / max(len(times), 1), 4)
     out = {"rate_hz": 1500.0, "measured_s": seconds, "pool_per_kind": pool_per_kind,
            "continuous_batching_f16": batched,
            "plain_f32": plain,

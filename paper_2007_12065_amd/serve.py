@@ -9,10 +9,10 @@ continuous batching on one GPU.
 * Execution.  One batch plan (pl_batch_*) spans all slots; each step writes a
   device activity mask selecting the slots admitted since the previous step
   and replays a HIP graph of the whole pipeline captured with that mask.  A
-  step of a single frame (a lightly loaded stream) instead runs the four
-  single-frame calls on that slot's buffers: fewer, smaller launches, and
-  the same output bits (the batched and single-frame paths agree bit for
-  bit).
+  step of a single frame (a lightly loaded stream) instead runs the fused
+  single-frame entry (pl_smooth_frame) on that slot's buffers: three
+  launches sized for one frame, and the same output bits (the batched and
+  single-frame paths agree bit for bit).
 * Continuous batching.  The next step is enqueued as soon as requests are
   waiting, while earlier steps may still be on the GPU: frames that arrive
   during a step join the next one instead of waiting for the queue to drain.
@@ -280,49 +280,65 @@ class GpuBatchExecutor:
 
     @staticmethod
     def single_bytes(pl, c, normal_bytes: int) -> int:
-        """Device bytes of one class's scratch for single-frame steps: the raw
-        normals and the three calls' workspaces."""
-        T = 2 * (c.M - 1) * (c.N - 1)
+        """Device bytes of one class's scratch for single-frame steps: the
+        fused entry's workspace."""
+        return GpuBatchExecutor._frame_ws_bytes(pl, c, normal_bytes) + 256
+
+    @staticmethod
+    def _frame_ws_bytes(pl, c, normal_bytes: int) -> int:
+        f = pl.PLFrame()
+        f.M, f.N = c.M, c.N
+        f.kernel_lap, f.iters_lap, f.lambda_ = c.kernel_lap, c.iters_lap, c.lam
+        f.kernel_bil, f.iters_bil = c.kernel_bil, c.iters_bil
+        f.sigma_length, f.sigma_angle = c.sigma_length, c.sigma_angle
+        # the size query reads no buffer: distinct, aligned, non-overlapping
+        # stand-in addresses are enough
+        for i, name in enumerate(("pts", "pts_out", "normals", "centroids", "tri_map",
+                                  "triangles", "n_tri", "normals_T")):
+            setattr(f, name, (i + 1) << 36)
         ndt = pl.PL_F32 if normal_bytes == 4 else pl.PL_F16
-        return (3 * T * normal_bytes + pl._lib.pl_mesh_opc_workspace(c.M, c.N)
-                + pl._lib.pl_laplacian_workspace(c.M, c.N, c.iters_lap)
-                + pl._lib.pl_bilateral_workspace(c.M, c.N, ndt, c.iters_bil) + 4 * 256)
+        n = pl._lib.pl_smooth_frame_workspace(pl.ctypes.byref(f), ndt)
+        if n == 0:
+            raise pl.PLError(-1, "pl_smooth_frame_workspace")
+        return int(n)
 
     def _single_scratch(self, cls: str):
         torch, pl = self.torch, self.pl
         if cls not in self.single:
             c = self.classes[cls]
-            ndt = pl._ndt(self.ndtype)
-            e = lambda n: torch.empty(max(n, 1), dtype=torch.uint8, device=self.dev)
-            sizes = (pl._lib.pl_mesh_opc_workspace(c.M, c.N),
-                     pl._lib.pl_laplacian_workspace(c.M, c.N, c.iters_lap),
-                     pl._lib.pl_bilateral_workspace(c.M, c.N, ndt, c.iters_bil))
-            raw = torch.empty((c.M - 1, c.N - 1, 2, 3), dtype=self.ndtype, device=self.dev)
-            self.single[cls] = (raw, [e(n) for n in sizes], sizes, ndt)
+            nb = 2 if self.ndtype == torch.float16 else 4
+            n = self._frame_ws_bytes(pl, c, nb)
+            self.single[cls] = (torch.empty(n, dtype=torch.uint8, device=self.dev), n)
         return self.single[cls]
 
-    def run_single(self, index: int) -> None:
-        """The four single-frame calls for slot `index`, into its outputs."""
+    def _slot_frame(self, index: int):
+        """The fused entry's frame descriptor for slot `index` (its input
+        and the plan's outputs for it), built once per plan."""
         pl = self.pl
         c = self.classes[self.slot_cls[index]]
-        raw, ws, sizes, ndt = self._single_scratch(self.slot_cls[index])
         o = self.batch.outputs[index]
-        x = self.inputs[index]
-        st = pl._stream(self.dev)
-        P = lambda t: pl._ptr(t)
-        T = 2 * (c.M - 1) * (c.N - 1)
-        pl._check(pl._lib.pl_mesh_opc(P(x), c.M, c.N, P(o["tri_valid"]), P(o["tri_map"]),
-                                      P(o["triangles"]), P(o["halfedges"]), T, P(o["n_tri"]),
-                                      P(ws[0]) if sizes[0] else None, sizes[0], st), "pl_mesh_opc")
-        pl._check(pl._lib.pl_laplacian(P(x), P(o["points"]), c.M, c.N, c.kernel_lap, c.lam,
-                                       c.iters_lap, P(ws[1]) if sizes[1] else None, sizes[1], st),
-                  "pl_laplacian")
-        pl._check(pl._lib.pl_tri_normals(P(o["points"]), c.M, c.N, P(raw), ndt, P(o["centroids"]), st),
-                  "pl_tri_normals")
-        pl._check(pl._lib.pl_bilateral(P(raw), P(o["centroids"]), ndt, c.M, c.N, c.kernel_bil,
-                                       c.sigma_length, c.sigma_angle, c.iters_bil, P(o["normals"]),
-                                       P(o["tri_map"]), P(o["normals_T"]),
-                                       P(ws[2]) if sizes[2] else None, sizes[2], st), "pl_bilateral")
+        f = pl.PLFrame()
+        f.M, f.N = c.M, c.N
+        f.kernel_lap, f.iters_lap, f.lambda_ = c.kernel_lap, c.iters_lap, c.lam
+        f.kernel_bil, f.iters_bil = c.kernel_bil, c.iters_bil
+        f.sigma_length, f.sigma_angle = c.sigma_length, c.sigma_angle
+        f.pts = self.inputs[index].data_ptr()
+        for key, field in (("points", "pts_out"), ("normals", "normals"),
+                           ("centroids", "centroids"), ("tri_valid", "tri_valid"),
+                           ("tri_map", "tri_map"), ("triangles", "triangles"),
+                           ("halfedges", "halfedges"), ("n_tri", "n_tri"),
+                           ("normals_T", "normals_T")):
+            setattr(f, field, o[key].data_ptr() if o[key] is not None else None)
+        return f
+
+    def run_single(self, index: int) -> None:
+        """Slot `index` alone through the fused single-frame entry
+        (pl_smooth_frame, a few launches), into its outputs: the same bits
+        as a batched step."""
+        pl = self.pl
+        ws, n = self._single_scratch(self.slot_cls[index])
+        pl._check(pl._lib.pl_smooth_frame(pl.ctypes.byref(self.frames[index]), pl._ndt(self.ndtype),
+                                          pl._ptr(ws), n, pl._stream(self.dev)), "pl_smooth_frame")
 
     def alloc(self, cls: str) -> None:
         c = self.classes[cls]
@@ -343,15 +359,7 @@ class GpuBatchExecutor:
         self.n = len(specs)
         for cls in set(self.slot_cls):        # scratch for one-frame steps, allocated up front
             self._single_scratch(cls)
-        # each slot's single-frame calls as a graph of their own (one launch
-        # from the host per one-frame step)
-        self.single_graphs = []
-        side = torch.cuda.Stream(self.dev)
-        for i in range(self.n):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=side):
-                self.run_single(i)
-            self.single_graphs.append(g)
+        self.frames = [self._slot_frame(i) for i in range(self.n)]
         self.mask_dev = torch.zeros(self.n, dtype=torch.uint8, device=self.dev)
         # the pinned mask of a step is reused max_inflight + 1 steps later,
         # when that step has been retired
@@ -387,7 +395,7 @@ class GpuBatchExecutor:
             # stream (no cross-stream wait), as the plain path does
             s, r = members[0]
             self.inputs[s.index].copy_(self.host[r.cls][r.frame], non_blocking=True)
-            self.single_graphs[s.index].replay()
+            self.run_single(s.index)
         else:
             dsts, srcs = [], []
             with self.torch.cuda.stream(self.copy_stream):
