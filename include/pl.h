@@ -283,8 +283,8 @@ pl_status pl_vertex_update(const float *pts_in, float *pts_out, int32_t M, int32
  *            processed (e.g. pl_mesh_opc's count).
  * halfedges  int32 [3 cap] output; entries at or past 3 min(*n_tri, cap) are
  *            left untouched.
- * Workspace: pl_user_halfedges_workspace(cap) bytes (a table of at least
- * 6 cap slots of 16 bytes; 0 when cap = 0).  PL_ERR_ARG / PL_ERR_SHAPE /
+ * Workspace: pl_user_halfedges_workspace(cap) bytes (a table of 4 cap slots
+ * of 16 bytes and one slot index per half-edge; 0 when cap = 0).  PL_ERR_ARG / PL_ERR_SHAPE /
  * PL_ERR_WORKSPACE / PL_ERR_ALIAS on invalid arguments (nothing enqueued).
  * Three launches on `stream`, no allocation, graph-capturable.
  */

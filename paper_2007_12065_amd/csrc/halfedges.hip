@@ -8,20 +8,27 @@
 // lowest-index half-edge keyed (b, a).  Half-edges from a point to itself
 // are never paired.
 //
-// The table is keyed by the undirected edge (lo, hi), lo < hi, and each slot
-// holds two values: the first half-edge running lo -> hi and the first
-// running hi -> lo.  Three launches:
+// The table is keyed by the undirected edge (lo, hi), lo < hi; a slot (16
+// bytes, one cache line holds eight) keeps the key and two values: the
+// first half-edge running lo -> hi and the first running hi -> lo.  Three
+// launches:
 //   k_he_clear    every slot of the table empty (a kernel, so the sequence
 //                 can be captured into a graph)
-//   k_he_insert   one thread per triangle: each half-edge claims its edge's
-//                 slot (64-bit compare-and-swap, linear probing) and lowers
-//                 its direction's value to its index (atomic min), so every
-//                 slot ends with the first index of each direction whatever
-//                 the order of the threads
-//   k_he_lookup   one thread per triangle: a half-edge that is the first of
-//                 its direction takes the other direction's value
-// The table has at least twice as many slots as half-edges (load <= 1/2),
-// so every probe sequence meets its key or an empty slot.
+//   k_he_insert   one thread per half-edge: it claims its edge's
+//                 slot (64-bit compare-and-swap, linear probing), lowers its
+//                 direction's value to its index (atomic min, in the same
+//                 line as the key), so every slot ends with the first index
+//                 of each direction whatever the order of the threads, and
+//                 records the slot it found
+//   k_he_lookup   one thread per half-edge: a half-edge that is the first of
+//                 its direction takes the other direction's value from its
+//                 recorded slot (one read, no probing)
+// The table has 4 cap slots (rounded up to 64), at least 4/3 as many as
+// half-edges (load <= 3/4), so every probe sequence meets its key or an
+// empty slot.  Hash values are reduced to a slot by a 64 x 64-bit high
+// product, which needs no power-of-two size.  Triangles are dealt to
+// workgroups in contiguous runs per XCD, so the two triangles of an edge in
+// an organized mesh, a row apart, usually run under the same L2.
 //
 // Probing reads a slot before it tries an atomic on it: only an empty slot
 // or the edge's own key is worth a compare-and-swap.
@@ -36,6 +43,11 @@ namespace {
 
 constexpr int kHeBlock = 256;
 constexpr unsigned long long kEmpty = ~0ull;   // (-1, -1): lo == hi, never inserted
+
+struct alignas(16) HeSlot {
+    unsigned long long key;
+    int fwd, bwd;                    // first half-edge lo -> hi, hi -> lo
+};
 
 __device__ __forceinline__ unsigned long long he_key(int lo, int hi) {
     return ((unsigned long long)(unsigned)lo << 32) | (unsigned)hi;
@@ -52,105 +64,102 @@ __device__ __forceinline__ unsigned long long he_mix(unsigned long long k) {
     return k;
 }
 
-__device__ __forceinline__ size_t he_slot(int lo, int hi, size_t mask) {
-    return (size_t)he_mix(he_key(lo, hi)) & mask;
+// hash in [0, 2^64) scaled to [0, slots)
+__device__ __forceinline__ unsigned long long he_slot(unsigned long long key,
+                                                      unsigned long long slots) {
+    return __umul64hi(he_mix(key), slots);
 }
 
 size_t table_slots(int cap) {
-    size_t s = 256;
-    while (s < 6 * (size_t)cap) s <<= 1;
-    return s;
+    const size_t s = (4 * (size_t)cap + 63) / 64 * 64;
+    return s < 256 ? 256 : s;
 }
 
-__global__ __launch_bounds__(kHeBlock) void k_he_clear(unsigned long long *__restrict__ keys,
-                                                       int2 *__restrict__ vals, size_t slots) {
+__global__ __launch_bounds__(kHeBlock) void k_he_clear(HeSlot *__restrict__ tab, size_t slots) {
     for (size_t i = (size_t)blockIdx.x * kHeBlock + threadIdx.x; i < slots;
          i += (size_t)gridDim.x * kHeBlock) {
-        keys[i] = kEmpty;
-        vals[i] = make_int2(INT_MAX, INT_MAX);
+        HeSlot e;
+        e.key = kEmpty;
+        e.fwd = INT_MAX;
+        e.bwd = INT_MAX;
+        tab[i] = e;
     }
 }
 
 __global__ __launch_bounds__(kHeBlock) void k_he_insert(const int32_t *__restrict__ tris,
                                                         const int32_t *__restrict__ n_tri,
-                                                        int cap,
-                                                        unsigned long long *__restrict__ keys,
-                                                        int2 *__restrict__ vals, size_t mask) {
-    const int n = min(max(*n_tri, 0), cap);
-    const int t = (int)blockIdx.x * kHeBlock + (int)threadIdx.x;
-    if (t >= n) return;
-    const int v[3] = {tris[3 * (size_t)t], tris[3 * (size_t)t + 1], tris[3 * (size_t)t + 2]};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int a = v[j], b = v[(j + 1) % 3];
-        if (a == b) continue;
+                                                        int cap, HeSlot *__restrict__ tab,
+                                                        unsigned long long slots,
+                                                        int32_t *__restrict__ hslot) {
+    // one thread per half-edge: the three of a triangle run side by side
+    const int n = 3 * min(max(*n_tri, 0), cap);
+    const int h = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kHeBlock + (int)threadIdx.x;
+    if (h >= n) return;
+    const int t = h / 3, j = h - 3 * t;
+    const int a = tris[h], b = tris[3 * t + (j == 2 ? 0 : j + 1)];
+    int found = -1;
+    if (a != b) {
         const int lo = min(a, b), hi = max(a, b);
         const unsigned long long key = he_key(lo, hi);
-        size_t slot = he_slot(lo, hi, mask);
+        unsigned long long slot = he_slot(key, slots);
         for (;;) {
             // a plain read first: only an empty slot or the key itself is
             // worth an atomic
-            const unsigned long long seen = __hip_atomic_load(&keys[slot], __ATOMIC_RELAXED,
+            const unsigned long long seen = __hip_atomic_load(&tab[slot].key, __ATOMIC_RELAXED,
                                                               __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long prev =
-                seen == kEmpty ? atomicCAS(&keys[slot], kEmpty, key) : seen;
+                seen == kEmpty ? atomicCAS(&tab[slot].key, kEmpty, key) : seen;
             if (prev == kEmpty || prev == key) {
-                int *dir = a < b ? &vals[slot].x : &vals[slot].y;
-                atomicMin(dir, 3 * t + j);
+                atomicMin(a < b ? &tab[slot].fwd : &tab[slot].bwd, h);
+                found = (int)slot;
                 break;
             }
-            slot = (slot + 1) & mask;
+            slot = slot + 1 == slots ? 0 : slot + 1;
         }
     }
+    hslot[h] = found;
 }
 
 __global__ __launch_bounds__(kHeBlock) void k_he_lookup(const int32_t *__restrict__ tris,
                                                         const int32_t *__restrict__ n_tri,
-                                                        int cap,
-                                                        const unsigned long long *__restrict__ keys,
-                                                        const int2 *__restrict__ vals, size_t mask,
+                                                        int cap, const HeSlot *__restrict__ tab,
+                                                        const int32_t *__restrict__ hslot,
                                                         int32_t *__restrict__ he) {
-    const int n = min(max(*n_tri, 0), cap);
-    const int t = (int)blockIdx.x * kHeBlock + (int)threadIdx.x;
-    if (t >= n) return;
-    const int v[3] = {tris[3 * (size_t)t], tris[3 * (size_t)t + 1], tris[3 * (size_t)t + 2]};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int a = v[j], b = v[(j + 1) % 3];
-        int twin = -1;
-        if (a != b) {
-            const int lo = min(a, b), hi = max(a, b);
-            const unsigned long long key = he_key(lo, hi);
-            size_t slot = he_slot(lo, hi, mask);
-            while (keys[slot] != key) slot = (slot + 1) & mask;   // inserted above: present
-            const int2 f = vals[slot];
-            const int own = a < b ? f.x : f.y, other = a < b ? f.y : f.x;
-            if (own == 3 * t + j && other != INT_MAX) twin = other;
-        }
-        he[3 * (size_t)t + j] = twin;
+    const int n = 3 * min(max(*n_tri, 0), cap);
+    const int h = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kHeBlock + (int)threadIdx.x;
+    if (h >= n) return;
+    const int sl = hslot[h];
+    int twin = -1;
+    if (sl >= 0) {
+        const int t = h / 3, j = h - 3 * t;
+        const int a = tris[h], b = tris[3 * t + (j == 2 ? 0 : j + 1)];
+        const int2 f = *reinterpret_cast<const int2 *>(&tab[sl].fwd);
+        const int own = a < b ? f.x : f.y, other = a < b ? f.y : f.x;
+        if (own == h && other != INT_MAX) twin = other;
     }
+    he[h] = twin;
 }
 
 }  // namespace
 
 size_t user_halfedges_workspace(int cap) {
-    const size_t s = table_slots(cap);
-    return align_up(8 * s, 256) + align_up(8 * s, 256);
+    return align_up(sizeof(HeSlot) * table_slots(cap), 256) + align_up(12 * (size_t)cap, 256);
 }
 
 pl_status launch_user_halfedges(const int32_t *tris, const int32_t *n_tri, int cap, int32_t *he,
                                 void *ws, hipStream_t s) {
     if (cap == 0) return PL_OK;
     const size_t slots = table_slots(cap);
-    auto *keys = static_cast<unsigned long long *>(ws);
-    auto *vals = reinterpret_cast<int2 *>(static_cast<uint8_t *>(ws) + align_up(8 * slots, 256));
+    auto *tab = static_cast<HeSlot *>(ws);
+    auto *hslot = reinterpret_cast<int32_t *>(static_cast<uint8_t *>(ws) +
+                                              align_up(sizeof(HeSlot) * slots, 256));
     const int clear_grid = (int)std::min<size_t>(4096, (slots + kHeBlock - 1) / kHeBlock);
-    k_he_clear<<<clear_grid, kHeBlock, 0, s>>>(keys, vals, slots);
+    k_he_clear<<<clear_grid, kHeBlock, 0, s>>>(tab, slots);
     if (pl_status st = hip_check(hipGetLastError(), "k_he_clear")) return st;
-    const int grid = (cap + kHeBlock - 1) / kHeBlock;
-    k_he_insert<<<grid, kHeBlock, 0, s>>>(tris, n_tri, cap, keys, vals, slots - 1);
+    const int grid = (int)((3 * (size_t)cap + kHeBlock - 1) / kHeBlock);
+    k_he_insert<<<grid, kHeBlock, 0, s>>>(tris, n_tri, cap, tab, slots, hslot);
     if (pl_status st = hip_check(hipGetLastError(), "k_he_insert")) return st;
-    k_he_lookup<<<grid, kHeBlock, 0, s>>>(tris, n_tri, cap, keys, vals, slots - 1, he);
+    k_he_lookup<<<grid, kHeBlock, 0, s>>>(tris, n_tri, cap, tab, hslot, he);
     return hip_check(hipGetLastError(), "k_he_lookup");
 }
 

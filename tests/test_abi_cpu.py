@@ -207,7 +207,7 @@ def test_user_halfedges_host_side(pl):
     lib = pl._lib
     assert lib.pl_user_halfedges_workspace(0) == 0
     assert lib.pl_user_halfedges_workspace(-1) == 0
-    assert lib.pl_user_halfedges_workspace(1000) >= 6 * 1000 * 12
+    assert lib.pl_user_halfedges_workspace(1000) >= 4 * 1000 * 16 + 12 * 1000
     assert lib.pl_user_halfedges_workspace(1 << 30) == 0
     ws = lib.pl_user_halfedges_workspace(100)
     D = 0x400000
