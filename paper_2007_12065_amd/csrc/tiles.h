@@ -679,17 +679,17 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // float32 values) before scaling; expanding them or pre-scaling the
 // centroids saves instructions but costs ~1e-5 relative weight accuracy.
 //
-// Eq. 6 renormalises, so a common factor of the weights cancels: both
-// triangles of a quad take w = 2^(m - e) with m = min(e01, 52), e01 the pair
-// exponent between the two (the same value in exact arithmetic).  The other
-// triangle of a quad is usually as close as its nearest neighbour, so the
-// largest weights stay near 1; with e >= 0 no weight exceeds 2^52, which keeps
-// the sums and the squared norm of Eq. 6 finite for windows up to 9 x 9
-// (160 neighbours).  If the total still drops below 2^-60 (every neighbour
-// far beyond the quad's own pair), that triangle is recomputed with every
-// exponent shifted by the smallest one, which puts the largest term at 1.
-// Such triangles are isolated ones (a few per thousand on the LiDAR frames,
-// which put one in about a tenth of the waves), so instead of the lane
+// Eq. 6 renormalises, so a common factor of the weights cancels: every
+// weight is taken as w = 2^(48 - e) (the same value in exact arithmetic).
+// The shift is a constant, so a pair's weight does not depend on which of
+// its triangles is being filtered; with e >= 0 no weight exceeds 2^48, which
+// keeps the sums and the squared norm of Eq. 6 finite for windows up to
+// 9 x 9 (160 neighbours), and terms down to e = 174 stay normal floats.  If
+// the total drops below 2^-60 (every neighbour at e > 108), that triangle is
+// recomputed with every exponent shifted by the smallest one, which puts the
+// largest term at 1.
+// Such triangles are isolated ones (about 7 per thousand on the LiDAR
+// frames, 4 per 10^4 on the RGB-D ones), so instead of the lane
 // redoing its window alone -- which held up its whole wave -- the lane
 // queues the triangle in LDS, and after the sweep one wave per queued
 // triangle takes its neighbours over the wave's lanes: the smallest exponent
@@ -719,7 +719,7 @@ constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
 // register budget of the bilateral kernels: at least 6 waves per SIMD
 // (<= 80 VGPRs), more than the LDS of a typical tile lets reside anyway
 constexpr int kBilWavesPerSimd = 6;
-constexpr float kBilShiftCap = 52.f;
+constexpr float kBilShift = 48.f;                 // every weight is 2^(48 - e)
 constexpr int kBilMaxSweeps = 8;                  // fused sweeps per launch at most
 __host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW) {
     return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) +
@@ -787,36 +787,35 @@ __device__ __forceinline__ float4 bil_finish(BilAcc s, float4 cur) {
                        round_storage<NT>(s.z * k), cur.w);
 }
 
-// The own triangles of the quad at LDS index a and their common shift.
-struct BilQuad {
-    float4 c0, c1, n0, n1;
-    BilOwn o0, o1;
-    float m;
-};
-
-__device__ __forceinline__ BilQuad bil_quad(const float4 *sc, const float4 *sn, int a, int plane,
-                                            float ka, float kb) {
-    BilQuad q;
-    q.c0 = sc[a]; q.c1 = sc[plane + a];
-    q.n0 = sn[a]; q.n1 = sn[plane + a];
-    q.o0 = BilOwn{q.c0.x, q.c0.y, q.c0.z, q.n0.x, q.n0.y, q.n0.z, ka, kb};
-    q.o1 = BilOwn{q.c1.x, q.c1.y, q.c1.z, q.n1.x, q.n1.y, q.n1.z, ka, kb};
-    // e01 is symmetric; NaN (both missing) or +inf (one missing) gives the cap
-    q.m = fminf(bil_pair_e(q.o0, q.c1, q.n1), kBilShiftCap);
-    return q;
+// Weight of a triangle pair (Eqs. 4-5 with log2(e) folded into ka and kb),
+// shifted by the constant 2^48: 2^(48 - e).  The value depends on the pair
+// only: swapping the triangles changes the sign of every difference exactly
+// and none of the squares.  A pair with an off-grid or missing triangle has
+// e = +inf and weight 0 (NaN only when both are missing; no sum uses that).
+__device__ __forceinline__ float bil_w(const float4 ci, const float4 ni, const float4 cj,
+                                       const float4 nj, float ka, float kb) {
+    const float ax = ni.x - nj.x, ay = ni.y - nj.y, az = ni.z - nj.z;
+    const float dn2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
+    const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+    const float dc2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    return __builtin_amdgcn_exp2f(-fmaf(dc2, ka, fmaf(dn2, kb, -kBilShift)));
 }
 
-// Eq. 6 for both triangles of a quad, missing triangles copied through;
-// pend0 / pend1: the sum underflowed (the triangle goes to the queue and
-// r0 / r1 are not set).
+// s += w n
+__device__ __forceinline__ void bil_acc(BilAcc &s, float w, const float4 n) {
+    s.w += w;
+    s.x = fmaf(w, n.x, s.x);
+    s.y = fmaf(w, n.y, s.y);
+    s.z = fmaf(w, n.z, s.z);
+}
+
+// Eq. 6 for one triangle: a missing one (c.w = 0) is copied through; pend:
+// the sum underflowed (the triangle goes to the queue and r is not set).
 template <typename NT>
-__device__ __forceinline__ void bil_close(const BilQuad &q, BilAcc s0, BilAcc s1, float4 &r0,
-                                          float4 &r1, bool &pend0, bool &pend1) {
-    const bool ok0 = q.c0.w != 0.f, ok1 = q.c1.w != 0.f;
-    pend0 = ok0 && !(s0.w >= kBilUnderflow);
-    pend1 = ok1 && !(s1.w >= kBilUnderflow);
-    r0 = ok0 ? bil_finish<NT>(s0, q.n0) : q.n0;
-    r1 = ok1 ? bil_finish<NT>(s1, q.n1) : q.n1;
+__device__ __forceinline__ float4 bil_close(const float4 c, const float4 n, BilAcc s, bool &pend) {
+    const bool ok = c.w != 0.f;
+    pend = ok && !(s.w >= kBilUnderflow);
+    return ok ? bil_finish<NT>(s, n) : n;
 }
 
 __device__ __forceinline__ float wave_min_f(float x) {
@@ -907,6 +906,9 @@ __device__ __forceinline__ void bil_push(const BilQueue &qu, int a, int k, int s
 #define PL_BIL_PARTS_K5 4
 #endif
 template <int R> constexpr int bil_parts() { return R == 1 ? PL_BIL_PARTS_K3 : PL_BIL_PARTS_K5; }
+static_assert(bil_ndplus<1>() % PL_BIL_PARTS_K3 == 0 && bil_ndplus<2>() % PL_BIL_PARTS_K5 == 0 &&
+                  bil_ndplus<3>() % PL_BIL_PARTS_K5 == 0 && bil_ndplus<4>() % PL_BIL_PARTS_K5 == 0,
+              "the lanes of a quad share |D+| evenly");
 
 template <int P>
 __device__ __forceinline__ BilAcc bil_reduce(BilAcc s) {
@@ -920,38 +922,65 @@ __device__ __forceinline__ BilAcc bil_reduce(BilAcc s) {
     return s;
 }
 
-// Both triangles of the quad at LDS index a, in the fixed summation order;
-// `part` is the lane's share (0 .. bil_parts<R>() - 1).  Every lane of the
-// quad returns the same r0, r1 (and pending flags: see bil_close).
+// Both triangles of the quad at LDS index a, in the fixed summation order:
+// for each d of D+ (this lane's share `part` of them), the two triangles of
+// quad a + d, then the two of quad a - d; the lanes' partial sums are added
+// in a fixed tree.  A pair weight takes its lower quad's triangle first
+// (bil_w is symmetric anyway).  Every lane of the quad returns the same r0,
+// r1 and pending flags.
 template <int R, typename NT>
-__device__ __forceinline__ void bil_filter_quad(const float4 *sc, const float4 *sn, int a,
+__device__ __forceinline__ void bil_sum_quad(const float4 *sc, const float4 *sn, int a,
                                                 int pitch, int plane, float ka, float kb,
                                                 int part, float4 &r0, float4 &r1, bool &pend0,
                                                 bool &pend1) {
-    constexpr int P = bil_parts<R>();
-    const BilQuad q = bil_quad(sc, sn, a, plane, ka, kb);
+    constexpr int ND = bil_ndplus<R>(), P = bil_parts<R>();
+    const float4 c0 = sc[a], c1 = sc[plane + a], n0 = sn[a], n1 = sn[plane + a];
     BilAcc s0{0.f, 0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-    for (int i = part; i < bil_ndplus<R>(); i += P) {
+    for (int j = 0; j < ND / P; ++j) {
+        const int i = j * P + part;
         int dy, dx;
         bil_dplus<R>(i, dy, dx);
         const int off = dy * pitch + dx;
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {        // quad a + d, then quad a - d
-            const int b = side == 0 ? a + off : a - off;
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                const float4 c = sc[b + kk * plane], n = sn[b + kk * plane];
-                bil_add(s0, q.m, bil_pair_e(q.o0, c, n), n);
-                bil_add(s1, q.m, bil_pair_e(q.o1, c, n), n);
-            }
-        }
+        const int bp = a + off, bm = a - off;
+        const float4 pc0 = sc[bp], pc1 = sc[plane + bp], p0 = sn[bp], p1 = sn[plane + bp];
+        const float4 mc0 = sc[bm], mc1 = sc[plane + bm], m0 = sn[bm], m1 = sn[plane + bm];
+        bil_acc(s0, bil_w(c0, n0, pc0, p0, ka, kb), p0);
+        bil_acc(s0, bil_w(c0, n0, pc1, p1, ka, kb), p1);
+        bil_acc(s0, bil_w(mc0, m0, c0, n0, ka, kb), m0);
+        bil_acc(s0, bil_w(mc1, m1, c0, n0, ka, kb), m1);
+        bil_acc(s1, bil_w(c1, n1, pc0, p0, ka, kb), p0);
+        bil_acc(s1, bil_w(c1, n1, pc1, p1, ka, kb), p1);
+        bil_acc(s1, bil_w(mc0, m0, c1, n1, ka, kb), m0);
+        bil_acc(s1, bil_w(mc1, m1, c1, n1, ka, kb), m1);
     }
     if constexpr (P > 1) {
         s0 = bil_reduce<P>(s0);
         s1 = bil_reduce<P>(s1);
     }
-    bil_close<NT>(q, s0, s1, r0, r1, pend0, pend1);
+    r0 = bil_close<NT>(c0, n0, s0, pend0);
+    r1 = bil_close<NT>(c1, n1, s1, pend1);
+}
+
+// One sweep over the OH x OW region at (oy0, ox0) of the staged tile;
+// out(ry, rx, a, r0, r1, pend0, pend1) takes each quad's results (ry, rx
+// within the region).  Ends with a barrier.
+template <int R, typename NT, typename Out>
+__device__ __forceinline__ void bil_sweep(const float4 *sc, const float4 *sn, int pitch, int plane,
+                                          int oy0, int ox0, int OH, int OW, float ka, float kb,
+                                          Out &&out) {
+    constexpr int P = bil_parts<R>();
+    const int slot = (int)threadIdx.x / P, part = (int)threadIdx.x % P;
+    const DivBy byOW(OW);
+    for (int idx = slot; idx < OH * OW; idx += kTileBlock / P) {
+        const int ry = byOW.div(idx), rx = idx - ry * OW;
+        const int a = (oy0 + ry) * pitch + ox0 + rx;
+        float4 r0, r1;
+        bool p0, p1;
+        bil_sum_quad<R, NT>(sc, sn, a, pitch, plane, ka, kb, part, r0, r1, p0, p1);
+        out(ry, rx, a, r0, r1, p0, p1);
+    }
+    __syncthreads();
 }
 
 // FromPts: the raw normals and centroids are not read but computed here from
@@ -1023,20 +1052,12 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     // intermediate sweeps: LDS to LDS over the shrinking exact region
     for (int f = 1; f < F; ++f) {
         const int lo = R * f;
-        const int Hf = H - 2 * lo, Wf = W - 2 * lo;
-        const DivBy byWf(Wf);
-        for (int idx = slot; idx < Hf * Wf; idx += kTileBlock / P) {
-            const int ry = byWf.div(idx);
-            const int a = (lo + ry) * W + lo + (idx - ry * Wf);
-            float4 r0, r1;
-            bool p0, p1;
-            bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, part, r0, r1, p0, p1);
-            if (part == 0) {
-                if (p0) bil_push(qu, a, 0, f); else nxt[a] = r0;
-                if (p1) bil_push(qu, a, 1, f); else nxt[S + a] = r1;
-            }
-        }
-        __syncthreads();
+        bil_sweep<R, NT>(s_c, cur, W, S, lo, lo, H - 2 * lo, W - 2 * lo, ka, kb,
+                         [&](int, int, int a, float4 r0, float4 r1, bool p0, bool p1) {
+                             if (part != 0) return;
+                             if (p0) bil_push(qu, a, 0, f); else nxt[a] = r0;
+                             if (p1) bil_push(qu, a, 1, f); else nxt[S + a] = r1;
+                         });
         const int nq = qu.count[f];
         for (int e = wave; e < nq; e += kTileBlock / kWave) {
             const int a = qu.entry[e] >> 1, k = qu.entry[e] & 1;
@@ -1050,17 +1071,12 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     }
 
     // last sweep (or the copy when F = 0): the tile itself, to global memory
-    const DivBy byTQW(TQW);
-    for (int idx = slot; idx < TQH * TQW; idx += kTileBlock / P) {
-        const int ty = byTQW.div(idx), tx = idx - ty * TQW;
+    auto emit = [&](int ty, int tx, int a, float4 r0, float4 r1, bool p0, bool p1) {
         const int qy = qy0 + ty, qx = qx0 + tx;
-        if (qy >= Mq || qx >= Nq) continue;
+        if (part != 0 || qy >= Mq || qx >= Nq) return;   // the quad's first lane stores
         const size_t q = (size_t)qy * Nq + qx;
-        const int a = (ty + halo) * W + tx + halo;
-        float4 r[2];
-        bool pend[2] = {false, false};
-        if (F > 0) bil_filter_quad<R, NT>(s_c, cur, a, W, S, ka, kb, part, r[0], r[1], pend[0], pend[1]);
-        if (part != 0) continue;             // the quad's first lane stores
+        const float4 r[2] = {r0, r1};
+        const bool pend[2] = {p0, p1};
         NT v[6];
         NT raw[6];                           // raw normals as stored (FromPts)
         if constexpr (FromPts) {
@@ -1115,10 +1131,20 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
 #pragma unroll
             for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t1 + i], v[3 + i]);
         }
+    };
+    if (F > 0) {
+        bil_sweep<R, NT>(s_c, cur, W, S, halo, halo, TQH, TQW, ka, kb, emit);
+    } else {
+        const DivBy byTQW(TQW);
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int idx = slot; idx < TQH * TQW; idx += kTileBlock / P) {
+            const int ty = byTQW.div(idx);
+            emit(ty, idx - ty * TQW, 0, z, z, false, false);
+        }
     }
     if (F > 0) {
-        // the queued triangles of the last sweep, one wave each
-        __syncthreads();
+        // the queued triangles of the last sweep, one wave each (the sweep
+        // ended with a barrier)
         const int nq = qu.count[F];
         for (int e = wave; e < nq; e += kTileBlock / kWave) {
             const int a = qu.entry[e] >> 1, k = qu.entry[e] & 1;
