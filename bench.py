@@ -48,7 +48,7 @@ TUNE_FILE = os.path.join(ROOT, "profiles", "tune.json")
 #  squared distance 3, rsqrt 4, weight sum 1, weighted sum 3; then 1/W 4 and
 #  the update 4.
 #  Bilateral, per triangle and sweep, per neighbour: two squared differences
-#  12, exponent 2, shift 1, exp2 4, accumulation 4; then renormalisation 10.
+#  12, exponent 2, exp2 4, accumulation 4; then renormalisation 10.
 #  Centroid and normal of a triangle: 31.
 
 
@@ -57,7 +57,7 @@ def lap_lane_ops(kernel):
 
 
 def bil_lane_ops(kernel):
-    return 2 * (kernel * kernel - 1) * 23 + 10
+    return 2 * (kernel * kernel - 1) * 22 + 10
 
 
 GEOM_LANE_OPS = 31
@@ -337,9 +337,11 @@ def ga_bench(plans, stream, reps=200, level=4, stride=1):
 
 def user_halfedges_bench(plans, stream, reps=100):
     """Half-edges of a user mesh (Sec. 4.3) on each frame's T taken as a
-    user-provided triangle list: per-call device time (graph replays) of the three launches (table
-    clear, insert, lookup), half-edges per second, and the oracle's rate
-    (sort and binary searches, one thread) on the same triangles."""
+    user-provided triangle list: per-call device time (graph replays) of the
+    partitioned way's five launches (bucket counts, their scan, the scatter
+    into bucket regions, the per-bucket LDS tables, the fallback check),
+    half-edges per second, and the oracle's rate (sort and binary searches,
+    one thread) on the same triangles."""
     import numpy as np
     import torch
 
@@ -364,8 +366,9 @@ def user_halfedges_bench(plans, stream, reps=100):
     t0 = time.perf_counter()
     oracle.user_halfedges(T)
     cpu_s = time.perf_counter() - t0
-    return {"kernels": ["k_he_clear", "k_he_insert", "k_he_lookup"], "call_us": round(us, 2),
-            "halfedges_per_s": round(3 * n_tri / (us * 1e-6), 1), "table_bytes": int(ws_n),
+    return {"kernels": ["k_he_count", "k_he_offsets", "k_he_scatter", "k_he_solve", "k_he_fallback"],
+            "call_us": round(us, 2),
+            "halfedges_per_s": round(3 * n_tri / (us * 1e-6), 1), "workspace_bytes": int(ws_n),
             "equals_alg2_he": same,
             "cpu_oracle_halfedges_per_s": round(3 * n0 / cpu_s, 1), "cpu_oracle_threads": 1}
 

@@ -283,10 +283,16 @@ pl_status pl_vertex_update(const float *pts_in, float *pts_out, int32_t M, int32
  *            processed (e.g. pl_mesh_opc's count).
  * halfedges  int32 [3 cap] output; entries at or past 3 min(*n_tri, cap) are
  *            left untouched.
- * Workspace: pl_user_halfedges_workspace(cap) bytes (a table of 4 cap slots
- * of 16 bytes and one slot index per half-edge; 0 when cap = 0).  PL_ERR_ARG / PL_ERR_SHAPE /
+ * Workspace: pl_user_halfedges_workspace(cap) bytes, 0 when cap = 0.  Up
+ * to 5.6 M triangles the edges are dealt to 2^k buckets by hash (2^k the
+ * power of two at or above 3 cap / 2048) and each bucket is solved in one
+ * workgroup's LDS: the workspace holds per-chunk bucket counts and starts,
+ * bucket regions of 3072 entries of 12 bytes and an overflow list of 3 cap
+ * entries (about 100 bytes per triangle at cap = 612k); five launches.
+ * Larger capacities use one hash table of 4 cap slots of 16 bytes and a
+ * slot index per half-edge; three launches.  PL_ERR_ARG / PL_ERR_SHAPE /
  * PL_ERR_WORKSPACE / PL_ERR_ALIAS on invalid arguments (nothing enqueued).
- * Three launches on `stream`, no allocation, graph-capturable.
+ * No allocation, graph-capturable (the workspace needs no clearing).
  */
 size_t pl_user_halfedges_workspace(int32_t cap);
 pl_status pl_user_halfedges(const int32_t *triangles, const int32_t *n_tri, int32_t cap,
