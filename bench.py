@@ -182,10 +182,10 @@ def kernel_source_digest(files=FRAME_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key, files=FRAME_SOURCES):
-    """HBM bytes per launch for `key` from the committed counter summary
-    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE runs, calibrated on a
-    copy of known size), or None when there is none or the kernel's sources
+def measured_counters(key, files=FRAME_SOURCES):
+    """The committed counter summary of launch `key` (profiles/traffic.json:
+    FETCH_SIZE and WRITE_SIZE runs calibrated on a copy of known size, and
+    SQ_INSTS_VALU), or None when there is none or the kernel's sources
     changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -196,7 +196,24 @@ def measured_traffic(key, files=FRAME_SOURCES):
     r = rec.get(key)
     if not r or r.get("source_digest") != kernel_source_digest(files):
         return None
-    return r.get("bytes_per_launch")
+    return r
+
+
+def measured_traffic(key, files=FRAME_SOURCES):
+    """HBM bytes per launch for `key` from the committed counters, or None."""
+    r = measured_counters(key, files)
+    return r.get("bytes_per_launch") if r else None
+
+
+def frame_kernel_name(kind, k):
+    """The kernel template a launch of the fused path runs (as the profiler
+    names it), from its kind bits."""
+    import paper_2007_12065_amd as pl
+    mesh = 1 if kind & pl.PL_LAUNCH_MESH_COUNT else 2 if kind & pl.PL_LAUNCH_MESH_EMIT else 0
+    if kind & pl.PL_LAUNCH_BILATERAL:
+        from_pts = "true" if kind & pl.PL_LAUNCH_NORMALS else "false"
+        return f"void k_frame_bilateral<{k.kernel_bil // 2}, float, {from_pts}, {mesh}>"
+    return f"void k_frame_laplacian<{k.kernel_lap // 2}, {mesh}>"
 
 
 def cpu_baseline(frames_np, k, seconds, threads=None):
@@ -612,9 +629,18 @@ def path_record(kind_name, k, M, N, frame_s, launch_s, kinds, n_tri, pts_np, tra
                  "launch_us_bracketed": round(launch_s[dom] * 1e6, 2),
                  "bytes_per_launch": int(m["bytes"]),
                  "lane_ops_per_launch": int(m["lane_ops"]),
-                 "traffic": measured_traffic(traffic_key) if traffic_key else None,
                  "timing": "uninstrumented frame time apportioned by the launches' shares in a "
                            "pass with HIP events around each launch on its stream"})
+    # counters of the same launch, if the committed summary has them
+    cnt = measured_counters(traffic_key) if traffic_key else None
+    if cnt and cnt.get("kernel") != frame_kernel_name(kinds[dom], k):
+        cnt = None
+    roof["traffic"] = cnt.get("bytes_per_launch") if cnt else None
+    if cnt and cnt.get("valu_insts"):
+        # issued VALU lane-slots (SQ_INSTS_VALU x 64) over the launch time: the
+        # hardware's own VALU occupancy, beside the algorithmic valu_frac
+        roof["valu_issue_frac"] = round(cnt["valu_insts"] * 64 / (launch_s[dom] * share)
+                                        / VALU_PEAK_LANE_OPS, 4)
     staged = staged_bytes(c, k)
     T = c["T"]
     return {"workload": kind_name, "frame": [M, N], "triangles_per_frame": T,
