@@ -184,3 +184,47 @@ def test_frame_plan_fused_equals_four_calls(pl):
         assert torch.equal(a.triangles[:n], b.triangles[:n])
         assert torch.equal(a.halfedges[:3 * n], b.halfedges[:3 * n])
         assert torch.equal(a.normals_T[:n].view(torch.uint8), b.normals_T[:n].view(torch.uint8))
+
+
+@pytest.mark.parametrize("kind", ["rgbd_small", "rgbd", "lidar", "lidar128"])
+def test_launch_layout(pl, kind):
+    """The launches pl_smooth_frame issues under the committed tuning
+    (profiles/tune.json): ceil(iters / fuse) filter launches per filter, the
+    mesh count in the first, the emit in exactly one (beside the first
+    bilateral pass unless that pass is the last), the normals in the first
+    bilateral pass and the gather in the last; 3 launches for the RGB-D
+    frames."""
+    import math
+    import os
+
+    import torch
+
+    from paper_2007_12065_amd import tune
+    k = KINDS[kind]
+    saved = [(st, kk, pl.pl_tune_get(st, kk)) for st in range(6) for kk in (3, 5)]
+    try:
+        assert tune.load_cache(os.path.join(os.path.dirname(__file__), "..", "profiles", "tune.json")) > 0
+        sl, sb = tune.frame_stages(k.M, k.N)
+        fl, fb = pl.pl_tune_get(sl, k.kernel_lap)[2], pl.pl_tune_get(sb, k.kernel_bil)[2]
+        plan = pl.FramePlan(k.M, k.N, k.kernel_lap, k.lam, k.iters_lap, k.kernel_bil, k.sigma_length,
+                            k.sigma_angle, k.iters_bil, torch.float32, torch.device("cuda:0"))
+        events = [torch.cuda.Event(enable_timing=True) for _ in range(16)]
+        kinds = plan.run_fused_events(dev_t(make_frame(kind, 3)), events)
+        torch.cuda.synchronize()
+    finally:
+        for st, kk, cfg in saved:
+            pl.pl_tune_set(st, kk, *cfg)
+    nl, nb = math.ceil(k.iters_lap / fl), math.ceil(k.iters_bil / fb)
+    emit_alone = nl + nb == 2 and nb == 1
+    print(f"[case] {kind}: launches {[hex(x) for x in kinds]}", flush=True)
+    assert len(kinds) == nl + nb + emit_alone
+    lap = [x for x in kinds if x & pl.PL_LAUNCH_LAPLACIAN]
+    bil = [x for x in kinds if x & pl.PL_LAUNCH_BILATERAL]
+    assert len(lap) == nl and len(bil) == nb
+    assert kinds[0] & pl.PL_LAUNCH_MESH_COUNT
+    assert sum(bool(x & pl.PL_LAUNCH_MESH_EMIT) for x in kinds) == 1
+    assert bil[0] & pl.PL_LAUNCH_NORMALS and bil[-1] & pl.PL_LAUNCH_GATHER
+    assert sum((x >> 8) & 0xff for x in lap) == k.iters_lap
+    assert sum((x >> 8) & 0xff for x in bil) == k.iters_bil
+    if kind.startswith("rgbd"):
+        assert len(kinds) == 3
