@@ -16,20 +16,21 @@
 //      no normals launch and the raw normals never travel through HBM; the
 //      last pass gathers onto T.
 // The mesh emit (T_map, T, HE) needs every count, so it rides in the second
-// launch; when that one is the gathering bilateral pass (which needs T_map),
-// the emit gets a launch of its own just before it.
+// launch.  When that one is the gathering bilateral pass, the gather cannot
+// read T_map (written by the same launch): it ranks each triangle in T
+// from the mesh's codes and segment counts instead (the same numbers), so a
+// 480 x 640 frame whose two bilateral sweeps fuse into one pass takes two
+// launches.
 //
 // A launch that carries mesh work has two kinds of workgroups: the filter's
-// tiles first, then the mesh's 256-quad row segments, several consecutive
-// segments per workgroup so that the mesh takes few of the workgroup slots
-// the filter's LDS leaves.  (Frames of more than kMeshSegMax segments are
-// meshed by whole quad rows, whose emit body needs more registers than the
-// filters may use; they get pl_mesh_opc's own two launches before the
-// filters, which at that size cost little.)  Each kind is dealt over the
-// eight XCDs on its own (the filter part is padded to a multiple of eight
-// workgroups, and xcd_remap_active gives each XCD a contiguous run), and
-// mesh workgroups stage their data in the same dynamic LDS the filter tiles
-// use.
+// tiles first, then one workgroup per 256-quad row segment of the mesh.
+// (Frames of more than kMeshSegMax segments are meshed by whole quad rows,
+// whose emit body needs more registers than the filters may use; they get
+// pl_mesh_opc's own two launches before the filters, which at that size
+// cost little.)  Each kind is dealt over the eight XCDs on its own (each
+// part padded to a multiple of eight workgroups, and xcd_remap_active gives
+// each XCD a contiguous run), and mesh workgroups stage their data in the
+// same dynamic LDS the filter tiles use.
 #include "groups.h"
 #include "tiles.h"
 #include "tuning.h"
@@ -47,12 +48,14 @@ struct MeshJob {
     int32_t *tri_map, *tris, *he, *n_tri;
     int cap, Mq, N, S;
     int units;       // row segments, Mq S
-    int per_group;   // consecutive segments per workgroup
+    int per_group;   // consecutive segments per workgroup (1)
     int groups;      // mesh workgroups: ceil(units / per_group)
 };
 
-// Mesh workgroups per launch aimed at: about one and a half per CU.
-constexpr int kMeshGroupsTarget = 384;
+// Mesh workgroups of a launch, padded to whole rounds of the eight XCDs.
+__host__ __device__ inline int mesh_blocks(const MeshJob &mj) {
+    return (mj.groups + kNumXcd - 1) / kNumXcd * kNumXcd;
+}
 
 template <int Kind>
 __device__ __forceinline__ void mesh_job(const MeshJob &j, int g, float4 *lds) {
@@ -74,19 +77,20 @@ __global__ __launch_bounds__(kTileBlock) void k_frame_laplacian(
     int TH, int TW, int tiles_x, int ntiles, int filter_blocks, MeshJob mj) {
     extern __shared__ float4 lds[];
     const int b = (int)blockIdx.x;
-    if (Kind == kMeshNone || b < filter_blocks) {
-        const int tile = xcd_remap_active(b, ntiles);
-        if (tile < 0) return;
-        lap_tile<R>(src, dst, M, N, lam, F, TH, TW, (tile / tiles_x) * TH, (tile % tiles_x) * TW,
-                    lds);
+    if (Kind != kMeshNone && b >= filter_blocks) {      // the mesh's workgroups follow the tiles
+        const int g = xcd_remap_active(b - filter_blocks, mj.groups);
+        if (g >= 0) mesh_job<Kind>(mj, g, lds);
         return;
     }
-    const int g = xcd_remap_active(b - filter_blocks, mj.groups);
-    if (g >= 0) mesh_job<Kind>(mj, g, lds);
+    const int tile = xcd_remap_active(b, ntiles);
+    if (tile < 0) return;
+    lap_tile<R>(src, dst, M, N, lam, F, TH, TW, (tile / tiles_x) * TH, (tile % tiles_x) * TW, lds);
 }
 
 // FromPts: the first pass (raw normals and centroids from the smoothed points).
-template <int R, typename NT, bool FromPts, int Kind>
+// ByCodes: the gathering pass beside the emit, ranking triangles from the
+// mesh codes (GatherCodes) instead of reading T_map.
+template <int R, typename NT, bool FromPts, int Kind, bool ByCodes = false>
 __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_frame_bilateral(
     const NT *__restrict__ nin, const float *__restrict__ cen, NT *__restrict__ nout, int Mq,
     int Nq, float ka, float kb, int F, int TQH, int TQW, int tiles_x, int ntiles,
@@ -94,22 +98,16 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_frame_bilatera
     const float *__restrict__ pts, float *__restrict__ cen_out, MeshJob mj) {
     extern __shared__ float4 lds[];
     const int b = (int)blockIdx.x;
-    if (Kind == kMeshNone || b < filter_blocks) {
-        const int tile = xcd_remap_active(b, ntiles);
-        if (tile < 0) return;
-        bil_tile<R, NT, FromPts>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW,
-                                 (tile / tiles_x) * TQH, (tile % tiles_x) * TQW, tri_map, nT, lds,
-                                 pts, cen_out);
+    if (Kind != kMeshNone && b >= filter_blocks) {      // the mesh's workgroups follow the tiles
+        const int g = xcd_remap_active(b - filter_blocks, mj.groups);
+        if (g >= 0) mesh_job<Kind>(mj, g, lds);
         return;
     }
-    const int g = xcd_remap_active(b - filter_blocks, mj.groups);
-    if (g >= 0) mesh_job<Kind>(mj, g, lds);
-}
-
-__global__ __launch_bounds__(kTileBlock) void k_frame_mesh_emit(MeshJob mj) {
-    extern __shared__ float4 lds[];
-    const int g = xcd_remap_active((int)blockIdx.x, mj.groups);
-    if (g >= 0) mesh_job<kMeshEmit>(mj, g, lds);
+    const int tile = xcd_remap_active(b, ntiles);
+    if (tile < 0) return;
+    bil_tile<R, NT, FromPts, ByCodes>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW,
+                                      (tile / tiles_x) * TQH, (tile % tiles_x) * TQW, tri_map, nT,
+                                      lds, pts, cen_out, GatherCodes{mj.codes, mj.counts, mj.S});
 }
 
 // Optional record of the launches (pl_smooth_frame_events): an event before
@@ -153,7 +151,7 @@ pl_status lap_launch(const float *src, float *dst, int M, int N, float lam, int 
     const int tiles_x = (N + c.tw - 1) / c.tw;
     const int ntiles = tiles_x * ((M + c.th - 1) / c.th);
     const int fb = Kind == kMeshNone ? ntiles : round8(ntiles);
-    const int grid = fb + (Kind == kMeshNone ? 0 : mj.groups);
+    const int grid = fb + (Kind == kMeshNone ? 0 : mesh_blocks(mj));
     size_t lds = lap_lds_bytes(R, F, c.th, c.tw);
     lds = lds > mesh_lds(Kind) ? lds : mesh_lds(Kind);
     if (pl_status st = allow_lds((const void *)k_frame_laplacian<R, Kind>, lds)) return st;
@@ -172,19 +170,19 @@ pl_status lap_dispatch(int kind, const float *src, float *dst, int M, int N, flo
     }
 }
 
-template <int R, typename NT, bool FromPts, int Kind>
+template <int R, typename NT, bool FromPts, int Kind, bool ByCodes = false>
 pl_status bil_launch(const NT *nin, const float *cen, NT *nout, int Mq, int Nq, float ka,
                      float kb, int F, TileCfg c, const int32_t *tri_map, NT *nT,
                      const float *pts, float *cen_out, const MeshJob &mj, hipStream_t s) {
     const int tiles_x = (Nq + c.tw - 1) / c.tw;
     const int ntiles = tiles_x * ((Mq + c.th - 1) / c.th);
     const int fb = Kind == kMeshNone ? ntiles : round8(ntiles);
-    const int grid = fb + (Kind == kMeshNone ? 0 : mj.groups);
+    const int grid = fb + (Kind == kMeshNone ? 0 : mesh_blocks(mj));
     size_t lds = bil_lds_bytes(R, F, c.th, c.tw);
     lds = lds > mesh_lds(Kind) ? lds : mesh_lds(Kind);
-    if (pl_status st = allow_lds((const void *)k_frame_bilateral<R, NT, FromPts, Kind>, lds))
+    if (pl_status st = allow_lds((const void *)k_frame_bilateral<R, NT, FromPts, Kind, ByCodes>, lds))
         return st;
-    k_frame_bilateral<R, NT, FromPts, Kind><<<grid, kTileBlock, lds, s>>>(
+    k_frame_bilateral<R, NT, FromPts, Kind, ByCodes><<<grid, kTileBlock, lds, s>>>(
         nin, cen, nout, Mq, Nq, ka, kb, F, c.th, c.tw, tiles_x, ntiles, fb, tri_map, nT, pts,
         cen_out, mj);
     return hip_check(hipGetLastError(), "k_frame_bilateral");
@@ -194,21 +192,18 @@ template <int R, typename NT>
 pl_status bil_dispatch(bool from_pts, int kind, const NT *nin, const float *cen, NT *nout,
                        int Mq, int Nq, float ka, float kb, int F, TileCfg c,
                        const int32_t *tri_map, NT *nT, const float *pts, float *cen_out,
-                       const MeshJob &mj, hipStream_t s) {
+                       const MeshJob &mj, bool gather_codes, hipStream_t s) {
     if (!from_pts)
         return bil_launch<R, NT, false, kMeshNone>(nin, cen, nout, Mq, Nq, ka, kb, F, c, tri_map,
                                                    nT, pts, cen_out, mj, s);
+    if (kind == kMeshEmit && gather_codes)
+        return bil_launch<R, NT, true, kMeshEmit, true>(nin, cen, nout, Mq, Nq, ka, kb, F, c,
+                                                        nullptr, nT, pts, cen_out, mj, s);
     if (kind == kMeshEmit)
         return bil_launch<R, NT, true, kMeshEmit>(nin, cen, nout, Mq, Nq, ka, kb, F, c, tri_map,
                                                   nT, pts, cen_out, mj, s);
     return bil_launch<R, NT, true, kMeshNone>(nin, cen, nout, Mq, Nq, ka, kb, F, c, tri_map, nT,
                                               pts, cen_out, mj, s);
-}
-
-pl_status emit_launch(const MeshJob &mj, hipStream_t s) {
-    const size_t lds = mesh_lds(kMeshEmit);
-    k_frame_mesh_emit<<<round8(mj.groups), kTileBlock, lds, s>>>(mj);
-    return hip_check(hipGetLastError(), "k_frame_mesh_emit");
 }
 
 template <typename NT>
@@ -230,8 +225,10 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s, LaunchLog *log) {
     mj.N = N;
     mj.S = mesh_segments(Nq);
     mj.units = Mq * mj.S;
-    mj.per_group = (mj.units + kMeshGroupsTarget - 1) / kMeshGroupsTarget;
-    mj.groups = (mj.units + mj.per_group - 1) / mj.per_group;
+    // one row segment per workgroup: several per workgroup (fewer, longer
+    // mesh workgroups) left the emit finishing after the filter's tiles
+    mj.per_group = 1;
+    mj.groups = mj.units;
     // frames meshed by whole rows: pl_mesh_opc's launches first, and no
     // mesh work in the filter launches
     const bool rows = (long)Mq * mj.S > kMeshSegMax;
@@ -252,9 +249,6 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s, LaunchLog *log) {
     const TileCfg cl = tile_cfg(frame_stage(true, M, N), Rl), cb = tile_cfg(frame_stage(false, M, N), Rb);
     const int Ll = f.iters_lap == 0 ? 1 : (f.iters_lap + cl.fuse - 1) / cl.fuse;
     const int Lb = f.iters_bil == 0 ? 1 : (f.iters_bil + cb.fuse - 1) / cb.fuse;
-    const int total = Ll + Lb;
-    // the emit rides in launch 1 unless that is the last (gathering) launch
-    const bool emit_alone = !rows && total == 2 && Lb == 1;
 
     const float *cur = f.pts;
     int left = f.iters_lap;
@@ -288,18 +282,17 @@ pl_status run(const pl_frame &f, void *ws, hipStream_t s, LaunchLog *log) {
         left -= F;
         const bool last = l == Lb - 1;
         NT *dst = ((Lb - 1 - l) % 2 == 0) ? nout : bil_tmp;             // last lands in normals
-        if (last && emit_alone) {
-            if (pl_status st = emit_launch(mj, s)) return st;
-            if (pl_status st = log_launch(log, PL_LAUNCH_MESH_EMIT, s)) return st;
-        }
-        const int kind = (!rows && Ll + l == 1 && !emit_alone) ? kMeshEmit : kMeshNone;
-        const int32_t *tm = last ? f.tri_map : nullptr;
+        // the emit rides in the second launch; when that is the gathering
+        // pass, the gather ranks the triangles from the mesh codes itself
+        const int kind = (!rows && Ll + l == 1) ? kMeshEmit : kMeshNone;
+        const bool by_codes = last && kind == kMeshEmit;
+        const int32_t *tm = last && !by_codes ? f.tri_map : nullptr;
         pl_status st;
         switch (Rb) {
-        case 1: st = bil_dispatch<1, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, s); break;
-        case 2: st = bil_dispatch<2, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, s); break;
-        case 3: st = bil_dispatch<3, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, s); break;
-        default: st = bil_dispatch<4, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, s); break;
+        case 1: st = bil_dispatch<1, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, by_codes, s); break;
+        case 2: st = bil_dispatch<2, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, by_codes, s); break;
+        case 3: st = bil_dispatch<3, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, by_codes, s); break;
+        default: st = bil_dispatch<4, NT>(l == 0, kind, ncur, f.centroids, dst, Mq, Nq, ka, kb, F, cb, tm, nT, f.pts_out, f.centroids, mj, by_codes, s); break;
         }
         if (st) return st;
         const int32_t what = PL_LAUNCH_BILATERAL | (l == 0 ? PL_LAUNCH_NORMALS : 0) |

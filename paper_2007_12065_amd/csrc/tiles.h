@@ -723,8 +723,18 @@ constexpr float kBilShift = 48.f;                 // every weight is 2^(48 - e)
 constexpr int kBilMaxSweeps = 8;                  // fused sweeps per launch at most
 __host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW) {
     return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) +
-           sizeof(int) * (2 * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) + kBilMaxSweeps + 1);
+           sizeof(int) * (2 * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) + kBilMaxSweeps + 1) +
+           sizeof(int) * (size_t)TQH * TQW;     // T ranks of the tile (gather from the mesh codes)
 }
+
+// The mesh's codes and per-segment counts (pl_mesh_opc's first pass): with
+// them the gather finds each triangle's place in T itself instead of reading
+// T_map, so the pass can run in the same launch as the mesh emit.
+struct GatherCodes {
+    const uint8_t *codes;       // [Mq][Nq] validity codes (bit k: triangle k)
+    const int *seg_count;       // [Mq][S] valid triangles per row segment
+    int S;                      // segments per quad row (mesh_segments(Nq))
+};
 
 // Output stores of the filter: streaming for float32 normals, plain for
 // float16 (measured on float32 only).
@@ -983,18 +993,61 @@ __device__ __forceinline__ void bil_sweep(const float4 *sc, const float4 *sn, in
     __syncthreads();
 }
 
+// T ranks of a tile's quads for the gather: rank[ty TQW + tx] is the index
+// in T of quad (qy0 + ty, qx0 + tx)'s first valid triangle, with the quad's
+// code in bits 30..31 (T has fewer than 2^30 triangles).  T is the valid
+// triangles in GID order, so the rank is the number of valid triangles in
+// the segments before the quad's row segment, plus those before it in its
+// segment: each wave takes tile rows, sums the counts of the segments
+// before the row's first column and the codes from that segment's start,
+// then scans the row.  Quads off the grid get code 0.  No barrier: the
+// caller's next one publishes the ranks.
+__device__ __forceinline__ void bil_gather_ranks(const GatherCodes &gc, int Mq, int Nq, int qy0,
+                                                 int qx0, int TQH, int TQW, int *rank) {
+    const int lane = (int)threadIdx.x & (kWave - 1), wave = (int)threadIdx.x / kWave;
+    const int s0 = qx0 / kMeshSeg;
+    // segments before the tile's first row: the same for every row of it
+    const int k0 = qy0 * gc.S;
+    int before = 0;
+    for (int k = lane; k < k0; k += kWave) before += gc.seg_count[k];
+    before = wave_sum(before);
+    for (int ty = wave; ty < TQH; ty += kTileBlock / kWave) {
+        const int u = qy0 + ty;
+        if (u >= Mq) {
+            for (int tx = lane; tx < TQW; tx += kWave) rank[ty * TQW + tx] = 0;
+            continue;
+        }
+        const uint8_t *row = gc.codes + (size_t)u * Nq;
+        // the rows between, the row's segments before s0, and its codes
+        // from the segment's first column up to qx0
+        int c = 0;
+        for (int k = k0 + lane; k < u * gc.S + s0; k += kWave) c += gc.seg_count[k];
+        for (int v = s0 * kMeshSeg + lane; v < qx0; v += kWave) c += popc2(row[v]);
+        int run = before + wave_sum(c);
+        for (int t0 = 0; t0 < TQW; t0 += kWave) {
+            const int tx = t0 + lane, v = qx0 + tx;
+            const int code = tx < TQW && v < Nq ? row[v] : 0;
+            const int n = popc2(code);
+            const int incl = wave_inclusive_scan(n);
+            if (tx < TQW) rank[ty * TQW + tx] = (run + incl - n) | (code << 30);
+            run += __shfl(incl, kWave - 1, kWave);
+        }
+    }
+}
+
 // FromPts: the raw normals and centroids are not read but computed here from
 // the (smoothed) points `pts` exactly as normals_quad computes and stores
 // them (normals rounded to NT), and the tile's centroids are written to
 // `cen` -- the batched path's first pass, which then needs no normals
 // stage.  Otherwise nin / cen are the stored raw normals and centroids.
-template <int R, typename NT, bool FromPts = false>
+template <int R, typename NT, bool FromPts = false, bool ByCodes = false>
 __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float *__restrict__ cen,
                                          NT *__restrict__ nout, int Mq, int Nq, float ka, float kb,
                                          int F, int TQH, int TQW, int qy0, int qx0,
                                          const int32_t *__restrict__ tri_map, NT *__restrict__ nT,
                                          float4 *lds, const float *__restrict__ pts = nullptr,
-                                         float *__restrict__ cen_out = nullptr) {
+                                         float *__restrict__ cen_out = nullptr,
+                                         GatherCodes gc = GatherCodes{nullptr, nullptr, 0}) {
     const int halo = R * F;
     const int H = TQH + 2 * halo, W = TQW + 2 * halo, S = H * W;
     float4 *s_c = lds;                  // [2][S] centroids, w = 1 if usable
@@ -1004,6 +1057,24 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     int *qbase = reinterpret_cast<int *>(lds + (F > 1 ? 6 : 4) * S);
     const BilQueue qu{qbase, qbase + 2 * S};
     if (threadIdx.x < kBilMaxSweeps + 1) qu.count[threadIdx.x] = 0;
+    // T ranks of the tile when the gather takes them from the mesh codes
+    int *rank = qbase + 2 * S + kBilMaxSweeps + 1;
+    constexpr bool by_codes = ByCodes;
+    if constexpr (by_codes) {
+        bil_gather_ranks(gc, Mq, Nq, qy0, qx0, TQH, TQW, rank);
+        if (F == 0) __syncthreads();
+    }
+    // index in T of triangle k of tile quad (ty, tx), or -1 (none, or no gather)
+    auto t_index = [&](int ty, int tx, size_t q, int k) -> int {
+        if constexpr (by_codes) {
+            const unsigned r = (unsigned)rank[ty * TQW + tx];
+            const int code = (int)(r >> 30), base = (int)(r & 0x3fffffffu);
+            if (!((code >> k) & 1)) return -1;
+            return base + (k == 1 ? (code & 1) : 0);
+        } else {
+            return tri_map ? tri_map[2 * q + k] : -1;
+        }
+    };
     const float inf = __builtin_inff();
     const int oy = qy0 - halo, ox = qx0 - halo;
 
@@ -1112,7 +1183,7 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
         // streaming stores (float32 normals): they write partial lines, about
         // 2 MB more per launch on a 480x640 frame, but the whole path gains
         // 2.4 us per frame.  A queued triangle is written after the sweep.
-        const int t0 = tri_map ? tri_map[2 * q] : -1, t1 = tri_map ? tri_map[2 * q + 1] : -1;
+        const int t0 = t_index(ty, tx, q, 0), t1 = t_index(ty, tx, q, 1);
         if (!(pend[0] | pend[1])) {
 #pragma unroll
             for (int i = 0; i < 6; ++i) bil_store(&nout[6 * q + i], v[i]);
@@ -1156,12 +1227,10 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
                 st_f(&v[0], r.x); st_f(&v[1], r.y); st_f(&v[2], r.z);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) bil_store(&nout[6 * q + 3 * k + i], v[i]);
-                if (tri_map) {
-                    const int t = tri_map[2 * q + k];
-                    if (t >= 0) {
+                const int t = t_index(ly - halo, lx - halo, q, k);
+                if (t >= 0) {
 #pragma unroll
-                        for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t + i], v[i]);
-                    }
+                    for (int i = 0; i < 3; ++i) bil_store(&nT[3 * (size_t)t + i], v[i]);
                 }
             }
         }

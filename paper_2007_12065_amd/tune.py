@@ -27,9 +27,9 @@ LAP_CANDIDATES = {
 }
 BIL_CANDIDATES = {
     3: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (8, 32, 2), (4, 32, 1), (8, 64, 1),
-        (2, 128, 1), (4, 16, 1)],
+        (2, 128, 1), (4, 16, 1), (8, 16, 2), (4, 32, 2), (4, 16, 2), (16, 16, 2), (8, 8, 2)],
     5: [(8, 32, 1), (4, 64, 1), (16, 16, 1), (16, 32, 1), (4, 32, 1), (8, 64, 1), (4, 16, 1),
-        (8, 8, 1), (2, 32, 1)],
+        (8, 8, 1), (2, 32, 1), (4, 16, 3), (8, 8, 3), (2, 32, 3), (4, 16, 2), (8, 8, 2)],
 }
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pl_tune.json")
 

@@ -189,11 +189,10 @@ def test_frame_plan_fused_equals_four_calls(pl):
 @pytest.mark.parametrize("kind", ["rgbd_small", "rgbd", "lidar", "lidar128"])
 def test_launch_layout(pl, kind):
     """The launches pl_smooth_frame issues under the committed tuning
-    (profiles/tune.json): ceil(iters / fuse) filter launches per filter, the
-    mesh count in the first, the emit in exactly one (beside the first
-    bilateral pass unless that pass is the last), the normals in the first
-    bilateral pass and the gather in the last; 3 launches for the RGB-D
-    frames."""
+    (profiles/tune.json): ceil(iters / fuse) filter launches per filter and
+    nothing else, the mesh count in the first, the emit in exactly one (the
+    second), the normals in the first bilateral pass and the gather in the
+    last; at most 3 launches for the RGB-D frames."""
     import math
     import os
 
@@ -215,9 +214,9 @@ def test_launch_layout(pl, kind):
         for st, kk, cfg in saved:
             pl.pl_tune_set(st, kk, *cfg)
     nl, nb = math.ceil(k.iters_lap / fl), math.ceil(k.iters_bil / fb)
-    emit_alone = nl + nb == 2 and nb == 1
     print(f"[case] {kind}: launches {[hex(x) for x in kinds]}", flush=True)
-    assert len(kinds) == nl + nb + emit_alone
+    assert len(kinds) == nl + nb
+    assert kinds[1] & pl.PL_LAUNCH_MESH_EMIT
     lap = [x for x in kinds if x & pl.PL_LAUNCH_LAPLACIAN]
     bil = [x for x in kinds if x & pl.PL_LAUNCH_BILATERAL]
     assert len(lap) == nl and len(bil) == nb
@@ -227,4 +226,4 @@ def test_launch_layout(pl, kind):
     assert sum((x >> 8) & 0xff for x in lap) == k.iters_lap
     assert sum((x >> 8) & 0xff for x in bil) == k.iters_bil
     if kind.startswith("rgbd"):
-        assert len(kinds) == 3
+        assert len(kinds) <= 3
