@@ -212,7 +212,9 @@ def frame_kernel_name(kind, k):
     mesh = 1 if kind & pl.PL_LAUNCH_MESH_COUNT else 2 if kind & pl.PL_LAUNCH_MESH_EMIT else 0
     if kind & pl.PL_LAUNCH_BILATERAL:
         from_pts = "true" if kind & pl.PL_LAUNCH_NORMALS else "false"
-        return f"void k_frame_bilateral<{k.kernel_bil // 2}, float, {from_pts}, {mesh}>"
+        # the gathering pass beside the emit ranks the triangles from the codes
+        by_codes = "true" if (kind & pl.PL_LAUNCH_GATHER and kind & pl.PL_LAUNCH_MESH_EMIT) else "false"
+        return f"void k_frame_bilateral<{k.kernel_bil // 2}, float, {from_pts}, {mesh}, {by_codes}>"
     return f"void k_frame_laplacian<{k.kernel_lap // 2}, {mesh}>"
 
 
@@ -631,10 +633,9 @@ def path_record(kind_name, k, M, N, frame_s, launch_s, kinds, n_tri, pts_np, tra
                  "lane_ops_per_launch": int(m["lane_ops"]),
                  "timing": "uninstrumented frame time apportioned by the launches' shares in a "
                            "pass with HIP events around each launch on its stream"})
-    # counters of the same launch, if the committed summary has them
-    cnt = measured_counters(traffic_key) if traffic_key else None
-    if cnt and cnt.get("kernel") != frame_kernel_name(kinds[dom], k):
-        cnt = None
+    # counters of the same launch (workload and kernel template), if the
+    # committed summary has them
+    cnt = measured_counters(f"{traffic_key}:{frame_kernel_name(kinds[dom], k)}") if traffic_key else None
     roof["traffic"] = cnt.get("bytes_per_launch") if cnt else None
     if cnt and cnt.get("valu_insts"):
         # issued VALU lane-slots (SQ_INSTS_VALU x 64) over the launch time: the
@@ -751,7 +752,7 @@ def main():
     frame_s, launch_s, kinds, lat = fused_pass(plans, frames, k, K, args.warmup, stream)
     n_tri = [int(p.n_tri.item()) for p in plans]
     rec = path_record("rgbd", k, M, N, frame_s, launch_s, kinds, float(np.mean(n_tri)),
-                      frames_np[0], traffic_key="rgbd:dominant")
+                      frames_np[0], traffic_key="rgbd")
     T = rec["triangles_per_frame"]
 
     # the four single-frame calls (the plain baseline of the batched and
@@ -852,7 +853,7 @@ def main():
                 fs, ls, kd, _ = fused_pass(pp, fr, kk, K, args.warmup, stream)
                 nt = float(np.mean([int(p.n_tri.item()) for p in pp]))
                 r = path_record(kind, kk, kk.M, kk.N, fs, ls, kd, nt, fr_np[0],
-                                traffic_key=f"{kind}:dominant")
+                                traffic_key=kind)
                 fnp = fr_np[0]
                 del fr, pp
             r["angle_err_rad_vs_fp64"] = angle_records(kind, kk, fnp,

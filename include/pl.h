@@ -489,9 +489,11 @@ pl_status pl_batch_replay_bounded(pl_batch batch, int32_t n_active, hipStream_t 
  * bit; frame->normals receives the FILTERED normals (T_FC layout) and the
  * unfiltered normals are not stored.  The mesh's validity pass runs in the
  * same launch as the Laplacian's first pass, the mesh emit in the launch
- * after it, and the first bilateral pass computes the normals and centroids
- * itself (a 480 x 640 frame with the default tuning: 3 launches instead of
- * 6).
+ * after it (whose gather, if it is the last bilateral pass, ranks the
+ * triangles in T from the validity codes instead of reading T_map), and the
+ * first bilateral pass computes the normals and centroids itself: one
+ * launch per filter pass (a 480 x 640 frame with the committed tuning: 3
+ * launches instead of 6; a 120 x 160 frame: 2).
  *
  * frame      HOST pointer to one pl_frame (the layout is documented with the
  *            batched path below); its buffers are device memory owned by
