@@ -836,6 +836,18 @@ def main():
     print(f"[bench] fused frame {frame_s * 1e6:.2f} us, four calls {four_s * 1e6:.2f} us",
           file=sys.stderr, flush=True)
 
+    # the same frames with float16 normal storage (m1): the fused path's time
+    # beside the float32 headline
+    plans16 = [mk(k, torch.float16) for _ in range(sets)]
+    f16_s, f16_launch, f16_kinds, _ = fused_pass(plans16, frames, k, K, args.warmup, stream)
+    out["fused_f16"] = {"ms_per_frame": round(f16_s * 1e3, 5),
+                        "triangles_per_s": round(T / f16_s, 1),
+                        "vs_f32": round(frame_s / f16_s, 4),
+                        "launch_us_bracketed": [round(t * 1e6, 2) for t in f16_launch],
+                        "note": "float16 normals (raw, intermediate and filtered), float32 "
+                                "arithmetic and points"}
+    del plans16
+
     if args.per_config:
         print("[bench] per-workload records", file=sys.stderr, flush=True)
         per = {}
