@@ -122,6 +122,11 @@ TUNINGS = {
     "laplacian fused, bilateral fused": [(0, 3, (16, 16, 8)), (0, 5, (8, 16, 5)), (0, 7, (8, 16, 5)),
                                          (0, 9, (4, 16, 5)), (1, 3, (16, 16, 4)), (1, 5, (8, 16, 4)),
                                          (1, 7, (4, 16, 3)), (1, 9, (4, 16, 3))],
+    # tile widths that do not divide the mesh's 256-quad row segments: tiles
+    # across a segment boundary when the gather ranks triangles from the codes
+    "bilateral fused, odd widths": [(0, 3, (16, 24, 8)), (0, 5, (8, 40, 5)), (0, 7, (8, 16, 5)),
+                                    (0, 9, (4, 16, 5)), (1, 3, (8, 24, 4)), (1, 5, (4, 20, 4)),
+                                    (1, 7, (4, 12, 3)), (1, 9, (2, 12, 3))],
 }
 
 
