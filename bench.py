@@ -48,7 +48,8 @@ TUNE_FILE = os.path.join(ROOT, "profiles", "tune.json")
 #  squared distance 3, rsqrt 4, weight sum 1, weighted sum 3; then 1/W 4 and
 #  the update 4.
 #  Bilateral, per triangle and sweep, per neighbour: two squared differences
-#  12, exponent 2, exp2 4, accumulation 4; then renormalisation 10.
+#  12, exponent 2, exp2 4, weighted sum 3 (Eq. 6 renormalises, so the sum of
+#  the weights is not needed); then renormalisation 10.
 #  Centroid and normal of a triangle: 31.
 
 
@@ -57,7 +58,7 @@ def lap_lane_ops(kernel):
 
 
 def bil_lane_ops(kernel):
-    return 2 * (kernel * kernel - 1) * 22 + 10
+    return 2 * (kernel * kernel - 1) * 21 + 10
 
 
 GEOM_LANE_OPS = 31

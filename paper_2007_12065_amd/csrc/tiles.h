@@ -685,9 +685,10 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // its triangles is being filtered; with e >= 0 no weight exceeds 2^48, which
 // keeps the sums and the squared norm of Eq. 6 finite for windows up to
 // 9 x 9 (160 neighbours), and terms down to e = 174 stay normal floats.  If
-// the total drops below 2^-60 (every neighbour at e > 108), that triangle is
-// recomputed with every exponent shifted by the smallest one, which puts the
-// largest term at 1.
+// the weighted sum of normals drops below 2^-60 in norm (always when every
+// neighbour is at e > 108; otherwise only where the normals nearly cancel),
+// that triangle is recomputed with every exponent shifted by the smallest
+// one, which puts the largest term at 1.
 // Such triangles are isolated ones (about 7 per thousand on the LiDAR
 // frames, 4 per 10^4 on the RGB-D ones), so instead of the lane
 // redoing its window alone -- which held up its whole wave -- the lane
@@ -715,7 +716,7 @@ __device__ __forceinline__ void normals_block(const float *__restrict__ pts, int
 // its count).
 // ---------------------------------------------------------------------------
 
-constexpr float kBilUnderflow = 8.673617e-19f;    // 2^-60
+constexpr float kBilUnderflow2 = 0x1p-120f;       // (2^-60)^2
 // register budget of the bilateral kernels: at least 6 waves per SIMD
 // (<= 80 VGPRs), more than the LDS of a typical tile lets reside anyway
 constexpr int kBilWavesPerSimd = 6;
@@ -761,14 +762,16 @@ __device__ __forceinline__ float bil_pair_e(const BilOwn &o, const float4 c, con
     return fmaf(dc2, o.ka, dn2 * o.kb);
 }
 
+// Sum of weighted neighbour normals.  Eq. 6 renormalises it, so the sum of
+// the weights is not needed; the underflow test uses the vector's norm,
+// which no total weight falls below the norm of (unit normals).
 struct BilAcc {
-    float x, y, z, w;
+    float x, y, z;
 };
 
 // s += 2^(m - e) * n
 __device__ __forceinline__ void bil_add(BilAcc &s, float m, float e, const float4 n) {
     const float w = __builtin_amdgcn_exp2f(m - e);
-    s.w += w;
     s.x = fmaf(w, n.x, s.x);
     s.y = fmaf(w, n.y, s.y);
     s.z = fmaf(w, n.z, s.z);
@@ -788,10 +791,14 @@ __device__ __forceinline__ void bil_dplus(int i, int &dy, int &dx) {
 }
 template <int R> constexpr int bil_ndplus() { return 2 * R * R + 2 * R; }
 
+__device__ __forceinline__ float bil_norm2(const BilAcc &s) {
+    return fmaf(s.x, s.x, fmaf(s.y, s.y, s.z * s.z));
+}
+
 template <typename NT>
 __device__ __forceinline__ float4 bil_finish(BilAcc s, float4 cur) {
-    const float l2 = fmaf(s.x, s.x, fmaf(s.y, s.y, s.z * s.z));
-    if (!(s.w > 0.f) || !(l2 > 0.f)) return cur;
+    const float l2 = bil_norm2(s);
+    if (!(l2 > 0.f)) return cur;            // no usable neighbour
     const float k = __builtin_amdgcn_rsqf(l2);
     return make_float4(round_storage<NT>(s.x * k), round_storage<NT>(s.y * k),
                        round_storage<NT>(s.z * k), cur.w);
@@ -813,18 +820,19 @@ __device__ __forceinline__ float bil_w(const float4 ci, const float4 ni, const f
 
 // s += w n
 __device__ __forceinline__ void bil_acc(BilAcc &s, float w, const float4 n) {
-    s.w += w;
     s.x = fmaf(w, n.x, s.x);
     s.y = fmaf(w, n.y, s.y);
     s.z = fmaf(w, n.z, s.z);
 }
 
 // Eq. 6 for one triangle: a missing one (c.w = 0) is copied through; pend:
-// the sum underflowed (the triangle goes to the queue and r is not set).
+// the weighted sum fell below 2^-60 in norm (the triangle goes to the queue
+// and r is not set).  Every total weight below 2^-60 is caught, since the
+// norm is at most the total weight.
 template <typename NT>
 __device__ __forceinline__ float4 bil_close(const float4 c, const float4 n, BilAcc s, bool &pend) {
     const bool ok = c.w != 0.f;
-    pend = ok && !(s.w >= kBilUnderflow);
+    pend = ok && !(bil_norm2(s) >= kBilUnderflow2);
     return ok ? bil_finish<NT>(s, n) : n;
 }
 
@@ -876,7 +884,7 @@ __device__ __forceinline__ float4 bil_fallback_wave(const float4 *sc, const floa
         }
     }
     mn = wave_min_f(mn);
-    BilAcc s{0.f, 0.f, 0.f, 0.f};
+    BilAcc s{0.f, 0.f, 0.f};
     if (mn < inf) {
 #pragma unroll
         for (int t = 0; t < kPer; ++t) bil_add(s, mn, e[t], nj[t]);
@@ -884,7 +892,6 @@ __device__ __forceinline__ float4 bil_fallback_wave(const float4 *sc, const floa
     s.x = wave_sum_f(s.x);
     s.y = wave_sum_f(s.y);
     s.z = wave_sum_f(s.z);
-    s.w = wave_sum_f(s.w);
     return bil_finish<NT>(s, n);
 }
 
@@ -927,7 +934,6 @@ __device__ __forceinline__ BilAcc bil_reduce(BilAcc s) {
         s.x += __shfl_xor(s.x, m, kWave);
         s.y += __shfl_xor(s.y, m, kWave);
         s.z += __shfl_xor(s.z, m, kWave);
-        s.w += __shfl_xor(s.w, m, kWave);
     }
     return s;
 }
@@ -945,7 +951,7 @@ __device__ __forceinline__ void bil_sum_quad(const float4 *sc, const float4 *sn,
                                                 bool &pend1) {
     constexpr int ND = bil_ndplus<R>(), P = bil_parts<R>();
     const float4 c0 = sc[a], c1 = sc[plane + a], n0 = sn[a], n1 = sn[plane + a];
-    BilAcc s0{0.f, 0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f, 0.f};
+    BilAcc s0{0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int j = 0; j < ND / P; ++j) {
         const int i = j * P + part;
