@@ -7,6 +7,7 @@
 #include "common.h"
 
 #include <float.h>
+#include <type_traits>
 
 namespace pl {
 
@@ -490,25 +491,36 @@ __device__ __forceinline__ void lap_tile(const float *__restrict__ src, float *_
             const bool active = __float_as_uint(c.w) == 0u;   // valid, not in the border band
             if (active) {
                 float ws = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-                // 3x3: fully unrolled; larger windows: one row of the window
-                // per iteration, so only that row's neighbours are live
-                constexpr int kRowUnroll = R == 1 ? 3 : 1;
+                // The weighted sums; with `skip` set, coincident neighbours
+                // (d2 = 0, weight 1/0) are left out.  Without the test such a neighbour makes ws
+                // infinite -- nothing else can, every other weight being at
+                // most 1/sqrt(the smallest float) -- so the point is summed
+                // again with it (rare: duplicated points), and every result
+                // is the same as with the test throughout.
+                auto sums = [&](auto skip) {
+                    ws = 0.f; sx = 0.f; sy = 0.f; sz = 0.f;
+                    // 3x3: fully unrolled; larger windows: one row of the
+                    // window per iteration, so only that row's neighbours are live
+                    constexpr int kRowUnroll = R == 1 ? 3 : 1;
 #pragma unroll kRowUnroll
-                for (int dy = -R; dy <= R; ++dy) {
+                    for (int dy = -R; dy <= R; ++dy) {
 #pragma unroll
-                    for (int dx = -R; dx <= R; ++dx) {
-                        if (dy == 0 && dx == 0) continue;
-                        const float4 p = A[(ly + dy) * W + lx + dx];
-                        const float ex = p.x - c.x, ey = p.y - c.y, ez = p.z - c.z;
-                        const float d2 = fmaf(ex, ex, fmaf(ey, ey, fmaf(ez, ez, p.w)));
-                        float w = __builtin_amdgcn_rsqf(d2);     // 1/||v_j - v_i||
-                        w = d2 > 0.f ? w : 0.f;                   // coincident: skipped
-                        ws += w;
-                        sx = fmaf(w, ex, sx);
-                        sy = fmaf(w, ey, sy);
-                        sz = fmaf(w, ez, sz);
+                        for (int dx = -R; dx <= R; ++dx) {
+                            if (dy == 0 && dx == 0) continue;
+                            const float4 p = A[(ly + dy) * W + lx + dx];
+                            const float ex = p.x - c.x, ey = p.y - c.y, ez = p.z - c.z;
+                            const float d2 = fmaf(ex, ex, fmaf(ey, ey, fmaf(ez, ez, p.w)));
+                            float w = __builtin_amdgcn_rsqf(d2);     // 1/||v_j - v_i||
+                            if constexpr (decltype(skip)::value) w = d2 > 0.f ? w : 0.f;
+                            ws += w;
+                            sx = fmaf(w, ex, sx);
+                            sy = fmaf(w, ey, sy);
+                            sz = fmaf(w, ez, sz);
+                        }
                     }
-                }
+                };
+                sums(std::false_type{});
+                if (!(ws < inf)) sums(std::true_type{});
                 if (ws > 0.f) {
                     const float k = lam * __builtin_amdgcn_rcpf(ws);
                     o.x = fmaf(k, sx, c.x);
