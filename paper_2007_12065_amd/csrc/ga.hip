@@ -47,9 +47,9 @@ namespace pl {
 namespace {
 
 constexpr int kGaBlock = 256;
-constexpr int kGaPer = 4;                  // integrated rows per thread and pass (large inputs)
+constexpr int kGaBatch = 6;                // candidate loads issued together
 #ifndef PL_GA_MAX_GRID
-#define PL_GA_MAX_GRID 1024
+#define PL_GA_MAX_GRID 1536
 #endif
 constexpr int kGaMaxGrid = PL_GA_MAX_GRID;  // workgroups of one integration launch
 constexpr int kGaReplicas = 16;             // histogram copies the workgroups flush into
@@ -96,12 +96,13 @@ __device__ __noinline__ int ga_nearest_all(float x, float y, float z,
     return arg;
 }
 
-// Each thread takes PER consecutive integrated rows and runs their searches
-// side by side (loads of all rows, then of all bins, then the candidates in
-// lockstep), so several dependent load chains are in flight per thread.
-// Inputs too small to give every CU a workgroup at four rows per thread run
-// with one (a sampled frame's normals).
-template <typename NT, int PER>
+// One integrated row per thread and pass: the row's normal, then its bin's
+// candidate range, then every candidate of the range at once (kGaBatch loads
+// issued before the first is used; the built tables hold at most 6 per bin,
+// longer ranges of a caller's cell set take further batches).  A wave thus
+// waits for three dependent loads per row instead of one per candidate of
+// its longest range.
+template <typename NT>
 __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
     const NT *__restrict__ normals, const int32_t *__restrict__ n_dev, int cap, int stride,
     const float *__restrict__ cells, int n_cells, const int *__restrict__ bin_start,
@@ -110,62 +111,46 @@ __global__ __launch_bounds__(kGaBlock) void k_ga_integrate(
     extern __shared__ uint32_t hist[];
     const int n = min(max(*n_dev, 0), cap);
     const int rows = n == 0 ? 0 : (n - 1) / stride + 1;
-    const int span = (int)gridDim.x * kGaBlock * PER;
-    const int first = (int)blockIdx.x * kGaBlock * PER;
+    const int span = (int)gridDim.x * kGaBlock;
+    const int first = (int)blockIdx.x * kGaBlock;
     if (first >= rows) return;                       // the whole workgroup has no row
     for (int i = threadIdx.x; i < n_cells; i += kGaBlock) hist[i] = 0u;
     __syncthreads();
-    for (int base = first + (int)threadIdx.x * PER; base < rows; base += span) {
-        float x[PER], y[PER], z[PER];
+    for (int j = first + (int)threadIdx.x; j < rows; j += span) {
+        const size_t t = (size_t)j * (size_t)stride;
+        const float x = ld_f(normals + 3 * t), y = ld_f(normals + 3 * t + 1),
+                    z = ld_f(normals + 3 * t + 2);
+        const float s2 = fmaf(x, x, fmaf(y, y, z * z));
+        // a NaN or infinite coordinate lands in no cell (every distance is NaN
+        // or infinite); only finite normals of odd length search all
+        const bool none = !(fabsf(x) <= FLT_MAX && fabsf(y) <= FLT_MAX && fabsf(z) <= FLT_MAX);
+        const bool all = !none && !(s2 >= 0.25f && s2 <= 4.0f);
+        const int b = (all || none) ? 0 : ga_bin(x, y, z, G);
+        const int lo = bin_start[b];
+        const int len = (all || none) ? 0 : bin_start[b + 1] - lo;
+        float best = __builtin_inff();
+        int arg = -1;
+        for (int k0 = 0; k0 < len; k0 += kGaBatch) {
+            float4 e[kGaBatch];
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int j = min(base + q, rows - 1);   // rows past the end repeat the last one
-            const size_t t = (size_t)j * (size_t)stride;
-            x[q] = ld_f(normals + 3 * t);
-            y[q] = ld_f(normals + 3 * t + 1);
-            z[q] = ld_f(normals + 3 * t + 2);
-        }
-        int lo[PER], len[PER], arg[PER];
-        bool all[PER], none[PER];
-        int longest = 0;
+            for (int k = 0; k < kGaBatch; ++k)
+                e[k] = k0 + k < len ? bin_cells[lo + k0 + k] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const float s2 = fmaf(x[q], x[q], fmaf(y[q], y[q], z[q] * z[q]));
-            // a NaN or infinite coordinate lands in no cell (every distance is
-            // NaN or infinite); only finite normals of odd length search all
-            none[q] = !(fabsf(x[q]) <= FLT_MAX && fabsf(y[q]) <= FLT_MAX && fabsf(z[q]) <= FLT_MAX);
-            all[q] = !none[q] && !(s2 >= 0.25f && s2 <= 4.0f);
-            const int b = (all[q] || none[q]) ? 0 : ga_bin(x[q], y[q], z[q], G);
-            lo[q] = bin_start[b];
-            len[q] = (all[q] || none[q]) ? 0 : bin_start[b + 1] - lo[q];
-            longest = max(longest, len[q]);
-            arg[q] = -1;
-        }
-        float best[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) best[q] = __builtin_inff();
-        for (int k = 0; k < longest; ++k) {
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                if (k < len[q]) {
+            for (int k = 0; k < kGaBatch; ++k) {
+                if (k0 + k < len) {
                     // a candidate is its cell's normal with the cell index in w
-                    const float4 e = bin_cells[lo[q] + k];
-                    const float dx = e.x - x[q], dy = e.y - y[q], dz = e.z - z[q];
+                    const float dx = e[k].x - x, dy = e[k].y - y, dz = e[k].z - z;
                     const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    if (d2 < best[q]) {
-                        best[q] = d2;
-                        arg[q] = (int)__float_as_uint(e.w);
+                    if (d2 < best) {
+                        best = d2;
+                        arg = (int)__float_as_uint(e[k].w);
                     }
                 }
             }
         }
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            if (base + q >= rows) break;
-            const int c = all[q] ? ga_nearest_all(x[q], y[q], z[q], cells, n_cells) : arg[q];
-            if (cell_out) cell_out[base + q] = c;
-            if (c >= 0) atomicAdd(&hist[c], 1u);
-        }
+        const int c = all ? ga_nearest_all(x, y, z, cells, n_cells) : arg;
+        if (cell_out) cell_out[j] = c;
+        if (c >= 0) atomicAdd(&hist[c], 1u);
     }
     __syncthreads();
     uint32_t *copy = replicas + (size_t)(blockIdx.x % kGaReplicas) * n_cells;
@@ -438,10 +423,7 @@ pl_status ga_upload(pl_ga_s *g, hipStream_t s) {
         return st;
     if (pl_status st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")) return st;
     g->lds = 4 * (size_t)T.n_cells;
-    for (const void *k : {(const void *)k_ga_integrate<float, kGaPer>,
-                          (const void *)k_ga_integrate<__half, kGaPer>,
-                          (const void *)k_ga_integrate<float, 1>,
-                          (const void *)k_ga_integrate<__half, 1>})
+    for (const void *k : {(const void *)k_ga_integrate<float>, (const void *)k_ga_integrate<__half>})
         if (pl_status st = allow_lds(k, g->lds)) return st;
     return PL_OK;
 }
@@ -490,28 +472,18 @@ pl_status ga_integrate(const pl_ga_s *g, const void *normals, pl_dtype ndt, cons
     const int *start = reinterpret_cast<const int *>(g->ws + T.off_start);
     const float4 *list = reinterpret_cast<const float4 *>(g->ws + T.off_list);
     uint32_t *reps = reinterpret_cast<uint32_t *>(g->ws + T.off_replicas);
-    // four rows per thread once that still gives every CU a workgroup
-    const bool wide = rows >= (long)kGaBlock * kGaPer * 256;
-    const long per_wg = (long)kGaBlock * (wide ? kGaPer : 1);
-    const int grid = (int)std::min<long>(kGaMaxGrid, (rows + per_wg - 1) / per_wg);
+    // one row per thread and pass, at most kGaMaxGrid workgroups (past that,
+    // threads loop: fewer histograms to clear and flush)
+    const int grid = (int)std::min<long>(kGaMaxGrid, (rows + kGaBlock - 1) / kGaBlock);
     const size_t lds = g->lds;
-    if (ndt == PL_F32) {
-        const float *nv = static_cast<const float *>(normals);
-        if (wide)
-            k_ga_integrate<float, kGaPer><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
-                                                                   T.n_cells, start, list, T.G, reps, cell_out);
-        else
-            k_ga_integrate<float, 1><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
-                                                              T.n_cells, start, list, T.G, reps, cell_out);
-    } else {
-        const __half *nv = static_cast<const __half *>(normals);
-        if (wide)
-            k_ga_integrate<__half, kGaPer><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
-                                                                    T.n_cells, start, list, T.G, reps, cell_out);
-        else
-            k_ga_integrate<__half, 1><<<grid, kGaBlock, lds, s>>>(nv, n_dev, cap, stride, cells,
-                                                               T.n_cells, start, list, T.G, reps, cell_out);
-    }
+    if (ndt == PL_F32)
+        k_ga_integrate<float><<<grid, kGaBlock, lds, s>>>(static_cast<const float *>(normals), n_dev,
+                                                          cap, stride, cells, T.n_cells, start, list,
+                                                          T.G, reps, cell_out);
+    else
+        k_ga_integrate<__half><<<grid, kGaBlock, lds, s>>>(static_cast<const __half *>(normals), n_dev,
+                                                           cap, stride, cells, T.n_cells, start, list,
+                                                           T.G, reps, cell_out);
     if (pl_status st = hip_check(hipGetLastError(), "k_ga_integrate")) return st;
     k_ga_fold<<<(T.n_cells + kGaBlock - 1) / kGaBlock, kGaBlock, 0, s>>>(reps, T.n_cells, counts);
     return hip_check(hipGetLastError(), "k_ga_fold");
