@@ -46,10 +46,10 @@ namespace pl {
 
 namespace {
 
-constexpr int kGaBlock = 256;
+constexpr int kGaBlock = 512;
 constexpr int kGaBatch = 6;                // candidate loads issued together
 #ifndef PL_GA_MAX_GRID
-#define PL_GA_MAX_GRID 1536
+#define PL_GA_MAX_GRID 768
 #endif
 constexpr int kGaMaxGrid = PL_GA_MAX_GRID;  // workgroups of one integration launch
 constexpr int kGaReplicas = 16;             // histogram copies the workgroups flush into
