@@ -776,7 +776,7 @@ __device__ __forceinline__ float bil_pair_e(const BilOwn &o, const float4 c, con
 
 // Sum of weighted neighbour normals.  Eq. 6 renormalises it, so the sum of
 // the weights is not needed; the underflow test uses the vector's norm,
-// which no total weight falls below the norm of (unit normals).
+// which never exceeds the total weight (unit normals).
 struct BilAcc {
     float x, y, z;
 };
