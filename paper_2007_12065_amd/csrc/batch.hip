@@ -184,10 +184,10 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_batch_bilatera
     const BFrame &f = fr[t.x];
     const PassFrame &p = pass[t.x];
     const int qy0 = (t.y / f.bil_tiles_x) * f.bil_th, qx0 = (t.y % f.bil_tiles_x) * f.bil_tw;
-    bil_tile<R, NT, FromPts>(FromPts ? nullptr : static_cast<const NT *>(p.src), f.centroids,
-                             static_cast<NT *>(p.dst), f.Mq, f.Nq, f.ka, f.kb, p.F, f.bil_th,
-                             f.bil_tw, qy0, qx0, p.gather ? f.tri_map : nullptr,
-                             static_cast<NT *>(f.normals_T), lds, f.pts_out, f.centroids);
+    bil_tile<R, NT, FromPts, false, bil_batch_lanes<R>()>(
+        FromPts ? nullptr : static_cast<const NT *>(p.src), f.centroids, static_cast<NT *>(p.dst),
+        f.Mq, f.Nq, f.ka, f.kb, p.F, f.bil_th, f.bil_tw, qy0, qx0, p.gather ? f.tri_map : nullptr,
+        static_cast<NT *>(f.normals_T), lds, f.pts_out, f.centroids);
 }
 
 static_assert(kGroupBlock == kTileBlock, "queue tiles are staged by kTileBlock threads");

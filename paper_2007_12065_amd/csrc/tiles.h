@@ -920,14 +920,18 @@ __device__ __forceinline__ void bil_push(const BilQueue &qu, int a, int k, int s
     qu.entry[i] = 2 * a + k;
 }
 
-// Lanes per quad: the displacements of D+ are dealt over P adjacent lanes
-// (lane part p takes i = p, p + P, ...), whose partial sums are then added
-// in a fixed tree -- (s_0 + s_1) for P = 2, ((s_0 + s_1) + (s_2 + s_3)) for
-// P = 4 -- identical on every lane of the quad (addition commutes exactly).
-// Larger windows take more lanes: a 5x5 window has 48 neighbours per
-// triangle, and a LiDAR frame of 64 x 1024 quads filled only one wave per
-// SIMD at one lane per quad.  Every kernel uses the same P for a given
-// window, so all paths keep giving the same bits.
+// Parts per quad: the displacements of D+ are dealt over P parts (part p
+// takes i = p, p + P, ...), whose partial sums are then added in a fixed
+// tree -- (s_0 + s_1) for P = 2, ((s_0 + s_1) + (s_2 + s_3)) for P = 4 --
+// identical on every lane of the quad (addition commutes exactly).  Larger
+// windows take more parts: a 5x5 window has 48 neighbours per triangle, and
+// a LiDAR frame of 64 x 1024 quads filled only one wave per SIMD at one lane
+// per quad.  A kernel runs the P parts on PP lanes (PP dividing P): a lane
+// keeps the partial sums of its P / PP parts apart and adds them in the same
+// tree, so every kernel gives the same bits whatever its PP.  One-round
+// launches (a single frame) take PP = P for more waves; the batch, many
+// rounds deep and bound by VALU issue, takes fewer lanes and so fewer
+// instructions per quad for the lane tree, the close and the stores.
 #ifndef PL_BIL_PARTS_K3
 #define PL_BIL_PARTS_K3 1
 #endif
@@ -935,77 +939,108 @@ __device__ __forceinline__ void bil_push(const BilQueue &qu, int a, int k, int s
 #define PL_BIL_PARTS_K5 4
 #endif
 template <int R> constexpr int bil_parts() { return R == 1 ? PL_BIL_PARTS_K3 : PL_BIL_PARTS_K5; }
+#ifndef PL_BIL_BATCH_LANES_K5
+#define PL_BIL_BATCH_LANES_K5 2
+#endif
+// lanes per quad of the batched kernels
+template <int R> constexpr int bil_batch_lanes() {
+    return R == 1 ? bil_parts<1>() : PL_BIL_BATCH_LANES_K5;
+}
 static_assert(bil_ndplus<1>() % PL_BIL_PARTS_K3 == 0 && bil_ndplus<2>() % PL_BIL_PARTS_K5 == 0 &&
                   bil_ndplus<3>() % PL_BIL_PARTS_K5 == 0 && bil_ndplus<4>() % PL_BIL_PARTS_K5 == 0,
               "the lanes of a quad share |D+| evenly");
 
-template <int P>
-__device__ __forceinline__ BilAcc bil_reduce(BilAcc s) {
+// The tree over the P parts of a quad held as P / PP sets on PP lanes (part
+// p = lane + k PP is set k): its steps with m < PP add across lanes, the
+// rest across sets, each term its own value plus its partner's.
+template <int P, int PP>
+__device__ __forceinline__ BilAcc bil_reduce(BilAcc (&s)[P / PP]) {
+    constexpr int NS = P / PP;
 #pragma unroll
-    for (int m = 1; m < P; m <<= 1) {
-        s.x += __shfl_xor(s.x, m, kWave);
-        s.y += __shfl_xor(s.y, m, kWave);
-        s.z += __shfl_xor(s.z, m, kWave);
+    for (int m = 1; m < PP; m <<= 1) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            s[k].x += __shfl_xor(s[k].x, m, kWave);
+            s[k].y += __shfl_xor(s[k].y, m, kWave);
+            s[k].z += __shfl_xor(s[k].z, m, kWave);
+        }
     }
-    return s;
+#pragma unroll
+    for (int m = 1; m < NS; m <<= 1) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (k & m) continue;
+            const int o = k ^ m;
+            const BilAcc u{s[k].x + s[o].x, s[k].y + s[o].y, s[k].z + s[o].z};
+            s[k] = u;
+            s[o] = u;
+        }
+    }
+    return s[0];
 }
 
 // Both triangles of the quad at LDS index a, in the fixed summation order:
-// for each d of D+ (this lane's share `part` of them), the two triangles of
-// quad a + d, then the two of quad a - d; the lanes' partial sums are added
-// in a fixed tree.  A pair weight takes its lower quad's triangle first
+// for each d of D+ (part p's share of them), the two triangles of quad
+// a + d, then the two of quad a - d; the parts' partial sums are added in a
+// fixed tree.  This lane (`lane` of PP) runs parts lane, lane + PP, ...: the
+// i-th displacement belongs to part i mod P, whose set here is
+// (i mod P) / PP.  A pair weight takes its lower quad's triangle first
 // (bil_w is symmetric anyway).  Every lane of the quad returns the same r0,
 // r1 and pending flags.
-template <int R, typename NT>
+template <int R, typename NT, int PP>
 __device__ __forceinline__ void bil_sum_quad(const float4 *sc, const float4 *sn, int a,
                                                 int pitch, int plane, float ka, float kb,
-                                                int part, float4 &r0, float4 &r1, bool &pend0,
+                                                int lane, float4 &r0, float4 &r1, bool &pend0,
                                                 bool &pend1) {
-    constexpr int ND = bil_ndplus<R>(), P = bil_parts<R>();
+    constexpr int ND = bil_ndplus<R>(), P = bil_parts<R>(), NS = P / PP;
+    static_assert(P % PP == 0, "the lanes of a quad share its parts evenly");
     const float4 c0 = sc[a], c1 = sc[plane + a], n0 = sn[a], n1 = sn[plane + a];
-    BilAcc s0{0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f};
+    BilAcc s0[NS], s1[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        s0[k] = BilAcc{0.f, 0.f, 0.f};
+        s1[k] = BilAcc{0.f, 0.f, 0.f};
+    }
 #pragma unroll 1
-    for (int j = 0; j < ND / P; ++j) {
-        const int i = j * P + part;
-        int dy, dx;
-        bil_dplus<R>(i, dy, dx);
-        const int off = dy * pitch + dx;
-        const int bp = a + off, bm = a - off;
-        const float4 pc0 = sc[bp], pc1 = sc[plane + bp], p0 = sn[bp], p1 = sn[plane + bp];
-        const float4 mc0 = sc[bm], mc1 = sc[plane + bm], m0 = sn[bm], m1 = sn[plane + bm];
-        bil_acc(s0, bil_w(c0, n0, pc0, p0, ka, kb), p0);
-        bil_acc(s0, bil_w(c0, n0, pc1, p1, ka, kb), p1);
-        bil_acc(s0, bil_w(mc0, m0, c0, n0, ka, kb), m0);
-        bil_acc(s0, bil_w(mc1, m1, c0, n0, ka, kb), m1);
-        bil_acc(s1, bil_w(c1, n1, pc0, p0, ka, kb), p0);
-        bil_acc(s1, bil_w(c1, n1, pc1, p1, ka, kb), p1);
-        bil_acc(s1, bil_w(mc0, m0, c1, n1, ka, kb), m0);
-        bil_acc(s1, bil_w(mc1, m1, c1, n1, ka, kb), m1);
+    for (int j0 = 0; j0 < ND / PP; j0 += NS) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {          // displacement j0 + k: set k
+            const int i = (j0 + k) * PP + lane;
+            int dy, dx;
+            bil_dplus<R>(i, dy, dx);
+            const int off = dy * pitch + dx;
+            const int bp = a + off, bm = a - off;
+            const float4 pc0 = sc[bp], pc1 = sc[plane + bp], p0 = sn[bp], p1 = sn[plane + bp];
+            const float4 mc0 = sc[bm], mc1 = sc[plane + bm], m0 = sn[bm], m1 = sn[plane + bm];
+            bil_acc(s0[k], bil_w(c0, n0, pc0, p0, ka, kb), p0);
+            bil_acc(s0[k], bil_w(c0, n0, pc1, p1, ka, kb), p1);
+            bil_acc(s0[k], bil_w(mc0, m0, c0, n0, ka, kb), m0);
+            bil_acc(s0[k], bil_w(mc1, m1, c0, n0, ka, kb), m1);
+            bil_acc(s1[k], bil_w(c1, n1, pc0, p0, ka, kb), p0);
+            bil_acc(s1[k], bil_w(c1, n1, pc1, p1, ka, kb), p1);
+            bil_acc(s1[k], bil_w(mc0, m0, c1, n1, ka, kb), m0);
+            bil_acc(s1[k], bil_w(mc1, m1, c1, n1, ka, kb), m1);
+        }
     }
-    if constexpr (P > 1) {
-        s0 = bil_reduce<P>(s0);
-        s1 = bil_reduce<P>(s1);
-    }
-    r0 = bil_close<NT>(c0, n0, s0, pend0);
-    r1 = bil_close<NT>(c1, n1, s1, pend1);
+    r0 = bil_close<NT>(c0, n0, bil_reduce<P, PP>(s0), pend0);
+    r1 = bil_close<NT>(c1, n1, bil_reduce<P, PP>(s1), pend1);
 }
 
 // One sweep over the OH x OW region at (oy0, ox0) of the staged tile;
 // out(ry, rx, a, r0, r1, pend0, pend1) takes each quad's results (ry, rx
 // within the region).  Ends with a barrier.
-template <int R, typename NT, typename Out>
+template <int R, typename NT, int PP, typename Out>
 __device__ __forceinline__ void bil_sweep(const float4 *sc, const float4 *sn, int pitch, int plane,
                                           int oy0, int ox0, int OH, int OW, float ka, float kb,
                                           Out &&out) {
-    constexpr int P = bil_parts<R>();
-    const int slot = (int)threadIdx.x / P, part = (int)threadIdx.x % P;
+    const int slot = (int)threadIdx.x / PP, lane = (int)threadIdx.x % PP;
     const DivBy byOW(OW);
-    for (int idx = slot; idx < OH * OW; idx += kTileBlock / P) {
+    for (int idx = slot; idx < OH * OW; idx += kTileBlock / PP) {
         const int ry = byOW.div(idx), rx = idx - ry * OW;
         const int a = (oy0 + ry) * pitch + ox0 + rx;
         float4 r0, r1;
         bool p0, p1;
-        bil_sum_quad<R, NT>(sc, sn, a, pitch, plane, ka, kb, part, r0, r1, p0, p1);
+        bil_sum_quad<R, NT, PP>(sc, sn, a, pitch, plane, ka, kb, lane, r0, r1, p0, p1);
         out(ry, rx, a, r0, r1, p0, p1);
     }
     __syncthreads();
@@ -1058,7 +1093,7 @@ __device__ __forceinline__ void bil_gather_ranks(const GatherCodes &gc, int Mq, 
 // them (normals rounded to NT), and the tile's centroids are written to
 // `cen` -- the batched path's first pass, which then needs no normals
 // stage.  Otherwise nin / cen are the stored raw normals and centroids.
-template <int R, typename NT, bool FromPts = false, bool ByCodes = false>
+template <int R, typename NT, bool FromPts = false, bool ByCodes = false, int PP = bil_parts<R>()>
 __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float *__restrict__ cen,
                                          NT *__restrict__ nout, int Mq, int Nq, float ka, float kb,
                                          int F, int TQH, int TQW, int qy0, int qx0,
@@ -1134,14 +1169,13 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
 
     const float4 *cur = s_n;
     float4 *nxt = s_m;
-    // lanes per quad (bil_parts): quad slot and share of this lane
-    constexpr int P = bil_parts<R>();
-    const int slot = (int)threadIdx.x / P, part = (int)threadIdx.x % P;
+    // PP lanes per quad: quad slot and lane within the quad
+    const int slot = (int)threadIdx.x / PP, part = (int)threadIdx.x % PP;
     const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
     // intermediate sweeps: LDS to LDS over the shrinking exact region
     for (int f = 1; f < F; ++f) {
         const int lo = R * f;
-        bil_sweep<R, NT>(s_c, cur, W, S, lo, lo, H - 2 * lo, W - 2 * lo, ka, kb,
+        bil_sweep<R, NT, PP>(s_c, cur, W, S, lo, lo, H - 2 * lo, W - 2 * lo, ka, kb,
                          [&](int, int, int a, float4 r0, float4 r1, bool p0, bool p1) {
                              if (part != 0) return;
                              if (p0) bil_push(qu, a, 0, f); else nxt[a] = r0;
@@ -1222,11 +1256,11 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
         }
     };
     if (F > 0) {
-        bil_sweep<R, NT>(s_c, cur, W, S, halo, halo, TQH, TQW, ka, kb, emit);
+        bil_sweep<R, NT, PP>(s_c, cur, W, S, halo, halo, TQH, TQW, ka, kb, emit);
     } else {
         const DivBy byTQW(TQW);
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int idx = slot; idx < TQH * TQW; idx += kTileBlock / P) {
+        for (int idx = slot; idx < TQH * TQW; idx += kTileBlock / PP) {
             const int ty = byTQW.div(idx);
             emit(ty, idx - ty * TQW, 0, z, z, false, false);
         }
