@@ -14,13 +14,13 @@ std::mutex g_mu;
 TileCfg g_cfg[kNumStages][kMaxRadius + 1] = {
     // Laplacian: {th, tw, fuse} per radius (3x3, 5x5: the fused path's
     // measured best on a 480x640 and a 128x2048 frame)
-    {{0, 0, 0}, {8, 32, 4}, {16, 16, 2}, {8, 32, 1}, {8, 32, 1}},
+    {{0, 0, 0}, {16, 16, 4}, {16, 16, 2}, {8, 32, 1}, {8, 32, 1}},
     // bilateral
     {{0, 0, 0}, {8, 32, 1}, {2, 32, 1}, {8, 32, 1}, {8, 32, 1}},
     // batched Laplacian (a 64-frame mix)
-    {{0, 0, 0}, {16, 16, 4}, {16, 32, 2}, {8, 32, 1}, {8, 32, 1}},
+    {{0, 0, 0}, {16, 16, 4}, {16, 16, 2}, {8, 32, 1}, {8, 32, 1}},
     // batched bilateral
-    {{0, 0, 0}, {8, 32, 1}, {4, 32, 1}, {8, 32, 1}, {8, 32, 1}},
+    {{0, 0, 0}, {8, 32, 1}, {16, 16, 1}, {8, 32, 1}, {8, 32, 1}},
     // Laplacian, small frames (120x160, 64x1024)
     {{0, 0, 0}, {8, 16, 4}, {8, 16, 2}, {8, 32, 1}, {8, 32, 1}},
     // bilateral, small frames
