@@ -465,7 +465,7 @@ pl_status plan_grids(pl_batch_s &b, const pl_frame *frames) {
             for (int i = 0; i < b.n; ++i) {
                 if (!p.q[r].count[i]) continue;
                 const TileCfg c = tile_cfg(kStageBatchBilateral, r + 1);
-                lds = std::max(lds, bil_lds_bytes(r + 1, p.tab[i].F, c.th, c.tw));
+                lds = std::max(lds, bil_lds_bytes(r + 1, p.tab[i].F, c.th, c.tw, bil_waves(r + 1, true)));
             }
             if (pl_status st = size_grid(p.q[r], bil_k[pi == 0][r], lds)) return st;
         }

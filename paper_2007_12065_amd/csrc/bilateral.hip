@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_bilateral(
     const int32_t *__restrict__ tri_map, NT *__restrict__ nT) {
     extern __shared__ float4 lds[];
     const int tile = xcd_remap(blockIdx.x, ntiles);
-    bil_tile<R, NT>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW, (tile / tiles_x) * TQH,
+    bil_tile<R, NT, false, false, bil_frame_lanes<R>()>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW, (tile / tiles_x) * TQH,
                     (tile % tiles_x) * TQW, tri_map, nT, lds);
 }
 
@@ -41,7 +41,7 @@ pl_status run(const NT *nin, const float *cen, int M, int N, float sl, float sa,
         left -= F;
         const bool last = l == launches - 1;
         NT *dst = ((launches - 1 - l) % 2 == 0) ? nout : tmp;    // last launch lands in nout
-        const size_t lds = bil_lds_bytes(R, F, c.th, c.tw);
+        const size_t lds = bil_lds_bytes(R, F, c.th, c.tw, bil_waves(R, false));
         if (pl_status st = allow_lds((const void *)k_bilateral<R, NT>, lds)) return st;
         k_bilateral<R, NT><<<ntiles, kTileBlock, lds, s>>>(cur, cen, dst, Mq, Nq, ka, kb, F,
                                                             c.th, c.tw, tiles_x, ntiles,

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_frame_bilatera
     }
     const int tile = xcd_remap_active(b, ntiles);
     if (tile < 0) return;
-    bil_tile<R, NT, FromPts, ByCodes>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW,
+    bil_tile<R, NT, FromPts, ByCodes, bil_frame_lanes<R>()>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW,
                                       (tile / tiles_x) * TQH, (tile % tiles_x) * TQW, tri_map, nT,
                                       lds, pts, cen_out, GatherCodes{mj.codes, mj.counts, mj.S});
 }
@@ -178,7 +178,7 @@ pl_status bil_launch(const NT *nin, const float *cen, NT *nout, int Mq, int Nq, 
     const int ntiles = tiles_x * ((Mq + c.th - 1) / c.th);
     const int fb = Kind == kMeshNone ? ntiles : round8(ntiles);
     const int grid = fb + (Kind == kMeshNone ? 0 : mesh_blocks(mj));
-    size_t lds = bil_lds_bytes(R, F, c.th, c.tw);
+    size_t lds = bil_lds_bytes(R, F, c.th, c.tw, bil_waves(R, false));
     lds = lds > mesh_lds(Kind) ? lds : mesh_lds(Kind);
     if (pl_status st = allow_lds((const void *)k_frame_bilateral<R, NT, FromPts, Kind, ByCodes>, lds))
         return st;

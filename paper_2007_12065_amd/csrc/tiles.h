@@ -734,10 +734,35 @@ constexpr float kBilUnderflow2 = 0x1p-120f;       // (2^-60)^2
 constexpr int kBilWavesPerSimd = 6;
 constexpr float kBilShift = 48.f;                 // every weight is 2^(48 - e)
 constexpr int kBilMaxSweeps = 8;                  // fused sweeps per launch at most
-__host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW) {
+#ifndef PL_BIL_PARTS_K3
+#define PL_BIL_PARTS_K3 1
+#endif
+#ifndef PL_BIL_PARTS_K5
+#define PL_BIL_PARTS_K5 4
+#endif
+#ifndef PL_BIL_FRAME_WAVES
+#define PL_BIL_FRAME_WAVES 1
+#endif
+#ifndef PL_BIL_BATCH_WAVES
+#define PL_BIL_BATCH_WAVES 0
+#endif
+// Whether a kernel runs the parts of a quad's sum on its waves (windows of
+// 5x5 and up): the single-frame kernels do, the batched ones (many rounds
+// of workgroups deep, where wave 0 closing the quads alone idles the others)
+// keep them on lanes.
+__host__ __device__ constexpr bool bil_waves(int R, bool batch) {
+    return R >= 2 && (batch ? PL_BIL_BATCH_WAVES : PL_BIL_FRAME_WAVES) != 0;
+}
+// floats of the parts' exchange when the parts run on waves: the partial
+// sums of parts 1.. of 64 quads
+__host__ __device__ constexpr int bil_xch_floats(int R) {
+    return R >= 2 ? (PL_BIL_PARTS_K5 - 1) * 6 * 64 : 0;
+}
+__host__ __device__ constexpr size_t bil_lds_bytes(int R, int F, int TQH, int TQW, bool waves) {
     return (F > 1 ? 6 : 4) * sizeof(float4) * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) +
            sizeof(int) * (2 * (size_t)(TQH + 2 * R * F) * (size_t)(TQW + 2 * R * F) + kBilMaxSweeps + 1) +
-           sizeof(int) * (size_t)TQH * TQW;     // T ranks of the tile (gather from the mesh codes)
+           sizeof(int) * (size_t)TQH * TQW +    // T ranks of the tile (gather from the mesh codes)
+           (waves ? sizeof(float) * (size_t)bil_xch_floats(R) : 0);
 }
 
 // The mesh's codes and per-segment counts (pl_mesh_opc's first pass): with
@@ -932,19 +957,17 @@ __device__ __forceinline__ void bil_push(const BilQueue &qu, int a, int k, int s
 // launches (a single frame) take PP = P for more waves; the batch, many
 // rounds deep and bound by VALU issue, takes fewer lanes and so fewer
 // instructions per quad for the lane tree, the close and the stores.
-#ifndef PL_BIL_PARTS_K3
-#define PL_BIL_PARTS_K3 1
-#endif
-#ifndef PL_BIL_PARTS_K5
-#define PL_BIL_PARTS_K5 4
-#endif
 template <int R> constexpr int bil_parts() { return R == 1 ? PL_BIL_PARTS_K3 : PL_BIL_PARTS_K5; }
 #ifndef PL_BIL_BATCH_LANES_K5
 #define PL_BIL_BATCH_LANES_K5 2
 #endif
-// lanes per quad of the batched kernels
+// lanes per quad (0: parts on waves) of the single-frame kernels
+template <int R> constexpr int bil_frame_lanes() {
+    return bil_waves(R, false) ? 0 : bil_parts<R>();
+}
+// lanes per quad (0: parts on waves) of the batched kernels
 template <int R> constexpr int bil_batch_lanes() {
-    return R == 1 ? bil_parts<1>() : PL_BIL_BATCH_LANES_K5;
+    return bil_waves(R, true) ? 0 : (R == 1 ? bil_parts<1>() : PL_BIL_BATCH_LANES_K5);
 }
 static_assert(bil_ndplus<1>() % PL_BIL_PARTS_K3 == 0 && bil_ndplus<2>() % PL_BIL_PARTS_K5 == 0 &&
                   bil_ndplus<3>() % PL_BIL_PARTS_K5 == 0 && bil_ndplus<4>() % PL_BIL_PARTS_K5 == 0,
@@ -979,6 +1002,30 @@ __device__ __forceinline__ BilAcc bil_reduce(BilAcc (&s)[P / PP]) {
     return s[0];
 }
 
+// The terms of the i-th displacement d of D+ for both triangles of the quad
+// at LDS index a (own centroids c, normals n): the two triangles of quad
+// a + d, then the two of quad a - d.
+template <int R>
+__device__ __forceinline__ void bil_disp(const float4 *sc, const float4 *sn, int a, int pitch,
+                                         int plane, float ka, float kb, int i, const float4 c0,
+                                         const float4 c1, const float4 n0, const float4 n1,
+                                         BilAcc &s0, BilAcc &s1) {
+    int dy, dx;
+    bil_dplus<R>(i, dy, dx);
+    const int off = dy * pitch + dx;
+    const int bp = a + off, bm = a - off;
+    const float4 pc0 = sc[bp], pc1 = sc[plane + bp], p0 = sn[bp], p1 = sn[plane + bp];
+    const float4 mc0 = sc[bm], mc1 = sc[plane + bm], m0 = sn[bm], m1 = sn[plane + bm];
+    bil_acc(s0, bil_w(c0, n0, pc0, p0, ka, kb), p0);
+    bil_acc(s0, bil_w(c0, n0, pc1, p1, ka, kb), p1);
+    bil_acc(s0, bil_w(mc0, m0, c0, n0, ka, kb), m0);
+    bil_acc(s0, bil_w(mc1, m1, c0, n0, ka, kb), m1);
+    bil_acc(s1, bil_w(c1, n1, pc0, p0, ka, kb), p0);
+    bil_acc(s1, bil_w(c1, n1, pc1, p1, ka, kb), p1);
+    bil_acc(s1, bil_w(mc0, m0, c1, n1, ka, kb), m0);
+    bil_acc(s1, bil_w(mc1, m1, c1, n1, ka, kb), m1);
+}
+
 // Both triangles of the quad at LDS index a, in the fixed summation order:
 // for each d of D+ (part p's share of them), the two triangles of quad
 // a + d, then the two of quad a - d; the parts' partial sums are added in a
@@ -1004,23 +1051,9 @@ __device__ __forceinline__ void bil_sum_quad(const float4 *sc, const float4 *sn,
 #pragma unroll 1
     for (int j0 = 0; j0 < ND / PP; j0 += NS) {
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {          // displacement j0 + k: set k
-            const int i = (j0 + k) * PP + lane;
-            int dy, dx;
-            bil_dplus<R>(i, dy, dx);
-            const int off = dy * pitch + dx;
-            const int bp = a + off, bm = a - off;
-            const float4 pc0 = sc[bp], pc1 = sc[plane + bp], p0 = sn[bp], p1 = sn[plane + bp];
-            const float4 mc0 = sc[bm], mc1 = sc[plane + bm], m0 = sn[bm], m1 = sn[plane + bm];
-            bil_acc(s0[k], bil_w(c0, n0, pc0, p0, ka, kb), p0);
-            bil_acc(s0[k], bil_w(c0, n0, pc1, p1, ka, kb), p1);
-            bil_acc(s0[k], bil_w(mc0, m0, c0, n0, ka, kb), m0);
-            bil_acc(s0[k], bil_w(mc1, m1, c0, n0, ka, kb), m1);
-            bil_acc(s1[k], bil_w(c1, n1, pc0, p0, ka, kb), p0);
-            bil_acc(s1[k], bil_w(c1, n1, pc1, p1, ka, kb), p1);
-            bil_acc(s1[k], bil_w(mc0, m0, c1, n1, ka, kb), m0);
-            bil_acc(s1[k], bil_w(mc1, m1, c1, n1, ka, kb), m1);
-        }
+        for (int k = 0; k < NS; ++k)            // displacement j0 + k: set k
+            bil_disp<R>(sc, sn, a, pitch, plane, ka, kb, (j0 + k) * PP + lane, c0, c1, n0, n1,
+                        s0[k], s1[k]);
     }
     r0 = bil_close<NT>(c0, n0, bil_reduce<P, PP>(s0), pend0);
     r1 = bil_close<NT>(c1, n1, bil_reduce<P, PP>(s1), pend1);
@@ -1042,6 +1075,60 @@ __device__ __forceinline__ void bil_sweep(const float4 *sc, const float4 *sn, in
         bool p0, p1;
         bil_sum_quad<R, NT, PP>(sc, sn, a, pitch, plane, ka, kb, lane, r0, r1, p0, p1);
         out(ry, rx, a, r0, r1, p0, p1);
+    }
+    __syncthreads();
+}
+
+// The same sweep with the P parts of a quad on the workgroup's P waves
+// (wave w runs part w of 64 quads at a time): the displacement index is the
+// same on every lane of a wave, so its decoding and the neighbour offsets
+// are scalar work; waves 1.. leave their partial sums in `xch`, and wave 0
+// adds them in the tree of bil_reduce -- ((s_0 + s_1) + (s_2 + s_3)) --
+// closes the quad and calls out, alone.  Same bits as the lane form.
+template <int R, typename NT, typename Out>
+__device__ __forceinline__ void bil_sweep_waves(const float4 *sc, const float4 *sn, int pitch,
+                                                int plane, int oy0, int ox0, int OH, int OW,
+                                                float ka, float kb, float *xch, Out &&out) {
+    constexpr int ND = bil_ndplus<R>(), P = bil_parts<R>();
+    static_assert(P == 4 && P == kTileBlock / kWave, "one wave per part, tree of four");
+    static_assert(bil_xch_floats(R) == (P - 1) * 6 * kWave, "exchange size");
+    const int part = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+    const int lane = (int)threadIdx.x & (kWave - 1);
+    const DivBy byOW(OW);
+    const int n = OH * OW;
+    for (int base = 0; base < n; base += kWave) {
+        const int idx = base + lane;
+        const bool have = idx < n;
+        const int ry = have ? byOW.div(idx) : 0, rx = have ? idx - ry * OW : 0;
+        const int a = (oy0 + ry) * pitch + ox0 + rx;
+        BilAcc s0{0.f, 0.f, 0.f}, s1{0.f, 0.f, 0.f};
+        float4 c0, c1, n0, n1;
+        if (have) {
+            c0 = sc[a]; c1 = sc[plane + a]; n0 = sn[a]; n1 = sn[plane + a];
+#pragma unroll 1
+            for (int j = 0; j < ND / P; ++j)
+                bil_disp<R>(sc, sn, a, pitch, plane, ka, kb, j * P + part, c0, c1, n0, n1, s0, s1);
+        }
+        if (part != 0) {
+            float *x = xch + (part - 1) * 6 * kWave + lane;
+            x[0] = s0.x; x[kWave] = s0.y; x[2 * kWave] = s0.z;
+            x[3 * kWave] = s1.x; x[4 * kWave] = s1.y; x[5 * kWave] = s1.z;
+        }
+        __syncthreads();
+        if (part == 0 && have) {
+            const float *x1 = xch + lane, *x2 = x1 + 6 * kWave, *x3 = x2 + 6 * kWave;
+            const BilAcc t0{(s0.x + x1[0]) + (x2[0] + x3[0]),
+                            (s0.y + x1[kWave]) + (x2[kWave] + x3[kWave]),
+                            (s0.z + x1[2 * kWave]) + (x2[2 * kWave] + x3[2 * kWave])};
+            const BilAcc t1{(s1.x + x1[3 * kWave]) + (x2[3 * kWave] + x3[3 * kWave]),
+                            (s1.y + x1[4 * kWave]) + (x2[4 * kWave] + x3[4 * kWave]),
+                            (s1.z + x1[5 * kWave]) + (x2[5 * kWave] + x3[5 * kWave])};
+            bool p0, p1;
+            const float4 r0 = bil_close<NT>(c0, n0, t0, p0);
+            const float4 r1 = bil_close<NT>(c1, n1, t1, p1);
+            out(ry, rx, a, r0, r1, p0, p1);
+        }
+        if (base + kWave < n) __syncthreads();   // xch is reused by the next 64 quads
     }
     __syncthreads();
 }
@@ -1093,6 +1180,8 @@ __device__ __forceinline__ void bil_gather_ranks(const GatherCodes &gc, int Mq, 
 // them (normals rounded to NT), and the tile's centroids are written to
 // `cen` -- the batched path's first pass, which then needs no normals
 // stage.  Otherwise nin / cen are the stored raw normals and centroids.
+// PP: lanes per quad for the parts of its sum (bil_parts); 0 puts the parts
+// on the workgroup's waves instead (bil_sweep_waves; windows of 5x5 and up).
 template <int R, typename NT, bool FromPts = false, bool ByCodes = false, int PP = bil_parts<R>()>
 __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float *__restrict__ cen,
                                          NT *__restrict__ nout, int Mq, int Nq, float ka, float kb,
@@ -1112,6 +1201,10 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
     if (threadIdx.x < kBilMaxSweeps + 1) qu.count[threadIdx.x] = 0;
     // T ranks of the tile when the gather takes them from the mesh codes
     int *rank = qbase + 2 * S + kBilMaxSweeps + 1;
+    // the parts' exchange (parts on waves)
+    float *xch = reinterpret_cast<float *>(rank + TQH * TQW);
+    constexpr bool waves = PP == 0;
+    static_assert(!waves || R >= 2, "parts on waves for windows of 5x5 and up");
     constexpr bool by_codes = ByCodes;
     if constexpr (by_codes) {
         bil_gather_ranks(gc, Mq, Nq, qy0, qx0, TQH, TQW, rank);
@@ -1169,18 +1262,28 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
 
     const float4 *cur = s_n;
     float4 *nxt = s_m;
-    // PP lanes per quad: quad slot and lane within the quad
-    const int slot = (int)threadIdx.x / PP, part = (int)threadIdx.x % PP;
+    // PP lanes per quad: quad slot and lane within the quad; parts on
+    // waves: the lane is the slot, the wave the part (only part 0 stores)
+    constexpr int QL = waves ? 1 : PP;                       // lanes per quad
+    const int slot = waves ? (int)threadIdx.x % kWave : (int)threadIdx.x / QL;
+    const int part = waves ? (int)threadIdx.x / kWave : (int)threadIdx.x % QL;
     const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
+    // one sweep over the OH x OW region at (o0, o0) of the staged tile
+    auto sweep = [&](int o0, int OH, int OW, auto &&out) {
+        if constexpr (waves)
+            bil_sweep_waves<R, NT>(s_c, cur, W, S, o0, o0, OH, OW, ka, kb, xch, out);
+        else
+            bil_sweep<R, NT, PP>(s_c, cur, W, S, o0, o0, OH, OW, ka, kb, out);
+    };
     // intermediate sweeps: LDS to LDS over the shrinking exact region
     for (int f = 1; f < F; ++f) {
         const int lo = R * f;
-        bil_sweep<R, NT, PP>(s_c, cur, W, S, lo, lo, H - 2 * lo, W - 2 * lo, ka, kb,
-                         [&](int, int, int a, float4 r0, float4 r1, bool p0, bool p1) {
-                             if (part != 0) return;
-                             if (p0) bil_push(qu, a, 0, f); else nxt[a] = r0;
-                             if (p1) bil_push(qu, a, 1, f); else nxt[S + a] = r1;
-                         });
+        sweep(lo, H - 2 * lo, W - 2 * lo,
+              [&](int, int, int a, float4 r0, float4 r1, bool p0, bool p1) {
+                  if (part != 0) return;
+                  if (p0) bil_push(qu, a, 0, f); else nxt[a] = r0;
+                  if (p1) bil_push(qu, a, 1, f); else nxt[S + a] = r1;
+              });
         const int nq = qu.count[f];
         for (int e = wave; e < nq; e += kTileBlock / kWave) {
             const int a = qu.entry[e] >> 1, k = qu.entry[e] & 1;
@@ -1256,11 +1359,11 @@ __device__ __forceinline__ void bil_tile(const NT *__restrict__ nin, const float
         }
     };
     if (F > 0) {
-        bil_sweep<R, NT, PP>(s_c, cur, W, S, halo, halo, TQH, TQW, ka, kb, emit);
+        sweep(halo, TQH, TQW, emit);
     } else {
         const DivBy byTQW(TQW);
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int idx = slot; idx < TQH * TQW; idx += kTileBlock / PP) {
+        for (int idx = slot; idx < TQH * TQW; idx += waves ? kWave : kTileBlock / QL) {
             const int ty = byTQW.div(idx);
             emit(ty, idx - ty * TQW, 0, z, z, false, false);
         }

@@ -34,7 +34,7 @@ constexpr size_t kLdsMax = 156 * 1024;
 
 size_t cfg_lds_bytes(Stage s, int R, TileCfg c) {
     return is_laplacian(s) ? lap_lds_bytes(R, c.fuse, c.th, c.tw)
-                           : bil_lds_bytes(R, c.fuse, c.th, c.tw);
+                           : bil_lds_bytes(R, c.fuse, c.th, c.tw, bil_waves(R, s == kStageBatchBilateral));
 }
 
 TileCfg tile_cfg(Stage s, int R) {
