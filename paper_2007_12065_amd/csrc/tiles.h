@@ -959,7 +959,7 @@ __device__ __forceinline__ void bil_push(const BilQueue &qu, int a, int k, int s
 // instructions per quad for the lane tree, the close and the stores.
 template <int R> constexpr int bil_parts() { return R == 1 ? PL_BIL_PARTS_K3 : PL_BIL_PARTS_K5; }
 #ifndef PL_BIL_BATCH_LANES_K5
-#define PL_BIL_BATCH_LANES_K5 2
+#define PL_BIL_BATCH_LANES_K5 1
 #endif
 // lanes per quad (0: parts on waves) of the single-frame kernels
 template <int R> constexpr int bil_frame_lanes() {
