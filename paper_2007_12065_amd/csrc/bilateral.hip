@@ -18,8 +18,9 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_bilateral(
     const int32_t *__restrict__ tri_map, NT *__restrict__ nT) {
     extern __shared__ float4 lds[];
     const int tile = xcd_remap(blockIdx.x, ntiles);
-    bil_tile<R, NT, false, false, bil_frame_lanes<R>()>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW, (tile / tiles_x) * TQH,
-                    (tile % tiles_x) * TQW, tri_map, nT, lds);
+    bil_tile<R, NT, false, false, bil_frame_lanes<R>()>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW,
+                                                        (tile / tiles_x) * TQH,
+                                                        (tile % tiles_x) * TQW, tri_map, nT, lds);
 }
 
 template <int R, typename NT>

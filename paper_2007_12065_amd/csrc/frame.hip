@@ -105,9 +105,9 @@ __global__ __launch_bounds__(kTileBlock, kBilWavesPerSimd) void k_frame_bilatera
     }
     const int tile = xcd_remap_active(b, ntiles);
     if (tile < 0) return;
-    bil_tile<R, NT, FromPts, ByCodes, bil_frame_lanes<R>()>(nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW,
-                                      (tile / tiles_x) * TQH, (tile % tiles_x) * TQW, tri_map, nT,
-                                      lds, pts, cen_out, GatherCodes{mj.codes, mj.counts, mj.S});
+    bil_tile<R, NT, FromPts, ByCodes, bil_frame_lanes<R>()>(
+        nin, cen, nout, Mq, Nq, ka, kb, F, TQH, TQW, (tile / tiles_x) * TQH, (tile % tiles_x) * TQW,
+        tri_map, nT, lds, pts, cen_out, GatherCodes{mj.codes, mj.counts, mj.S});
 }
 
 // Optional record of the launches (pl_smooth_frame_events): an event before

@@ -953,10 +953,11 @@ __device__ __forceinline__ void bil_push(const BilQueue &qu, int a, int k, int s
 // a LiDAR frame of 64 x 1024 quads filled only one wave per SIMD at one lane
 // per quad.  A kernel runs the P parts on PP lanes (PP dividing P): a lane
 // keeps the partial sums of its P / PP parts apart and adds them in the same
-// tree, so every kernel gives the same bits whatever its PP.  One-round
-// launches (a single frame) take PP = P for more waves; the batch, many
-// rounds deep and bound by VALU issue, takes fewer lanes and so fewer
-// instructions per quad for the lane tree, the close and the stores.
+// tree, so every kernel gives the same bits whatever its PP.  The single-
+// frame kernels put the four parts of a 5x5-and-up quad on the workgroup's
+// four waves instead (bil_sweep_waves, same tree again); the batch, many
+// rounds deep and bound by VALU issue, runs them on one lane, which needs no
+// lane tree and closes and stores each quad once.
 template <int R> constexpr int bil_parts() { return R == 1 ? PL_BIL_PARTS_K3 : PL_BIL_PARTS_K5; }
 #ifndef PL_BIL_BATCH_LANES_K5
 #define PL_BIL_BATCH_LANES_K5 1
@@ -971,7 +972,7 @@ template <int R> constexpr int bil_batch_lanes() {
 }
 static_assert(bil_ndplus<1>() % PL_BIL_PARTS_K3 == 0 && bil_ndplus<2>() % PL_BIL_PARTS_K5 == 0 &&
                   bil_ndplus<3>() % PL_BIL_PARTS_K5 == 0 && bil_ndplus<4>() % PL_BIL_PARTS_K5 == 0,
-              "the lanes of a quad share |D+| evenly");
+              "the parts of a quad share |D+| evenly");
 
 // The tree over the P parts of a quad held as P / PP sets on PP lanes (part
 // p = lane + k PP is set k): its steps with m < PP add across lanes, the
